@@ -1,0 +1,228 @@
+/*
+ * tl.h - C ABI of the MI355X (gfx950) lattice core-Hamiltonian library.
+ *
+ * Method: Khoromskaia & Khoromskij, "Tensor numerical approach to linearized
+ * Hartree-Fock equation for lattice-type and periodic systems"
+ * (arXiv:1408.3839).  The library assembles the Galerkin core Hamiltonian
+ * H = T - V_c and the mass matrix S of a Gaussian basis replicated over an
+ * (L1,L2,L3) lattice, with every basis function and the Newton potential held
+ * as separable 1D vectors on a global 3D grid, and diagonalises the periodic
+ * case through the block-circulant structure.
+ *
+ * Conventions shared by every call
+ *   - All array arguments named *_dev are device pointers (HBM) owned by the
+ *     caller; the library never allocates, frees or retains them.  All other
+ *     pointers (inside tl_system) are host pointers read during the call only.
+ *   - Every call is asynchronous on `stream` (a hipStream_t, passed as void*;
+ *     NULL = the default stream).  It validates its arguments, enqueues its
+ *     kernels and returns; results are valid once the stream is synchronised.
+ *   - Return value: TL_OK (0) or a negative tl_status.  On error nothing is
+ *     enqueued and tl_last_error() returns a message for the calling thread.
+ *   - Layout: row-major, FP64.  Complex values are interleaved (re, im) pairs.
+ *   - Numerical failures inside a batched eigensolve never fail the call;
+ *     they are reported per problem in an `info` array.
+ */
+#ifndef TL_H
+#define TL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int tl_status;
+#define TL_OK 0
+#define TL_EINVAL (-1)         /* invalid argument (see tl_last_error)          */
+#define TL_EUNSUPPORTED (-2)   /* valid request outside what this build covers  */
+#define TL_EHIP (-3)           /* a HIP runtime call failed                     */
+#define TL_EWORKSPACE (-4)     /* workspace argument smaller than required      */
+
+typedef enum {
+  TL_FP64 = 0,        /* 1D contractions in FP64 (MFMA f64)                          */
+  TL_FP32 = 1,        /* 1D contractions in FP32 (MFMA f32), FP64 chunk sums         */
+  TL_SPLIT_BF16 = 2,  /* operands split into bf16 slices, FP32 MFMA accumulation     */
+  TL_SPLIT_FP16 = 3   /* operands split into fp16 slices, FP32 MFMA accumulation     */
+} tl_precision;
+
+#define TL_MODE_PERIODIC 0   /* first block column of the 3-level block circulant */
+#define TL_MODE_BOX 1        /* full matrices of an open-boundary chain           */
+
+#define TL_MAX_M0 32
+#define TL_MAX_SITES 16
+#define TL_MAX_R 64
+
+/*
+ * Problem description (host memory).  Dimension l in {0,1,2} is x, y, z.
+ *  periodic[l] = 1: torus of L[l] cells of length a[l]; nodes x_i = i*h,
+ *     n[l] = L[l]*cell_nodes[l], cell_nodes[l] = a[l]/h (an integer).
+ *  periodic[l] = 0: open box, nodes x_i = x0[l] + i*h, homogeneous Dirichlet
+ *     conditions outside the n[l] nodes (Sec. 3.4).
+ *  mode TL_MODE_PERIODIC: nuc_pos/nuc_Z are the n_nuc sites of the unit cell
+ *     (offsets from the cell origin, k*a for cell k), at most TL_MAX_SITES;
+ *     in periodic dims the offsets must be multiples of h.  K[l] is the image
+ *     range -K..K of the lattice sum restricted to the central cell
+ *     (Sec. 4.1, eq. (EwaldSumP)).
+ *  mode TL_MODE_BOX: nuc_pos/nuc_Z list every nucleus (absolute positions);
+ *     the L[0] cells of a chain along x carry the basis, cell c at
+ *     x = box_origin0 + c*a[0], y = z = 0.  All three dims must be open.
+ *  Basis function mu of a cell (m0 <= TL_MAX_M0): centre cell origin +
+ *     fn_center[3*mu..], 1D factors fn_coef[3*mu+l] (x-A_l)^fn_l[3*mu+l]
+ *     exp(-fn_alpha[mu] (x-A_l)^2), fn_l in {0,1}.
+ *  Newton kernel: 1/rho ~ sum_{q<R} w_q exp(-t_q^2 rho^2) (Sec. 3.2,
+ *     eq. (sinc_general)).
+ */
+typedef struct {
+  int mode;
+  int L[3];
+  int periodic[3];
+  int n[3];
+  int cell_nodes[3];
+  int K[3];
+  double h;
+  double x0[3];
+  double a[3];
+  double box_origin0;
+  int n_nuc;
+  const double* nuc_pos;   /* [n_nuc][3] */
+  const double* nuc_Z;     /* [n_nuc]    */
+  int m0;
+  const double* fn_center; /* [m0][3] */
+  const int* fn_l;         /* [m0][3] */
+  const double* fn_alpha;  /* [m0]    */
+  const double* fn_coef;   /* [m0][3] */
+  int R;
+  const double* t_q;       /* [R] */
+  const double* w_q;       /* [R] */
+} tl_system;
+
+/* Library identification and the thread-local text of the last error. */
+const char* tl_version(void);
+const char* tl_status_string(tl_status s);
+const char* tl_last_error(void);
+
+/*
+ * Sizes (in elements, not bytes) of the arrays exchanged for a system.
+ *   basis_rows[l]   rows of the sampled basis on dim l: m0, or L[0]*m0 on
+ *                   dim 0 in box mode.
+ *   basis_elems     sum_l basis_rows[l]*n[l] (one array each for G, AG, SG;
+ *                   dim l starts at offset sum_{e<l} basis_rows[e]*n[e]).
+ *   pot_terms       canonical rank of the potential: R times the number of
+ *                   groups of nuclei sharing their (y,z) position.
+ *   pot_elems       sum_l pot_terms*n[l] (dim l at offset pot_terms*sum_{e<l} n[e]).
+ *   block_elems     periodic: L1*L2*L3*m0*m0 (one real array each for H, S);
+ *                   box: (L[0]*m0)^2.
+ */
+typedef struct {
+  int64_t basis_rows[3];
+  int64_t basis_elems;
+  int64_t pot_terms;
+  int64_t pot_elems;
+  int64_t block_elems;
+} tl_sizes;
+tl_status tl_query_sizes(const tl_system* sys, tl_sizes* out);
+
+/* Workspace (bytes of device memory, 256-byte aligned by the caller) that
+ * tl_lattice_sum_potential and tl_assemble_core_hamiltonian_block need. */
+tl_status tl_potential_workspace_bytes(const tl_system* sys, size_t* bytes);
+tl_status tl_assemble_workspace_bytes(const tl_system* sys, tl_precision prec,
+                                      int n_slices, size_t* bytes);
+tl_status tl_block_fft_workspace_bytes(int L1, int L2, int L3, int m0, int batch,
+                                       size_t* bytes);
+
+/*
+ * tl_build_basis - nodal samples of the basis and its FEM images
+ * (Sec. 3.4, eq. (Gaus pwl) and the 1D matrices A = (1/h) tridiag(-1,2,-1),
+ * S = (h/6) tridiag(1,4,1)).
+ *   G_dev[row][i]  = g_row(x_i), periodised over the torus in periodic dims
+ *                    (sum over images within exp(-46) of the peak),
+ *   AG_dev = A g, SG_dev = S g (circulant on a torus, Dirichlet in a box).
+ * Each array holds basis_elems doubles.  Periodic mode: the rows are the m0
+ * functions of cell 0; box mode, dim 0: row c*m0+mu is function mu of cell c.
+ */
+tl_status tl_build_basis(const tl_system* sys, double* G_dev, double* AG_dev, double* SG_dev,
+                         void* stream);
+
+/*
+ * tl_lattice_sum_potential - canonical 1D vectors of the lattice-summed
+ * Newton potential (Sec. 3.2 eqs. (galten), (core_tens), (EwaldTensorGl);
+ * Sec. 4.1 eq. (EwaldSumP)).  For term t = g*R + q (g = group of nuclei with
+ * equal (y,z), q = quadrature node):
+ *   P_dev[l][t][i] = prod over l of these factors gives sum_nu Z_nu w_q
+ *   exp-sum image of the cell-averaged kernel; w_q and Z_nu sit in dim 0.
+ *   Periodic dims: image sum k = -K..K of cell integrals
+ *   int_cell exp(-t_q^2 (y - o - k a)^2) dy evaluated on the central cell and
+ *   replicated with period a ("master" vectors on the accompanying grid,
+ *   shifted and windowed); box dims: one factor per nucleus.
+ * P_dev holds pot_elems doubles; ws_dev holds tl_potential_workspace_bytes.
+ */
+tl_status tl_lattice_sum_potential(const tl_system* sys, double* P_dev, void* ws_dev,
+                                   size_t ws_bytes, void* stream);
+
+/*
+ * tl_assemble_core_hamiltonian_block - Galerkin matrices from 1D inner
+ * products (proof of Lemma 3.1, eq. (nuc_potMatrTot); Sec. 3.4 A_3; Lemma 4.1
+ * eqs. (BC-Core), (BC-mass), (BC-Laplace)):
+ *   C_l[t][mu][nu][s] = sum_i g_mu(x_i - s a_l) p_t(x_i) g_nu(x_i)
+ *   D_l, M_l likewise with A g_nu, S g_nu in place of p_t g_nu,
+ *   V = sum_t prod_l C_l,  T = 1/2 (D1 M2 M3 + M1 D2 M3 + M1 M2 D3),
+ *   S = M1 M2 M3,  H = T - V.
+ * Periodic mode: H_dev, S_dev = generating blocks (first block column)
+ *   [k1][k2][k3][mu][nu], A_k[mu][nu] = <g_(mu, cell k) | op | g_(nu, cell 0)>,
+ *   only shifts 0..L/2 are contracted; A_{-k} = A_k^T fills the rest.
+ * Box mode: H_dev, S_dev = full (L0*m0)^2 matrices, row c*m0+mu.
+ * prec selects the arithmetic of the 1D contractions; the combination over
+ * terms and dimensions is FP64 in every mode.  n_slices is used by the split
+ * modes (2..8 slices per operand), ignored otherwise.
+ * Inputs: the arrays filled by tl_build_basis and tl_lattice_sum_potential.
+ */
+tl_status tl_assemble_core_hamiltonian_block(const tl_system* sys, const double* G_dev,
+                                             const double* AG_dev, const double* SG_dev,
+                                             const double* P_dev, tl_precision prec,
+                                             int n_slices, double* H_dev, double* S_dev,
+                                             void* ws_dev, size_t ws_bytes, void* stream);
+
+/*
+ * tl_set_contraction_events - profiling hook: when both are non-NULL, the
+ * assembly calls made afterwards by the calling thread record start_event
+ * (a hipEvent_t) on their stream right before the 1D-contraction kernels
+ * and stop_event right after them, so a caller can time that kernel
+ * live with hipEventElapsedTime.  NULL, NULL switches the hook off.
+ * The events stay owned by the caller.
+ */
+tl_status tl_set_contraction_events(void* start_event, void* stop_event);
+
+/*
+ * tl_block_fft - Fourier block-diagonalisation of 3-level block-circulant
+ * matrices (Lemma 2.2 eq. (DiagMLcirc); Appendix, Proposition on
+ * block-circulant diagonalisation):
+ *   out[b][j1][j2][j3] = sum_k w1^(j1 k1) w2^(j2 k2) w3^(j3 k3) in[b][k1][k2][k3],
+ *   w_l = exp(-2 pi i / L_l), for every m0 x m0 entry, for each of `batch`
+ *   real input block columns.  in_dev: batch*L1*L2*L3*m0*m0 doubles;
+ *   out_dev: the same count of complex values (2x doubles).
+ * ws_dev: tl_block_fft_workspace_bytes (0 when at most one L_l exceeds 1).
+ */
+tl_status tl_block_fft(const double* in_dev, int L1, int L2, int L3, int m0, int batch,
+                       double* out_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/*
+ * tl_batched_heigh - eigenvalues (and optionally eigenvectors) of `count`
+ * Hermitian-definite pencils (Hbar_j - lambda Sbar_j) u = 0 of order m0
+ * (Sec. 4.2 eq. (HF-FSpace-Block); Proposition eq. (lambdAbc)).
+ *   H_dev, S_dev: [count][m0][m0] complex (S_dev may be NULL: standard problem).
+ *   evals_dev: [count][m0] ascending.  evecs_dev (nullable): [count][m0][m0]
+ *   complex, column m = eigenvector of evals[m], normalised u^H Sbar u = 1.
+ *   info_dev: [count] int, 0 = converged, k > 0 = Sbar not positive definite
+ *   at pivot k (evals set to NaN), -1 = Jacobi iteration did not converge.
+ * Method: Cholesky Sbar = L L^H, C = L^-1 Hbar L^-H, cyclic parallel complex
+ * Jacobi, u = L^-H v.  1 <= m0 <= TL_MAX_M0.
+ */
+tl_status tl_batched_heigh(const double* H_dev, const double* S_dev, int count, int m0,
+                           double* evals_dev, double* evecs_dev, int* info_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TL_H */

@@ -1,0 +1,123 @@
+// Step a6: Fourier block-diagonalisation of a 3-level block-circulant matrix.
+//   Abar_j = sum_k w1^(j1 k1) w2^(j2 k2) w3^(j3 k3) A_k,  w_l = exp(-2 pi i / L_l)
+// (Lemma 2.2, eq. (DiagMLcirc); Appendix, Proposition on block-circulant
+// diagonalisation).  F_L = F_L1 x F_L2 x F_L3 is applied one lattice axis at
+// a time; each pass is a batched 1D DFT along that axis for every entry of
+// every m0 x m0 block.  Twiddles use the exact residue (j k mod L), so the
+// phase is never formed from a large angle.
+#include <algorithm>
+
+#include "common.h"
+
+namespace tl {
+namespace {
+
+struct DftArgs {
+  const double* in;   // real (first pass) or complex input
+  double* out;        // complex output
+  int len;            // transform length along the axis
+  int64_t inner;      // product of the extents after the axis, times m0*m0
+  int64_t total;      // number of output complex values
+  int real_in;
+};
+
+// Thread per output value; consecutive threads carry consecutive block
+// entries, so loads are coalesced along the m0*m0 entries of each block.
+__global__ __launch_bounds__(256) void dft_axis_kernel(DftArgs a) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.total) return;
+  // decompose idx = ((outer * len) + j) * inner + r
+  int64_t r = idx % a.inner;
+  int64_t rest = idx / a.inner;
+  int j = (int)(rest % a.len);
+  int64_t outer = rest / a.len;
+  int64_t base = (outer * a.len) * a.inner + r;
+  double re = 0.0, im = 0.0;
+  int p = 0;  // (j * k) mod len
+  const double inv = 2.0 / (double)a.len;
+  for (int k = 0; k < a.len; ++k) {
+    double s, c;
+    sincospi((double)p * inv, &s, &c);  // w^p = cos(2 pi p/L) - i sin(2 pi p/L)
+    int64_t src = base + (int64_t)k * a.inner;
+    if (a.real_in) {
+      double x = a.in[src];
+      re += c * x;
+      im -= s * x;
+    } else {
+      double xr = a.in[2 * src], xi = a.in[2 * src + 1];
+      re += c * xr + s * xi;
+      im += c * xi - s * xr;
+    }
+    p += j;
+    if (p >= a.len) p -= a.len;
+  }
+  a.out[2 * idx] = re;
+  a.out[2 * idx + 1] = im;
+}
+
+}  // namespace
+
+tl_status block_fft(const double* in, int L1, int L2, int L3, int m0, int batch, double* out,
+                    void* ws, size_t ws_bytes, hipStream_t stream) {
+  const int L[3] = {L1, L2, L3};
+  const int64_t E = (int64_t)m0 * m0;
+  const int64_t total = (int64_t)batch * L1 * L2 * L3 * E;
+  int axes[3], na = 0;
+  for (int d = 0; d < 3; ++d)
+    if (L[d] > 1) axes[na++] = d;
+  size_t need = na >= 2 ? align_up(sizeof(double) * 2 * (size_t)total, 256) : 0;
+  if (ws_bytes < need || (need && !ws)) {
+    set_error("block_fft workspace: need %zu bytes, got %zu", need, ws_bytes);
+    return TL_EWORKSPACE;
+  }
+  double* tmp = (double*)ws;
+  if (na == 0) {  // one cell: the block is its own transform (imaginary part 0)
+    DftArgs a{in, out, 1, E, total, 1};
+    hipLaunchKernelGGL(dft_axis_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream,
+                       a);
+    TL_CHECK_LAUNCH();
+    return TL_OK;
+  }
+  // pass 0 reads `in`, the last pass writes `out`: in->out (one axis),
+  // in->tmp->out (two axes), in->out->tmp->out (three axes).
+  const double* src = in;
+  for (int p = 0; p < na; ++p) {
+    int d = axes[p];
+    int64_t inner = E;
+    for (int e = d + 1; e < 3; ++e) inner *= L[e];
+    double* dst = out;
+    if (na == 2 && p == 0) dst = tmp;
+    if (na == 3 && p == 1) dst = tmp;
+    DftArgs a{src, dst, L[d], inner, total, p == 0};
+    hipLaunchKernelGGL(dft_axis_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream,
+                       a);
+    TL_CHECK_LAUNCH();
+    src = dst;
+  }
+  return TL_OK;
+}
+
+}  // namespace tl
+
+extern "C" tl_status tl_block_fft_workspace_bytes(int L1, int L2, int L3, int m0, int batch,
+                                                  size_t* bytes) {
+  tl::clear_error();
+  TL_REQUIRE(bytes != nullptr, "null output");
+  TL_REQUIRE(L1 >= 1 && L2 >= 1 && L3 >= 1 && m0 >= 1 && batch >= 1, "invalid sizes");
+  int na = (L1 > 1) + (L2 > 1) + (L3 > 1);
+  int64_t total = (int64_t)batch * L1 * L2 * L3 * m0 * m0;
+  *bytes = na >= 2 ? tl::align_up(sizeof(double) * 2 * (size_t)total, 256) : 0;
+  return TL_OK;
+}
+
+extern "C" tl_status tl_block_fft(const double* in_dev, int L1, int L2, int L3, int m0, int batch,
+                                  double* out_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  tl::clear_error();
+  TL_REQUIRE(in_dev && out_dev, "null array argument");
+  TL_REQUIRE(L1 >= 1 && L2 >= 1 && L3 >= 1, "lattice extents must be >= 1");
+  TL_REQUIRE(m0 >= 1 && m0 <= TL_MAX_M0, "m0 outside [1, %d]", TL_MAX_M0);
+  TL_REQUIRE(batch >= 1, "batch must be >= 1");
+  TL_REQUIRE((int64_t)L1 * L2 * L3 <= (1 << 22), "lattice too large");
+  return tl::block_fft(in_dev, L1, L2, L3, m0, batch, out_dev, ws_dev, ws_bytes,
+                       (hipStream_t)stream);
+}

@@ -1,0 +1,337 @@
+// Step a7: batched eigensolver for the k-block pencils (Hbar_j - lambda Sbar_j)
+// of the Fourier-space problem (Sec. 4.2, eq. (HF-FSpace-Block); Proposition
+// on block-circulant diagonalisation, eq. (lambdAbc)).
+//
+// One workgroup per block, one thread per matrix entry, everything in LDS:
+//   1. Cholesky Sbar = L L^H (lower),
+//   2. C = L^-1 Hbar L^-H by two forward substitutions, Hermitian average,
+//   3. complex Jacobi iteration with the parallel round-robin ordering
+//      (m/2 disjoint rotations per round, every thread updates its own
+//      entry from the four entries of its 2x2 coupling),
+//   4. eigenvalues sorted ascending; eigenvectors u = L^-H v.
+#include <cmath>
+
+#include "common.h"
+
+namespace tl {
+namespace {
+
+struct cx {
+  double re, im;
+};
+__device__ inline cx cmul(cx a, cx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline cx cconj(cx a) { return {a.re, -a.im}; }
+__device__ inline cx cadd(cx a, cx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline cx csub(cx a, cx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline cx cscale(cx a, double s) { return {a.re * s, a.im * s}; }
+__device__ inline double cabs2(cx a) { return a.re * a.re + a.im * a.im; }
+
+constexpr int kMaxSweeps = 60;
+
+template <int MAXM>
+__global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ H,
+                                                     const double* __restrict__ S, int m,
+                                                     double* __restrict__ evals,
+                                                     double* __restrict__ evecs,
+                                                     int* __restrict__ info) {
+  constexpr int LD = MAXM + 1;
+  constexpr int NP = MAXM / 2 + 1;
+  __shared__ cx A[MAXM * LD];  // Hbar -> C -> eigenvalues on the diagonal
+  __shared__ cx B[MAXM * LD];  // Sbar -> Cholesky factor L
+  __shared__ cx V[MAXM * LD];  // scratch, then the Jacobi eigenvectors
+  __shared__ double rc[NP], rs[NP], rtb[NP];
+  __shared__ cx rph[NP];
+  __shared__ int ract[NP];
+  __shared__ int partner[MAXM + 2], pid[MAXM + 2], first[MAXM + 2];
+  __shared__ int rank_of[MAXM];
+  __shared__ int fail;
+  __shared__ double red[2];
+
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int64_t blk = blockIdx.x;
+  const int mm = m * m;
+  const cx* Hb = (const cx*)H + blk * mm;
+  const cx* Sb = S ? (const cx*)S + blk * mm : nullptr;
+
+  for (int e = tid; e < mm; e += nt) {
+    int i = e / m, j = e - i * m;
+    A[i * LD + j] = Hb[e];
+    B[i * LD + j] = Sb ? Sb[e] : cx{i == j ? 1.0 : 0.0, 0.0};
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
+
+  // 1. Cholesky, right-looking, lower triangle of B.
+  if (Sb) {
+    for (int k = 0; k < m; ++k) {
+      if (tid == 0) {
+        double d = B[k * LD + k].re;
+        if (!(d > 0.0) || !isfinite(d))
+          fail = k + 1;
+        else
+          B[k * LD + k] = {sqrt(d), 0.0};
+      }
+      __syncthreads();
+      if (fail) break;
+      double inv = 1.0 / B[k * LD + k].re;
+      for (int i = k + 1 + tid; i < m; i += nt) B[i * LD + k] = cscale(B[i * LD + k], inv);
+      __syncthreads();
+      int w = m - k - 1;
+      for (int e = tid; e < w * w; e += nt) {
+        int i = k + 1 + e / w, j = k + 1 + e % w;
+        if (j <= i) B[i * LD + j] = csub(B[i * LD + j], cmul(B[i * LD + k], cconj(B[j * LD + k])));
+      }
+      __syncthreads();
+    }
+  }
+  if (fail) {
+    for (int i = tid; i < m; i += nt) evals[blk * m + i] = NAN;
+    if (evecs)
+      for (int e = tid; e < mm; e += nt) {
+        ((cx*)evecs)[blk * mm + e] = {0.0, 0.0};
+      }
+    if (tid == 0) info[blk] = fail;
+    return;
+  }
+
+  // 2. C = L^-1 Hbar L^-H.  W = L^-1 Hbar in place in A, then Z = L^-1 W^H in
+  // V, C = Z^H back in A.
+  if (Sb) {
+    for (int i = 0; i < m; ++i) {
+      for (int j = tid; j < m; j += nt) {
+        cx s = A[i * LD + j];
+        for (int k = 0; k < i; ++k) s = csub(s, cmul(B[i * LD + k], A[k * LD + j]));
+        A[i * LD + j] = cscale(s, 1.0 / B[i * LD + i].re);
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < mm; e += nt) {
+      int i = e / m, j = e - i * m;
+      V[i * LD + j] = cconj(A[j * LD + i]);
+    }
+    __syncthreads();
+    for (int i = 0; i < m; ++i) {
+      for (int j = tid; j < m; j += nt) {
+        cx s = V[i * LD + j];
+        for (int k = 0; k < i; ++k) s = csub(s, cmul(B[i * LD + k], V[k * LD + j]));
+        V[i * LD + j] = cscale(s, 1.0 / B[i * LD + i].re);
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < mm; e += nt) {
+      int i = e / m, j = e - i * m;
+      A[i * LD + j] = cconj(V[j * LD + i]);
+    }
+    __syncthreads();
+  }
+  // Hermitian average (removes the rounding asymmetry), V = I.  The launch
+  // has at least m*m threads: thread e owns entry (e / m, e % m).
+  const bool owner = tid < mm;
+  const int ei = owner ? tid / m : 0, ej = owner ? tid - (tid / m) * m : 0;
+  {
+    cx mine = {0.0, 0.0};
+    if (owner) {
+      cx a = A[ei * LD + ej], b = A[ej * LD + ei];
+      mine = ei == ej ? cx{a.re, 0.0} : cscale(cadd(a, cconj(b)), 0.5);
+    }
+    __syncthreads();
+    if (owner) {
+      A[ei * LD + ej] = mine;
+      V[ei * LD + ej] = {ei == ej ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+  }
+
+  // 3. Jacobi sweeps, round-robin pairing of the (even-padded) indices.
+  int converged = (m == 1);
+  const int me = m + (m & 1);
+  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+    // convergence: off-diagonal Frobenius norm against the whole norm
+    if (tid < 2) red[tid] = 0.0;
+    __syncthreads();
+    double off = 0.0, all = 0.0;
+    if (owner) {
+      double v = cabs2(A[ei * LD + ej]);
+      all = v;
+      if (ei != ej) off = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      all += __shfl_xor(all, o);
+    }
+    if ((tid & 63) == 0) {
+      atomicAdd(&red[0], off);
+      atomicAdd(&red[1], all);
+    }
+    __syncthreads();
+    if (red[0] <= 1e-32 * red[1]) {
+      converged = 1;
+      break;
+    }
+    __syncthreads();
+    for (int r = 0; r < me - 1; ++r) {
+      for (int pk = tid; pk < me / 2; pk += nt) {
+        int p, q;
+        if (pk == 0) {
+          p = me - 1;
+          q = r;
+        } else {
+          p = (r + pk) % (me - 1);
+          q = (r - pk + me - 1) % (me - 1);
+        }
+        if (p > q) {
+          int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        partner[p] = q;
+        partner[q] = p;
+        first[p] = 1;
+        first[q] = 0;
+        pid[p] = pk;
+        pid[q] = pk;
+        int act = 0;
+        if (q < m) {
+          double a = A[p * LD + p].re, d = A[q * LD + q].re;
+          cx b = A[p * LD + q];
+          double ab = sqrt(cabs2(b));
+          if (ab > 0.0) {
+            double tau = (d - a) / (2.0 * ab);
+            double t;
+            if (fabs(tau) > 1e150)
+              t = 0.5 / tau;
+            else
+              t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            double c = 1.0 / sqrt(1.0 + t * t);
+            rc[pk] = c;
+            rs[pk] = t * c;
+            rtb[pk] = t * ab;
+            rph[pk] = cscale(cconj(b), 1.0 / ab);  // exp(-i phi), b = |b| exp(i phi)
+            act = 1;
+          }
+        }
+        ract[pk] = act;
+      }
+      __syncthreads();
+      // new entry of this thread in registers, then written back
+      cx na = {0.0, 0.0}, nv = {0.0, 0.0};
+      if (owner) {
+        const int i = ei, j = ej;
+        // column i of J: diagonal entry Jii and the partner entry Jpi (row partner(i))
+        int pi = pid[i], pj = pid[j];
+        int ai = ract[pi], aj = ract[pj];
+        int ip = partner[i], jp = partner[j];
+        cx Jii = {1.0, 0.0}, Jpi = {0.0, 0.0}, Jjj = {1.0, 0.0}, Jpj = {0.0, 0.0};
+        if (ai) {
+          double cc = rc[pi], ss = rs[pi];
+          cx ph = rph[pi];
+          if (first[i]) {
+            Jii = {cc, 0.0};
+            Jpi = cscale(ph, -ss);
+          } else {
+            Jii = cscale(ph, cc);
+            Jpi = {ss, 0.0};
+          }
+        }
+        if (aj) {
+          double cc = rc[pj], ss = rs[pj];
+          cx ph = rph[pj];
+          if (first[j]) {
+            Jjj = {cc, 0.0};
+            Jpj = cscale(ph, -ss);
+          } else {
+            Jjj = cscale(ph, cc);
+            Jpj = {ss, 0.0};
+          }
+        }
+        if (ai && pi == pj) {
+          // inside one rotated 2x2 block: exact diagonal form
+          if (i == j)
+            na = {A[i * LD + i].re + (first[i] ? -rtb[pi] : rtb[pi]), 0.0};
+        } else {
+          // sum over a in {i, ip}, b in {j, jp} of conj(J[a][i]) A[a][b] J[b][j]
+          cx t0 = cmul(A[i * LD + j], Jjj);
+          if (aj) t0 = cadd(t0, cmul(A[i * LD + jp], Jpj));
+          na = cmul(cconj(Jii), t0);
+          if (ai) {
+            cx t1 = cmul(A[ip * LD + j], Jjj);
+            if (aj) t1 = cadd(t1, cmul(A[ip * LD + jp], Jpj));
+            na = cadd(na, cmul(cconj(Jpi), t1));
+          }
+        }
+        nv = cmul(V[i * LD + j], Jjj);
+        if (aj) nv = cadd(nv, cmul(V[i * LD + jp], Jpj));
+      }
+      __syncthreads();
+      if (owner) {
+        A[ei * LD + ej] = na;
+        V[ei * LD + ej] = nv;
+      }
+      __syncthreads();
+    }
+  }
+
+  // 4. sort ascending, back-transform u = L^-H v, write out.
+  for (int i = tid; i < m; i += nt) {
+    double li = A[i * LD + i].re;
+    int rk = 0;
+    for (int k = 0; k < m; ++k) {
+      double lk = A[k * LD + k].re;
+      if (lk < li || (lk == li && k < i)) ++rk;
+    }
+    rank_of[i] = rk;
+    evals[blk * m + rk] = li;
+  }
+  if (tid == 0) info[blk] = converged ? 0 : -1;
+  __syncthreads();
+  if (evecs) {
+    if (Sb) {
+      for (int i = m - 1; i >= 0; --i) {
+        for (int j = tid; j < m; j += nt) {
+          cx s = V[i * LD + j];
+          for (int k = i + 1; k < m; ++k) s = csub(s, cmul(cconj(B[k * LD + i]), V[k * LD + j]));
+          V[i * LD + j] = cscale(s, 1.0 / B[i * LD + i].re);
+        }
+        __syncthreads();
+      }
+    }
+    cx* out = (cx*)evecs + blk * mm;
+    for (int e = tid; e < mm; e += nt) {
+      int i = e / m, j = e - i * m;
+      out[i * m + rank_of[j]] = V[i * LD + j];
+    }
+  }
+}
+
+}  // namespace
+
+tl_status batched_heigh(const double* H, const double* S, int count, int m, double* evals,
+                        double* evecs, int* info, hipStream_t stream) {
+  int threads = (int)std::max<int64_t>(64, ceil_div((int64_t)m * m, 64) * 64);
+  if (m <= 8) {
+    hipLaunchKernelGGL(heigh_kernel<8>, dim3(count), dim3(threads), 0, stream, H, S, m, evals,
+                       evecs, info);
+  } else if (m <= 16) {
+    hipLaunchKernelGGL(heigh_kernel<16>, dim3(count), dim3(threads), 0, stream, H, S, m, evals,
+                       evecs, info);
+  } else {
+    hipLaunchKernelGGL(heigh_kernel<32>, dim3(count), dim3(threads), 0, stream, H, S, m, evals,
+                       evecs, info);
+  }
+  TL_CHECK_LAUNCH();
+  return TL_OK;
+}
+
+}  // namespace tl
+
+extern "C" tl_status tl_batched_heigh(const double* H_dev, const double* S_dev, int count, int m0,
+                                      double* evals_dev, double* evecs_dev, int* info_dev,
+                                      void* stream) {
+  tl::clear_error();
+  TL_REQUIRE(H_dev && evals_dev && info_dev, "null array argument");
+  TL_REQUIRE(m0 >= 1 && m0 <= TL_MAX_M0, "m0 = %d outside [1, %d]", m0, TL_MAX_M0);
+  TL_REQUIRE(count >= 1 && count <= (1 << 30), "count = %d out of range", count);
+  return tl::batched_heigh(H_dev, S_dev, count, m0, evals_dev, evecs_dev, info_dev,
+                           (hipStream_t)stream);
+}

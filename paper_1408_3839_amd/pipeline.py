@@ -1,0 +1,84 @@
+"""Device buffers and call sequence for the periodic path (plumbing only).
+
+Allocates the arrays that the C ABI exchanges (torch tensors on the GPU) and
+runs the five calls in order on one stream:
+
+    tl_build_basis -> tl_lattice_sum_potential -> tl_assemble_core_hamiltonian_block
+    -> tl_block_fft (H and S as a batch of two) -> tl_batched_heigh
+"""
+from __future__ import annotations
+
+import torch
+
+from . import tl
+
+
+class PeriodicPipeline:
+    def __init__(self, sys, precision: str = "fp64", n_slices: int = 0,
+                 device: str = "cuda:0", with_evecs: bool = False):
+        if sys.mode != "periodic":
+            raise ValueError("PeriodicPipeline needs a periodic-mode system")
+        tl.load()
+        self.sys = sys
+        self.handle = tl.SystemHandle(sys)
+        self.prec = tl.PRECISIONS[precision]
+        self.n_slices = int(n_slices)
+        self.device = torch.device(device)
+        sz = tl.tl_query_sizes(self.handle)
+        self.sizes = sz
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.G = torch.empty(sz["basis_elems"], **f64)
+        self.AG = torch.empty(sz["basis_elems"], **f64)
+        self.SG = torch.empty(sz["basis_elems"], **f64)
+        self.P = torch.empty(sz["pot_elems"], **f64)
+        self.pot_ws_bytes = tl.tl_potential_workspace_bytes(self.handle)
+        self.pot_ws = torch.empty(max(1, self.pot_ws_bytes), dtype=torch.uint8, device=self.device)
+        self.asm_ws_bytes = tl.tl_assemble_workspace_bytes(self.handle, self.prec, self.n_slices)
+        self.asm_ws = torch.empty(max(1, self.asm_ws_bytes), dtype=torch.uint8, device=self.device)
+        L = [int(v) for v in sys.L]
+        self.L = L
+        self.m0 = sys.m0
+        self.nblocks = L[0] * L[1] * L[2]
+        self.HS = torch.empty(2, sz["block_elems"], **f64)          # H and S block columns
+        self.HSbar = torch.empty(2, sz["block_elems"], 2, **f64)    # their transforms
+        self.fft_ws_bytes = tl.tl_block_fft_workspace_bytes(L[0], L[1], L[2], self.m0, 2)
+        self.fft_ws = torch.empty(max(1, self.fft_ws_bytes), dtype=torch.uint8, device=self.device)
+        self.evals = torch.empty(self.nblocks, self.m0, **f64)
+        self.evecs = torch.empty(self.nblocks, self.m0, self.m0, 2, **f64) if with_evecs else None
+        self.info = torch.empty(self.nblocks, dtype=torch.int32, device=self.device)
+
+    @property
+    def H(self):
+        return self.HS[0].view(*self.L, self.m0, self.m0)
+
+    @property
+    def S(self):
+        return self.HS[1].view(*self.L, self.m0, self.m0)
+
+    def build_basis(self, stream=None):
+        tl.tl_build_basis(self.handle, self.G, self.AG, self.SG, stream)
+
+    def lattice_sum_potential(self, stream=None):
+        tl.tl_lattice_sum_potential(self.handle, self.P, self.pot_ws, self.pot_ws_bytes, stream)
+
+    def assemble(self, stream=None):
+        tl.tl_assemble_core_hamiltonian_block(self.handle, self.G, self.AG, self.SG, self.P,
+                                              self.prec, self.n_slices, self.HS[0], self.HS[1],
+                                              self.asm_ws, self.asm_ws_bytes, stream)
+
+    def block_fft(self, stream=None):
+        L = self.L
+        tl.tl_block_fft(self.HS, L[0], L[1], L[2], self.m0, 2, self.HSbar, self.fft_ws,
+                        self.fft_ws_bytes, stream)
+
+    def heigh(self, stream=None):
+        tl.tl_batched_heigh(self.HSbar[0], self.HSbar[1], self.nblocks, self.m0, self.evals,
+                            self.evecs, self.info, stream)
+
+    def run(self, stream=None):
+        self.build_basis(stream)
+        self.lattice_sum_potential(stream)
+        self.assemble(stream)
+        self.block_fft(stream)
+        self.heigh(stream)
+        return self.evals

@@ -1,0 +1,99 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/tl.h, reports the documented sizes and
+rejects invalid arguments before enqueuing anything."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1408_3839_amd import tl, workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "tl.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tl_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tl.load()
+    names = _declared()
+    assert "tl_batched_heigh" in names and len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in tl.SIGNATURES, n
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in tl.tl_version()
+    lib = tl.load()
+    assert lib.tl_status_string(tl.TL_EWORKSPACE).decode() == "workspace too small"
+
+
+@pytest.mark.parametrize("cid", [1, 2, 3, 5])
+def test_sizes(cid):
+    s = wl.config(cid)
+    z = tl.tl_query_sizes(s)
+    groups = len({(float(p[1]), float(p[2])) for p in s.nuc_pos})
+    assert z["pot_terms"] == s.R * groups
+    rows = [s.m0 * (s.ncells if (s.mode == "box" and d == 0) else 1) for d in range(3)]
+    assert z["basis_rows"] == rows
+    assert z["basis_elems"] == sum(rows[d] * int(s.n[d]) for d in range(3))
+    assert z["pot_elems"] == z["pot_terms"] * int(np.sum(s.n))
+    nb = s.ncells * s.m0
+    assert z["block_elems"] == (nb * nb if s.mode == "box" else s.ncells * s.m0 * s.m0)
+
+
+def _expect(status_fn, code, *args):
+    with pytest.raises(tl.TlError) as ei:
+        status_fn(*args)
+    assert tl.load().tl_status_string(code).decode() in str(ei.value)
+    return str(ei.value)
+
+
+def test_invalid_systems_rejected():
+    base = wl.config(1)
+    cases = []
+    s = wl.config(1); s.h = 0.0; cases.append((s, "grid step"))
+    s = wl.config(1); s.fn_alpha = s.fn_alpha.copy(); s.fn_alpha[0] = -1.0; cases.append((s, "fn_alpha"))
+    s = wl.config(1); s.a = s.a.copy(); s.a[0] = 2.03; cases.append((s, "a[0]/h"))
+    s = wl.config(1); s.n = s.n.copy(); s.n[0] = 127; cases.append((s, "n[0]"))
+    s = wl.config(1); s.nuc_pos = s.nuc_pos + np.array([0.01, 0, 0]); cases.append((s, "multiples of h"))
+    s = wl.config(1); s.fn_l = s.fn_l.copy(); s.fn_l[0][0] = 2; cases.append((s, "fn_l"))
+    s = wl.config(1); s.t_q = s.t_q.copy(); s.t_q[3] = np.nan; cases.append((s, "quadrature"))
+    for sys, frag in cases:
+        msg = _expect(tl.tl_query_sizes, tl.TL_EINVAL, sys)
+        assert frag in msg, (frag, msg)
+    s = wl.tiny_periodic(m0=3)
+    s.fn_alpha = np.ones(33); s.fn_l = np.zeros((33, 3), int); s.fn_center = np.zeros((33, 3))
+    s.fn_coef = np.ones((33, 3))
+    assert "m0" in _expect(tl.tl_query_sizes, tl.TL_EINVAL, s)
+    assert base.R <= 64
+
+
+def test_null_outputs_and_small_workspaces_rejected():
+    s = wl.config(1)
+    _expect(tl.tl_build_basis, tl.TL_EINVAL, s, 0, 0, 0, 0)
+    _expect(tl.tl_lattice_sum_potential, tl.TL_EWORKSPACE, s, 16, 0, 0, 0)
+    _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EWORKSPACE, s, 8, 8, 8, 8,
+            tl.TL_FP64, 0, 8, 8, 0, 0, 0)
+    _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EINVAL, s, 8, 8, 8, 8, 7, 0, 8, 8,
+            0, 0, 0)
+    _expect(tl.tl_block_fft, tl.TL_EINVAL, 8, 0, 1, 1, 4, 1, 8, 0, 0, 0)
+    _expect(tl.tl_block_fft, tl.TL_EWORKSPACE, 8, 4, 4, 1, 4, 1, 8, 0, 0, 0)
+    _expect(tl.tl_batched_heigh, tl.TL_EINVAL, 8, 0, 4, 0, 8, 0, 8, 0)
+    _expect(tl.tl_batched_heigh, tl.TL_EINVAL, 8, 0, 4, 33, 8, 0, 8, 0)
+    _expect(tl.tl_batched_heigh, tl.TL_EINVAL, 0, 0, 4, 4, 8, 0, 8, 0)
+
+
+def test_workspace_queries():
+    for cid in (1, 2, 5):
+        s = wl.config(cid)
+        assert tl.tl_potential_workspace_bytes(s) > 0
+        assert tl.tl_assemble_workspace_bytes(s) % 256 == 0
+    assert tl.tl_block_fft_workspace_bytes(64, 1, 1, 8, 2) == 0
+    assert tl.tl_block_fft_workspace_bytes(8, 8, 8, 10, 2) == 8 * 2 * 512 * 100 * 2
