@@ -181,11 +181,13 @@ def potential_vectors(sys) -> List[np.ndarray]:
 # Galerkin entries: products of 1D inner products (Lemma 3.1 proof, Sec. 3.4)
 
 
-def shift_contractions(sys, d: int, G: np.ndarray, P: np.ndarray):
+def shift_contractions(sys, d: int, G: np.ndarray, P: np.ndarray, absolute: bool = False):
     """1D inner products on dimension d for every shift s of the left function
     by s cells (s = 0..L_d-1 on a torus, s = 0 in a box):
       C[t][mu][nu][s] = sum_i g_mu(x_i - s a) p_t(x_i) g_nu(x_i)
-      D[mu][nu][s]    = <A (shifted g_mu), g_nu>,  M[mu][nu][s] = <S (shifted g_mu), g_nu>."""
+      D[mu][nu][s]    = <A (shifted g_mu), g_nu>,  M[mu][nu][s] = <S (shifted g_mu), g_nu>.
+    absolute=True returns the same sums over absolute values of every product
+    (|A| and |S| stencils), the magnitude the sums have without cancellation."""
     per = bool(sys.periodic[d])
     nshift = int(sys.L[d]) if per else 1
     c = int(sys.cell_nodes[d])
@@ -194,12 +196,19 @@ def shift_contractions(sys, d: int, G: np.ndarray, P: np.ndarray):
     C = np.zeros((T, m0, m0, nshift))
     D = np.zeros((m0, m0, nshift))
     M = np.zeros((m0, m0, nshift))
+    if absolute:
+        G, P = np.abs(G), np.abs(P)
     for s in range(nshift):
         Gs = np.roll(G, s * c, axis=1)          # Gs[mu][i] = g_mu(x_{i - s c})
         for t in range(T):
             C[t, :, :, s] = (Gs * P[t]) @ G.T
-        D[:, :, s] = fem_stiffness(Gs, per, sys.h) @ G.T
-        M[:, :, s] = fem_mass(Gs, per, sys.h) @ G.T
+        if absolute:
+            # (1/h)(2|g_i| + |g_i-1| + |g_i+1|) = 4|g|/h - A|g|
+            D[:, :, s] = (4.0 * Gs / sys.h - fem_stiffness(Gs, per, sys.h)) @ G.T
+            M[:, :, s] = fem_mass(Gs, per, sys.h) @ G.T
+        else:
+            D[:, :, s] = fem_stiffness(Gs, per, sys.h) @ G.T
+            M[:, :, s] = fem_mass(Gs, per, sys.h) @ G.T
     return C, D, M
 
 
@@ -209,35 +218,38 @@ def core_hamiltonian_blocks(sys, return_parts: bool = False):
     S[k1][k2][k3][mu][nu] = <g_(mu,k) | g_(nu,0)> (FEM mass), with
       V_k = sum_t prod_d C^(d)[t][:,:,k_d]
       T_k = 1/2 (D1 M2 M3 + M1 D2 M3 + M1 M2 D3),  S_k = M1 M2 M3,  H_k = T_k - V_k.
-    Also returns `scale`, the entry magnitude without cancellation
-    (1/2 sum |T terms| + sum_t |prod_d C|), used by the parity norm."""
+    Also returns `scale`, the entry magnitude without any cancellation: the
+    same formula with every 1D sum taken over absolute values of its products
+    (|A| = (1/h) tridiag(1,2,1)), used by the parity norm."""
     assert sys.mode == "periodic"
     P = potential_vectors(sys)
-    parts = []
+    parts, absparts = [], []
     for d in range(3):
         G = cell0_basis(sys, d)
         parts.append(shift_contractions(sys, d, G, P[d]))
+        absparts.append(shift_contractions(sys, d, G, P[d], absolute=True))
     L = [int(v) for v in sys.L]
     m0 = sys.m0
     H = np.zeros((L[0], L[1], L[2], m0, m0))
     S = np.zeros_like(H)
     scale = np.zeros_like(H)
     (C1, D1, M1), (C2, D2, M2), (C3, D3, M3) = parts
+    (A1, E1, N1), (A2, E2, N2), (A3, E3, N3) = absparts
     for k1 in range(L[0]):
         for k2 in range(L[1]):
             for k3 in range(L[2]):
-                c1 = C1[:, :, :, k1]
-                c2 = C2[:, :, :, k2]
-                c3 = C3[:, :, :, k3]
-                V = np.sum(c1 * c2 * c3, axis=0)
-                Vabs = np.sum(np.abs(c1 * c2 * c3), axis=0)
+                V = np.sum(C1[:, :, :, k1] * C2[:, :, :, k2] * C3[:, :, :, k3], axis=0)
                 t1 = D1[:, :, k1] * M2[:, :, k2] * M3[:, :, k3]
                 t2 = M1[:, :, k1] * D2[:, :, k2] * M3[:, :, k3]
                 t3 = M1[:, :, k1] * M2[:, :, k2] * D3[:, :, k3]
                 T = 0.5 * (t1 + t2 + t3)
                 H[k1, k2, k3] = T - V
                 S[k1, k2, k3] = M1[:, :, k1] * M2[:, :, k2] * M3[:, :, k3]
-                scale[k1, k2, k3] = 0.5 * (np.abs(t1) + np.abs(t2) + np.abs(t3)) + Vabs
+                Va = np.sum(A1[:, :, :, k1] * A2[:, :, :, k2] * A3[:, :, :, k3], axis=0)
+                Ta = 0.5 * (E1[:, :, k1] * N2[:, :, k2] * N3[:, :, k3]
+                            + N1[:, :, k1] * E2[:, :, k2] * N3[:, :, k3]
+                            + N1[:, :, k1] * N2[:, :, k2] * E3[:, :, k3])
+                scale[k1, k2, k3] = Ta + Va
     if return_parts:
         return H, S, scale, {"P": P, "parts": parts}
     return H, S, scale

@@ -95,10 +95,12 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(ContractArgs a) {
     }
     __syncthreads();
   }
+  // f64 16x16x4 result layout on gfx950: register r of lane l holds
+  // D[l / 16 + 4 r][l % 16] (checked with a one-wave probe).
   const int col = col0 + wn * 16 + (lane & 15);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    int row = row0 + wm * 16 + 4 * (lane >> 4) + r;
+    int row = row0 + wm * 16 + (lane >> 4) + 4 * r;
     if (row < a.M && col < a.N) a.out[((int64_t)blockIdx.z * a.M + row) * a.N + col] = acc[r];
   }
 }

@@ -78,10 +78,12 @@ def test_basis_parity(name):
     for d in range(3):
         g = oracle.cell0_basis(sys, d)
         per = bool(sys.periodic[d])
-        for got, ref in ((G[d], g), (AG[d], oracle.fem_stiffness(g, per, sys.h)),
-                         (SG[d], oracle.fem_mass(g, per, sys.h))):
-            scale = np.abs(ref).max(axis=1, keepdims=True)
-            assert np.all(np.abs(got - ref) <= 1e-14 * scale + 1e-300), (name, d)
+        gmax = np.abs(g).max(axis=1, keepdims=True)
+        # the stencils cancel: their rounding scale is |g|/h and |g| h
+        for got, ref, scale in ((G[d], g, gmax),
+                                (AG[d], oracle.fem_stiffness(g, per, sys.h), 4 * gmax / sys.h),
+                                (SG[d], oracle.fem_mass(g, per, sys.h), gmax * sys.h)):
+            assert np.all(np.abs(got - ref) <= 1e-14 * scale), (name, d)
 
 
 @pytest.mark.parametrize("name", NAMES)
