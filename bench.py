@@ -119,20 +119,31 @@ def main():
         pl.run()
     torch.cuda.synchronize()
 
-    # HIP events around the contraction kernels of every timed step
+    # timed region 1: K whole steps, each one replay of the captured HIP graph
+    pl.capture()
+    for _ in range(args.warmup):
+        pl.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pl.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    # timed region 2: the same K steps launched eagerly, with HIP events
+    # recorded around the contraction kernel on its stream
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     for a, b in evs:
         a.record(stream)
         b.record(stream)
     torch.cuda.synchronize()
-
-    t0 = time.perf_counter()
+    te0 = time.perf_counter()
     for k in range(args.steps):
         tl.tl_set_contraction_events(evs[k][0].cuda_event, evs[k][1].cuda_event)
         pl.run()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    te1 = time.perf_counter()
     tl.tl_set_contraction_events(None, None)
 
     dt = t1 - t0
@@ -160,6 +171,8 @@ def main():
                         "alpha log-uniform [0.1,30], seed 2; grid 2048x256x256, h=0.0625; "
                         "R=24 sinc terms, images -32..32",
             "precision": args.precision,
+            "step": "one HIP-graph replay of the whole path",
+            "eager_ms_per_step": 1e3 * (te1 - te0) / args.steps,
             "entries_per_step": entries,
             "k_blocks_per_step": sys_.ncells,
         },
@@ -167,7 +180,7 @@ def main():
         "roofline": {
             "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": None,
-            "kernel": "contract_f64_kernel (1D contractions, 3 launches per step)",
+            "kernel": "contract_f64_kernel (1D contractions of the three dims, one launch)",
             "flops_per_step": flops, "avg_kernel_ms": contr_ms,
         },
     }
@@ -176,7 +189,8 @@ def main():
         out["cpu_baseline"] = cb
         H = pl.H.cpu().numpy()
         _, _, scale = __import__("oracle").core_hamiltonian_blocks(sys_)
-        acc = {"max_rel_dH_over_scale": float(np.max(np.abs(H - Hr) / scale))}
+        acc = {"max_rel_dH_over_scale":
+               float(np.max(np.abs(H - Hr) / np.where(scale > 0, scale, 1.0)))}
         acc.update(eig_errors(pl.evals.cpu().numpy(), Hb, Sb, sys_.m0))
         out["accuracy_vs_fp64_oracle"] = acc
     print(json.dumps(out))

@@ -31,68 +31,100 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBM = 32;   // rows of a workgroup tile (2 MFMA row blocks)
 constexpr int kBN = 32;   // columns of a workgroup tile (2 MFMA column blocks)
-constexpr int kKT = 32;   // nodes per LDS stage
+constexpr int kKT = 64;   // nodes per LDS stage
 constexpr int kLDP = kKT + 1;
+constexpr int kPerThread = kBM * kKT / 256;  // staged values per thread and operand
 
-struct ContractArgs {
+struct DimArgs {
   const double* G;
   const double* AG;
   const double* SG;
   const double* P;
-  double* out;     // [ksplit][M][N] partial sums
-  int n, m0, T, S, cn, M, N, kchunk;
+  double* part;    // [ks][M][N] partial sums over node chunks
+  int n, S, cn, M, N, kchunk, ks, tiles_n, block_begin;
 };
 
-// One workgroup = 4 waves = a 32 x 32 tile of C over one chunk of nodes; each
-// wave owns a 16 x 16 block and issues V_MFMA_F64_16X16X4_F64 from LDS.
+struct ContractArgs {
+  DimArgs d[3];
+  int m0, T;
+};
+
+// X[(t, nu)][i] for one staged element (0 outside the matrix / chunk).
+__device__ inline double x_value(const DimArgs& p, int m0, int T, int row, int i) {
+  int t = row / m0, nu = row - t * m0;
+  int64_t gi = (int64_t)nu * p.n + i;
+  if (t < T) return p.P[(int64_t)t * p.n + i] * p.G[gi];
+  return t == T ? p.AG[gi] : p.SG[gi];
+}
+
+// Y[(mu, s)][i] = g_mu(x_{i - s c}) (cyclic).
+__device__ inline double y_value(const DimArgs& p, int col, int i) {
+  int mu = col / p.S, s = col - mu * p.S;
+  int src = i - s * p.cn;
+  if (src < 0) src += p.n;
+  return p.G[(int64_t)mu * p.n + src];
+}
+
+// One launch for the three dimensions.  Workgroup = 4 waves = a 32 x 32 tile
+// of C_l over one chunk of nodes; each wave owns a 16 x 16 block and issues
+// V_MFMA_F64_16X16X4_F64 from LDS.  The next 64-node stage is loaded into
+// registers while the current one is multiplied (double buffering).
 __global__ __launch_bounds__(256) void contract_f64_kernel(ContractArgs a) {
   __shared__ double Xs[kBM][kLDP];
   __shared__ double Ys[kBN][kLDP];
+  const int b = blockIdx.x;
+  const int dd = b >= a.d[2].block_begin ? 2 : (b >= a.d[1].block_begin ? 1 : 0);
+  const DimArgs& p = a.d[dd];
+  const int local = b - p.block_begin;
+  const int z = local % p.ks;
+  const int rest = local / p.ks;
+  const int col0 = (rest % p.tiles_n) * kBN;
+  const int row0 = (rest / p.tiles_n) * kBM;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int col0 = blockIdx.x * kBN;
-  const int row0 = blockIdx.y * kBM;
-  const int kbeg = blockIdx.z * a.kchunk;
-  const int kend = min(a.n, kbeg + a.kchunk);
+  const int kbeg = z * p.kchunk;
+  const int kend = min(p.n, kbeg + p.kchunk);
   const int wm = wave >> 1, wn = wave & 1;
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kbeg; k0 < kend; k0 += kKT) {
-    for (int e = tid; e < kBM * kKT; e += 256) {
+  double xr[kPerThread], yr[kPerThread];
+
+  auto stage = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) {
+      int e = tid + 256 * j;
       int r = e / kKT, kk = e - r * kKT;
-      int row = row0 + r, i = k0 + kk;
-      double v = 0.0;
-      if (row < a.M && i < kend) {
-        int t = row / a.m0, nu = row - t * a.m0;
-        int64_t gi = (int64_t)nu * a.n + i;
-        if (t < a.T)
-          v = a.P[(int64_t)t * a.n + i] * a.G[gi];
-        else if (t == a.T)
-          v = a.AG[gi];
-        else
-          v = a.SG[gi];
-      }
-      Xs[r][kk] = v;
+      int i = k0 + kk;
+      bool in_k = i < kend;
+      int row = row0 + r, col = col0 + r;
+      xr[j] = (row < p.M && in_k) ? x_value(p, a.m0, a.T, row, i) : 0.0;
+      yr[j] = (col < p.N && in_k) ? y_value(p, col, i) : 0.0;
     }
-    for (int e = tid; e < kBN * kKT; e += 256) {
-      int c = e / kKT, kk = e - c * kKT;
-      int col = col0 + c, i = k0 + kk;
-      double v = 0.0;
-      if (col < a.N && i < kend) {
-        int mu = col / a.S, s = col - mu * a.S;
-        int src = i - s * a.cn;
-        if (src < 0) src += a.n;
-        v = a.G[(int64_t)mu * a.n + src];
-      }
-      Ys[c][kk] = v;
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) {
+      int e = tid + 256 * j;
+      int r = e / kKT, kk = e - r * kKT;
+      Xs[r][kk] = xr[j];
+      Ys[r][kk] = yr[j];
     }
-    __syncthreads();
+  };
+
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  stage(kbeg);
+  commit();
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += kKT) {
+    const bool more = k0 + kKT < kend;
+    if (more) stage(k0 + kKT);
 #pragma unroll
     for (int kk = 0; kk < kKT; kk += 4) {
       double av = Xs[wm * 16 + (lane & 15)][kk + (lane >> 4)];
       double bv = Ys[wn * 16 + (lane & 15)][kk + (lane >> 4)];
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
     }
+    __syncthreads();
+    if (more) commit();
     __syncthreads();
   }
   // f64 16x16x4 result layout on gfx950: register r of lane l holds
@@ -101,15 +133,33 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(ContractArgs a) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     int row = row0 + wm * 16 + (lane >> 4) + 4 * r;
-    if (row < a.M && col < a.N) a.out[((int64_t)blockIdx.z * a.M + row) * a.N + col] = acc[r];
+    if (row < p.M && col < p.N) p.part[((int64_t)z * p.M + row) * p.N + col] = acc[r];
   }
+}
+
+struct ReduceArgs {
+  const double* part[3];
+  double* C[3];
+  int64_t MN[3];
+  int ks[3];
+  int64_t begin[3];  // flat start of each dim; begin[3] implied by total
+};
+
+// Sums the node-chunk partial sums into the compact C_l (all dims at once).
+__global__ __launch_bounds__(256) void reduce_partials_kernel(ReduceArgs a, int64_t total) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  int d = idx >= a.begin[2] ? 2 : (idx >= a.begin[1] ? 1 : 0);
+  int64_t e = idx - a.begin[d];
+  const double* p = a.part[d] + e;
+  double v = 0.0;
+  for (int s = 0; s < a.ks[d]; ++s) v += p[(int64_t)s * a.MN[d]];
+  a.C[d][e] = v;
 }
 
 struct CombineArgs {
   const double* C[3];
-  int ks[3], S[3], L[3], periodic[3];
-  int64_t MN[3];
-  int N[3];
+  int S[3], L[3], periodic[3], N[3];
   int m0, T;
   double* H;
   double* Sm;
@@ -124,64 +174,83 @@ __device__ inline double lookup(const CombineArgs& a, int d, int t, int mu, int 
     row = t * a.m0 + mu;
     col = nu * a.S[d] + (a.L[d] - k);
   }
-  const double* p = a.C[d] + (int64_t)row * a.N[d] + col;
-  double v = 0.0;
-  for (int s = 0; s < a.ks[d]; ++s) v += p[(int64_t)s * a.MN[d]];
-  return v;
+  return a.C[d][(int64_t)row * a.N[d] + col];
 }
 
+// One wave per entry of the block column: lane t forms the product of term t
+// (t < T), lane T the kinetic combination, lane T+1 the mass product; a
+// wave-wide sum then gives V (FP64 throughout).
 __global__ __launch_bounds__(256) void combine_periodic_kernel(CombineArgs a, int64_t total) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (idx >= total) return;
-  int m2 = a.m0 * a.m0;
-  int64_t kflat = idx / m2;
-  int e = (int)(idx - kflat * m2);
-  int mu = e / a.m0, nu = e - mu * a.m0;
-  int k3 = (int)(kflat % a.L[2]);
-  int k2 = (int)((kflat / a.L[2]) % a.L[1]);
-  int k1 = (int)(kflat / ((int64_t)a.L[2] * a.L[1]));
-  double V = 0.0;
-  for (int t = 0; t < a.T; ++t) {
-    double c1 = lookup(a, 0, t, mu, nu, k1);
-    double c2 = lookup(a, 1, t, mu, nu, k2);
-    double c3 = lookup(a, 2, t, mu, nu, k3);
-    V += c1 * c2 * c3;
+  const int m2 = a.m0 * a.m0;
+  const int64_t kflat = idx / m2;
+  const int e = (int)(idx - kflat * m2);
+  const int mu = e / a.m0, nu = e - mu * a.m0;
+  const int k3 = (int)(kflat % a.L[2]);
+  const int k2 = (int)((kflat / a.L[2]) % a.L[1]);
+  const int k1 = (int)(kflat / ((int64_t)a.L[2] * a.L[1]));
+  double V = 0.0, Tk = 0.0, Sk = 0.0;
+  for (int t = lane; t < a.T + 2; t += 64) {
+    if (t < a.T) {
+      V += lookup(a, 0, t, mu, nu, k1) * lookup(a, 1, t, mu, nu, k2) * lookup(a, 2, t, mu, nu, k3);
+    } else if (t == a.T) {
+      double D1 = lookup(a, 0, a.T, mu, nu, k1), M1 = lookup(a, 0, a.T + 1, mu, nu, k1);
+      double D2 = lookup(a, 1, a.T, mu, nu, k2), M2 = lookup(a, 1, a.T + 1, mu, nu, k2);
+      double D3 = lookup(a, 2, a.T, mu, nu, k3), M3 = lookup(a, 2, a.T + 1, mu, nu, k3);
+      Tk = 0.5 * (D1 * M2 * M3 + M1 * D2 * M3 + M1 * M2 * D3);
+    } else {
+      Sk = lookup(a, 0, a.T + 1, mu, nu, k1) * lookup(a, 1, a.T + 1, mu, nu, k2) *
+           lookup(a, 2, a.T + 1, mu, nu, k3);
+    }
   }
-  double D1 = lookup(a, 0, a.T, mu, nu, k1), M1 = lookup(a, 0, a.T + 1, mu, nu, k1);
-  double D2 = lookup(a, 1, a.T, mu, nu, k2), M2 = lookup(a, 1, a.T + 1, mu, nu, k2);
-  double D3 = lookup(a, 2, a.T, mu, nu, k3), M3 = lookup(a, 2, a.T + 1, mu, nu, k3);
-  double Tk = 0.5 * (D1 * M2 * M3 + M1 * D2 * M3 + M1 * M2 * D3);
-  a.H[idx] = Tk - V;
-  a.Sm[idx] = M1 * M2 * M3;
+  for (int o = 32; o > 0; o >>= 1) V += __shfl_xor(V, o);
+  const int tl = a.T % 64, sl = (a.T + 1) % 64;
+  Tk = __shfl(Tk, tl);
+  Sk = __shfl(Sk, sl);
+  if (lane == 0) {
+    a.H[idx] = Tk - V;
+    a.Sm[idx] = Sk;
+  }
 }
 
-// Optional HIP events recorded around the contraction launches of the next
+// Optional HIP events recorded around the contraction launch of the next
 // assembly calls of this thread (profiling hook for measured rooflines).
 thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
 
 struct Plan {
-  int M[3], N[3], ks[3], kchunk[3];
-  size_t part_off[3];  // byte offsets of the partial arrays in the workspace
+  int M[3], N[3], ks[3], kchunk[3], tiles_n[3], blocks[3];
+  size_t part_off[3], c_off[3];  // byte offsets in the workspace
   size_t bytes;
+  int total_blocks;
 };
 
 Plan make_plan(const Geometry& g) {
   Plan p;
   size_t off = 0;
+  int nblk = 0;
   for (int d = 0; d < 3; ++d) {
     p.M[d] = (int)((g.pot_terms + 2) * g.m0);
     p.N[d] = g.m0 * g.shifts[d];
     int64_t tiles = ceil_div(p.M[d], kBM) * ceil_div(p.N[d], kBN);
-    int64_t want = std::max<int64_t>(1, ceil_div(2048, tiles));
-    int64_t maxsplit = std::max<int64_t>(1, g.n[d] / 128);
+    // enough workgroups to cover the chip, at least two stages per chunk
+    int64_t want = std::max<int64_t>(1, ceil_div(512, tiles));
+    int64_t maxsplit = std::max<int64_t>(1, g.n[d] / (2 * kKT));
     int ks = (int)std::min(want, maxsplit);
     int kchunk = (int)(ceil_div(ceil_div(g.n[d], ks), kKT) * kKT);
     ks = (int)ceil_div(g.n[d], kchunk);
     p.ks[d] = ks;
     p.kchunk[d] = kchunk;
+    p.tiles_n[d] = (int)ceil_div(p.N[d], kBN);
+    p.blocks[d] = (int)(tiles * ks);
+    nblk += p.blocks[d];
     p.part_off[d] = off;
     off += align_up(sizeof(double) * (size_t)ks * p.M[d] * p.N[d], 256);
+    p.c_off[d] = off;
+    off += align_up(sizeof(double) * (size_t)p.M[d] * p.N[d], 256);
   }
+  p.total_blocks = nblk;
   p.bytes = off;
   return p;
 }
@@ -209,35 +278,52 @@ tl_status assemble_periodic(const Geometry& g, const double* G, const double* AG
     return TL_EWORKSPACE;
   }
   char* wsb = (char*)ws;
-  if (g_ev_start) TL_HIP(hipEventRecord(g_ev_start, stream));
+  ContractArgs a;
+  a.m0 = g.m0;
+  a.T = (int)g.pot_terms;
+  int begin = 0;
   for (int d = 0; d < 3; ++d) {
-    ContractArgs a;
-    a.G = G + g.basis_off[d];
-    a.AG = AG + g.basis_off[d];
-    a.SG = SG + g.basis_off[d];
-    a.P = P + g.pot_off[d];
-    a.out = (double*)(wsb + plan.part_off[d]);
-    a.n = g.n[d];
-    a.m0 = g.m0;
-    a.T = (int)g.pot_terms;
-    a.S = g.shifts[d];
-    a.cn = g.periodic[d] ? g.cell_nodes[d] : 0;
-    a.M = plan.M[d];
-    a.N = plan.N[d];
-    a.kchunk = plan.kchunk[d];
-    dim3 grid((unsigned)ceil_div(a.N, kBN), (unsigned)ceil_div(a.M, kBM), (unsigned)plan.ks[d]);
-    hipLaunchKernelGGL(contract_f64_kernel, grid, dim3(256), 0, stream, a);
-    TL_CHECK_LAUNCH();
+    DimArgs& p = a.d[d];
+    p.G = G + g.basis_off[d];
+    p.AG = AG + g.basis_off[d];
+    p.SG = SG + g.basis_off[d];
+    p.P = P + g.pot_off[d];
+    p.part = (double*)(wsb + plan.part_off[d]);
+    p.n = g.n[d];
+    p.S = g.shifts[d];
+    p.cn = g.periodic[d] ? g.cell_nodes[d] : 0;
+    p.M = plan.M[d];
+    p.N = plan.N[d];
+    p.kchunk = plan.kchunk[d];
+    p.ks = plan.ks[d];
+    p.tiles_n = plan.tiles_n[d];
+    p.block_begin = begin;
+    begin += plan.blocks[d];
   }
+  if (g_ev_start) TL_HIP(hipEventRecord(g_ev_start, stream));
+  hipLaunchKernelGGL(contract_f64_kernel, dim3((unsigned)plan.total_blocks), dim3(256), 0, stream,
+                     a);
+  TL_CHECK_LAUNCH();
   if (g_ev_stop) TL_HIP(hipEventRecord(g_ev_stop, stream));
+  ReduceArgs ra;
+  int64_t tot = 0;
+  for (int d = 0; d < 3; ++d) {
+    ra.part[d] = (const double*)(wsb + plan.part_off[d]);
+    ra.C[d] = (double*)(wsb + plan.c_off[d]);
+    ra.MN[d] = (int64_t)plan.M[d] * plan.N[d];
+    ra.ks[d] = plan.ks[d];
+    ra.begin[d] = tot;
+    tot += ra.MN[d];
+  }
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0,
+                     stream, ra, tot);
+  TL_CHECK_LAUNCH();
   CombineArgs c;
   for (int d = 0; d < 3; ++d) {
-    c.C[d] = (const double*)(wsb + plan.part_off[d]);
-    c.ks[d] = plan.ks[d];
+    c.C[d] = (const double*)(wsb + plan.c_off[d]);
     c.S[d] = g.shifts[d];
     c.L[d] = g.L[d];
     c.periodic[d] = g.periodic[d];
-    c.MN[d] = (int64_t)plan.M[d] * plan.N[d];
     c.N[d] = plan.N[d];
   }
   c.m0 = g.m0;
@@ -245,7 +331,7 @@ tl_status assemble_periodic(const Geometry& g, const double* G, const double* AG
   c.H = H;
   c.Sm = S;
   int64_t total = g.block_elems;
-  hipLaunchKernelGGL(combine_periodic_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0,
+  hipLaunchKernelGGL(combine_periodic_kernel, dim3((unsigned)ceil_div(total, 4)), dim3(256), 0,
                      stream, c, total);
   TL_CHECK_LAUNCH();
   return TL_OK;

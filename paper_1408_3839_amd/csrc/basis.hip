@@ -12,8 +12,12 @@ constexpr double kGaussTailExponent = 46.0;  // images within exp(-46) of the pe
 
 struct BasisArgs {
   FnParams fn[TL_MAX_M0];
-  double x0, h, period, box_origin0, box_a;
-  int n, periodic, rows, m0, box_dim;  // box_dim: rows are cells x functions
+  double x0[3], period[3];
+  int64_t begin[3];   // flat start of each dimension (rows * n elements each)
+  int64_t total;
+  int n[3], periodic[3], rows[3];
+  double h, box_origin0, box_a;
+  int m0;
 };
 
 __device__ inline double factor_value(double x, double A, int l, double alpha, double coef) {
@@ -24,41 +28,45 @@ __device__ inline double factor_value(double x, double A, int l, double alpha, d
 
 // g(x_i) for one row; on a torus the images A + j*P that can reach the
 // interval within the tail cutoff are summed.
-__device__ inline double sample(const BasisArgs& p, double A, int l, double alpha, double coef,
-                                int i) {
-  double x = p.x0 + p.h * (double)i;
-  if (!p.periodic) return factor_value(x, A, l, alpha, coef);
+__device__ inline double sample(double x0, double h, double period, int periodic, double A, int l,
+                                double alpha, double coef, int i) {
+  double x = x0 + h * (double)i;
+  if (!periodic) return factor_value(x, A, l, alpha, coef);
   double rcut = sqrt(kGaussTailExponent / alpha);
-  int J = (int)ceil(rcut / p.period) + 1;
+  int J = (int)ceil(rcut / period) + 1;
   double acc = 0.0;
-  for (int j = -J; j <= J; ++j) acc += factor_value(x, A + (double)j * p.period, l, alpha, coef);
+  for (int j = -J; j <= J; ++j) acc += factor_value(x, A + (double)j * period, l, alpha, coef);
   return acc;
 }
 
+// One launch for the three dimensions, thread per (row, node).
 __global__ __launch_bounds__(256) void basis_kernel(BasisArgs p, double* __restrict__ G,
                                                     double* __restrict__ AG,
                                                     double* __restrict__ SG) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t total = (int64_t)p.rows * p.n;
-  if (idx >= total) return;
-  int row = (int)(idx / p.n);
-  int i = (int)(idx - (int64_t)row * p.n);
-  int mu = row % p.m0;
-  int cell = row / p.m0;
+  if (idx >= p.total) return;
+  const int dim = idx >= p.begin[2] ? 2 : (idx >= p.begin[1] ? 1 : 0);
+  const int64_t e = idx - p.begin[dim];
+  const int n = p.n[dim];
+  const int row = (int)(e / n);
+  const int i = (int)(e - (int64_t)row * n);
+  const int mu = row % p.m0;
+  const int cell = row / p.m0;
   const FnParams& f = p.fn[mu];
-  int dim = p.box_dim;  // the dimension index of this launch
   double A = f.center[dim];
-  if (p.rows > p.m0) A += p.box_origin0 + (double)cell * p.box_a;
-  int l = f.l[dim];
-  double alpha = f.alpha, coef = f.coef[dim];
-  double gi = sample(p, A, l, alpha, coef, i);
+  if (p.rows[dim] > p.m0) A += p.box_origin0 + (double)cell * p.box_a;
+  const int l = f.l[dim];
+  const double alpha = f.alpha, coef = f.coef[dim];
+  const double x0 = p.x0[dim], per = p.period[dim];
+  const int periodic = p.periodic[dim];
+  double gi = sample(x0, p.h, per, periodic, A, l, alpha, coef, i);
   double gl, gr;
-  if (p.periodic) {
-    gl = sample(p, A, l, alpha, coef, i == 0 ? p.n - 1 : i - 1);
-    gr = sample(p, A, l, alpha, coef, i == p.n - 1 ? 0 : i + 1);
+  if (periodic) {
+    gl = sample(x0, p.h, per, periodic, A, l, alpha, coef, i == 0 ? n - 1 : i - 1);
+    gr = sample(x0, p.h, per, periodic, A, l, alpha, coef, i == n - 1 ? 0 : i + 1);
   } else {
-    gl = i == 0 ? 0.0 : sample(p, A, l, alpha, coef, i - 1);
-    gr = i == p.n - 1 ? 0.0 : sample(p, A, l, alpha, coef, i + 1);
+    gl = i == 0 ? 0.0 : sample(x0, p.h, per, periodic, A, l, alpha, coef, i - 1);
+    gr = i == n - 1 ? 0.0 : sample(x0, p.h, per, periodic, A, l, alpha, coef, i + 1);
   }
   G[idx] = gi;
   AG[idx] = (2.0 * gi - gl - gr) / p.h;
@@ -84,18 +92,17 @@ tl_status build_basis(const Geometry& g, const tl_system* s, double* G, double* 
   p.box_origin0 = g.box_origin0;
   p.box_a = g.a[0];
   for (int d = 0; d < 3; ++d) {
-    p.x0 = g.x0[d];
-    p.n = g.n[d];
-    p.periodic = g.periodic[d];
-    p.period = g.periodic[d] ? g.L[d] * g.a[d] : 0.0;
-    p.rows = (int)g.basis_rows[d];
-    p.box_dim = d;
-    int64_t total = (int64_t)p.rows * p.n;
-    int blocks = (int)ceil_div(total, 256);
-    hipLaunchKernelGGL(basis_kernel, dim3(blocks), dim3(256), 0, stream, p, G + g.basis_off[d],
-                       AG + g.basis_off[d], SG + g.basis_off[d]);
-    TL_CHECK_LAUNCH();
+    p.x0[d] = g.x0[d];
+    p.n[d] = g.n[d];
+    p.periodic[d] = g.periodic[d];
+    p.period[d] = g.periodic[d] ? g.L[d] * g.a[d] : 0.0;
+    p.rows[d] = (int)g.basis_rows[d];
+    p.begin[d] = g.basis_off[d];
   }
+  p.total = g.basis_elems;
+  hipLaunchKernelGGL(basis_kernel, dim3((unsigned)ceil_div(p.total, 256)), dim3(256), 0, stream, p,
+                     G, AG, SG);
+  TL_CHECK_LAUNCH();
   return TL_OK;
 }
 

@@ -17,29 +17,49 @@ struct DftArgs {
   double* out;        // complex output
   int len;            // transform length along the axis
   int64_t inner;      // product of the extents after the axis, times m0*m0
-  int64_t total;      // number of output complex values
   int real_in;
 };
 
-// Thread per output value; consecutive threads carry consecutive block
-// entries, so loads are coalesced along the m0*m0 entries of each block.
+constexpr int kMaxTwiddle = 4096;  // lengths up to this keep their twiddles in LDS
+
+// Workgroup per (outer, j) output line segment: the twiddles w^(j k mod L)
+// of its j are tabulated once in LDS, threads run over consecutive block
+// entries r (coalesced loads along the m0*m0 entries).
+template <bool REAL_IN, bool TABLE>
 __global__ __launch_bounds__(256) void dft_axis_kernel(DftArgs a) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= a.total) return;
-  // decompose idx = ((outer * len) + j) * inner + r
-  int64_t r = idx % a.inner;
-  int64_t rest = idx / a.inner;
-  int j = (int)(rest % a.len);
-  int64_t outer = rest / a.len;
-  int64_t base = (outer * a.len) * a.inner + r;
-  double re = 0.0, im = 0.0;
-  int p = 0;  // (j * k) mod len
+  extern __shared__ double tw[];  // [len][2] (cos, sin)
+  const int64_t oj = blockIdx.x;  // outer * len + j
+  const int j = (int)(oj % a.len);
+  const int64_t outer = oj / a.len;
+  const int64_t r = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
   const double inv = 2.0 / (double)a.len;
+  if (TABLE) {
+    for (int k = threadIdx.x; k < a.len; k += blockDim.x) {
+      int p = (int)(((int64_t)j * k) % a.len);
+      double s, c;
+      sincospi((double)p * inv, &s, &c);  // w^p = cos(2 pi p/L) - i sin(2 pi p/L)
+      tw[2 * k] = c;
+      tw[2 * k + 1] = s;
+    }
+    __syncthreads();
+  }
+  if (r >= a.inner) return;
+  const int64_t base = outer * a.len * a.inner + r;
+  double re = 0.0, im = 0.0;
+  int p = 0;
+#pragma unroll 8
   for (int k = 0; k < a.len; ++k) {
     double s, c;
-    sincospi((double)p * inv, &s, &c);  // w^p = cos(2 pi p/L) - i sin(2 pi p/L)
+    if (TABLE) {
+      c = tw[2 * k];
+      s = tw[2 * k + 1];
+    } else {
+      sincospi((double)p * inv, &s, &c);
+      p += j;
+      if (p >= a.len) p -= a.len;
+    }
     int64_t src = base + (int64_t)k * a.inner;
-    if (a.real_in) {
+    if (REAL_IN) {
       double x = a.in[src];
       re += c * x;
       im -= s * x;
@@ -48,11 +68,26 @@ __global__ __launch_bounds__(256) void dft_axis_kernel(DftArgs a) {
       re += c * xr + s * xi;
       im += c * xi - s * xr;
     }
-    p += j;
-    if (p >= a.len) p -= a.len;
   }
-  a.out[2 * idx] = re;
-  a.out[2 * idx + 1] = im;
+  const int64_t o = (outer * a.len + j) * a.inner + r;
+  a.out[2 * o] = re;
+  a.out[2 * o + 1] = im;
+}
+
+tl_status launch_axis(const DftArgs& a, int64_t outer, hipStream_t stream) {
+  dim3 grid((unsigned)(outer * a.len), (unsigned)ceil_div(a.inner, 256));
+  const bool table = a.len <= kMaxTwiddle;
+  size_t shmem = table ? sizeof(double) * 2 * (size_t)a.len : 0;
+  if (a.real_in && table)
+    hipLaunchKernelGGL((dft_axis_kernel<true, true>), grid, dim3(256), shmem, stream, a);
+  else if (a.real_in)
+    hipLaunchKernelGGL((dft_axis_kernel<true, false>), grid, dim3(256), shmem, stream, a);
+  else if (table)
+    hipLaunchKernelGGL((dft_axis_kernel<false, true>), grid, dim3(256), shmem, stream, a);
+  else
+    hipLaunchKernelGGL((dft_axis_kernel<false, false>), grid, dim3(256), shmem, stream, a);
+  TL_CHECK_LAUNCH();
+  return TL_OK;
 }
 
 }  // namespace
@@ -72,11 +107,8 @@ tl_status block_fft(const double* in, int L1, int L2, int L3, int m0, int batch,
   }
   double* tmp = (double*)ws;
   if (na == 0) {  // one cell: the block is its own transform (imaginary part 0)
-    DftArgs a{in, out, 1, E, total, 1};
-    hipLaunchKernelGGL(dft_axis_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream,
-                       a);
-    TL_CHECK_LAUNCH();
-    return TL_OK;
+    DftArgs a{in, out, 1, E, 1};
+    return launch_axis(a, batch, stream);
   }
   // pass 0 reads `in`, the last pass writes `out`: in->out (one axis),
   // in->tmp->out (two axes), in->out->tmp->out (three axes).
@@ -85,13 +117,12 @@ tl_status block_fft(const double* in, int L1, int L2, int L3, int m0, int batch,
     int d = axes[p];
     int64_t inner = E;
     for (int e = d + 1; e < 3; ++e) inner *= L[e];
+    int64_t outer = total / (inner * L[d]);
     double* dst = out;
     if (na == 2 && p == 0) dst = tmp;
     if (na == 3 && p == 1) dst = tmp;
-    DftArgs a{src, dst, L[d], inner, total, p == 0};
-    hipLaunchKernelGGL(dft_axis_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream,
-                       a);
-    TL_CHECK_LAUNCH();
+    DftArgs a{src, dst, L[d], inner, p == 0};
+    TL_TRY(launch_axis(a, outer, stream));
     src = dst;
   }
   return TL_OK;

@@ -28,6 +28,63 @@ __device__ inline double cabs2(cx a) { return a.re * a.re + a.im * a.im; }
 
 constexpr int kMaxSweeps = 60;
 
+// Partner of index x in round r of the round-robin ordering of `me` (even)
+// indices: me-1 meets r, every other pair {r+k, r-k} (mod me-1).
+__device__ inline int rr_partner(int x, int r, int me) {
+  const int n1 = me - 1;
+  if (x == n1) return r;
+  if (x == r) return n1;
+  int y = (2 * r - x) % n1;
+  return y < 0 ? y + n1 : y;
+}
+
+struct Rot {
+  double c, s, tb;  // cos, sin, t*|b| (shift of the diagonal)
+  cx ph;            // exp(-i phi), b = |b| exp(i phi)
+  bool active;
+};
+
+// Jacobi rotation zeroing A[p][q] of the Hermitian 2x2 [[a, b], [conj b, d]]
+// (Golub & Van Loan, sym.schur2, after removing the phase of b).
+__device__ inline Rot make_rot(const cx* A, int LD, int p, int q, int m) {
+  Rot r;
+  r.active = false;
+  r.c = 1.0;
+  r.s = 0.0;
+  r.tb = 0.0;
+  r.ph = {1.0, 0.0};
+  if (q >= m) return r;
+  double a = A[p * LD + p].re, d = A[q * LD + q].re;
+  cx b = A[p * LD + q];
+  double ab = sqrt(cabs2(b));
+  if (!(ab > 0.0)) return r;
+  double tau = (d - a) / (2.0 * ab);
+  double t = fabs(tau) > 1e150 ? 0.5 / tau
+                               : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  r.c = 1.0 / sqrt(1.0 + t * t);
+  r.s = t * r.c;
+  r.tb = t * ab;
+  r.ph = cscale(cconj(b), 1.0 / ab);
+  r.active = true;
+  return r;
+}
+
+// Column x of the rotation J (rows x and its partner xp), J = D R with
+// D = diag(1, exp(-i phi)) on (p, q): J[p][p] = c, J[q][p] = -s e^{-i phi},
+// J[p][q] = s, J[q][q] = c e^{-i phi}.
+__device__ inline void rot_column(const Rot& r, bool first, cx& Jxx, cx& Jpx) {
+  if (!r.active) {
+    Jxx = {1.0, 0.0};
+    Jpx = {0.0, 0.0};
+  } else if (first) {
+    Jxx = {r.c, 0.0};
+    Jpx = cscale(r.ph, -r.s);
+  } else {
+    Jxx = cscale(r.ph, r.c);
+    Jpx = {r.s, 0.0};
+  }
+}
+
 template <int MAXM>
 __global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ H,
                                                      const double* __restrict__ S, int m,
@@ -35,14 +92,13 @@ __global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ 
                                                      double* __restrict__ evecs,
                                                      int* __restrict__ info) {
   constexpr int LD = MAXM + 1;
-  constexpr int NP = MAXM / 2 + 1;
-  __shared__ cx A[MAXM * LD];  // Hbar -> C -> eigenvalues on the diagonal
-  __shared__ cx B[MAXM * LD];  // Sbar -> Cholesky factor L
-  __shared__ cx V[MAXM * LD];  // scratch, then the Jacobi eigenvectors
-  __shared__ double rc[NP], rs[NP], rtb[NP];
-  __shared__ cx rph[NP];
-  __shared__ int ract[NP];
-  __shared__ int partner[MAXM + 2], pid[MAXM + 2], first[MAXM + 2];
+  // two copies of C and of V so that a Jacobi round needs one barrier
+  // (read one copy, write the other); L is the Cholesky factor.
+  constexpr bool kDouble = MAXM <= 16;
+  constexpr int NB = kDouble ? 2 : 1;
+  __shared__ cx Ab[NB][MAXM * LD];
+  __shared__ cx Vb[NB][MAXM * LD];
+  __shared__ cx B[MAXM * LD];
   __shared__ int rank_of[MAXM];
   __shared__ int fail;
   __shared__ double red[2];
@@ -53,6 +109,8 @@ __global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ 
   const int mm = m * m;
   const cx* Hb = (const cx*)H + blk * mm;
   const cx* Sb = S ? (const cx*)S + blk * mm : nullptr;
+  cx* A = Ab[0];
+  cx* V = Vb[0];
 
   for (int e = tid; e < mm; e += nt) {
     int i = e / m, j = e - i * m;
@@ -88,9 +146,7 @@ __global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ 
   if (fail) {
     for (int i = tid; i < m; i += nt) evals[blk * m + i] = NAN;
     if (evecs)
-      for (int e = tid; e < mm; e += nt) {
-        ((cx*)evecs)[blk * mm + e] = {0.0, 0.0};
-      }
+      for (int e = tid; e < mm; e += nt) ((cx*)evecs)[blk * mm + e] = {0.0, 0.0};
     if (tid == 0) info[blk] = fail;
     return;
   }
@@ -143,8 +199,10 @@ __global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ 
     __syncthreads();
   }
 
-  // 3. Jacobi sweeps, round-robin pairing of the (even-padded) indices.
+  // 3. Jacobi sweeps, round-robin pairing of the (even-padded) indices.  Every
+  // thread forms the rotations of its row pair and column pair itself.
   int converged = (m == 1);
+  int cur = 0;
   const int me = m + (m & 1);
   for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
     // convergence: off-diagonal Frobenius norm against the whole norm
@@ -169,106 +227,50 @@ __global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ 
       converged = 1;
       break;
     }
-    __syncthreads();
     for (int r = 0; r < me - 1; ++r) {
-      for (int pk = tid; pk < me / 2; pk += nt) {
-        int p, q;
-        if (pk == 0) {
-          p = me - 1;
-          q = r;
-        } else {
-          p = (r + pk) % (me - 1);
-          q = (r - pk + me - 1) % (me - 1);
-        }
-        if (p > q) {
-          int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        partner[p] = q;
-        partner[q] = p;
-        first[p] = 1;
-        first[q] = 0;
-        pid[p] = pk;
-        pid[q] = pk;
-        int act = 0;
-        if (q < m) {
-          double a = A[p * LD + p].re, d = A[q * LD + q].re;
-          cx b = A[p * LD + q];
-          double ab = sqrt(cabs2(b));
-          if (ab > 0.0) {
-            double tau = (d - a) / (2.0 * ab);
-            double t;
-            if (fabs(tau) > 1e150)
-              t = 0.5 / tau;
-            else
-              t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            double c = 1.0 / sqrt(1.0 + t * t);
-            rc[pk] = c;
-            rs[pk] = t * c;
-            rtb[pk] = t * ab;
-            rph[pk] = cscale(cconj(b), 1.0 / ab);  // exp(-i phi), b = |b| exp(i phi)
-            act = 1;
-          }
-        }
-        ract[pk] = act;
-      }
-      __syncthreads();
-      // new entry of this thread in registers, then written back
       cx na = {0.0, 0.0}, nv = {0.0, 0.0};
       if (owner) {
         const int i = ei, j = ej;
-        // column i of J: diagonal entry Jii and the partner entry Jpi (row partner(i))
-        int pi = pid[i], pj = pid[j];
-        int ai = ract[pi], aj = ract[pj];
-        int ip = partner[i], jp = partner[j];
-        cx Jii = {1.0, 0.0}, Jpi = {0.0, 0.0}, Jjj = {1.0, 0.0}, Jpj = {0.0, 0.0};
-        if (ai) {
-          double cc = rc[pi], ss = rs[pi];
-          cx ph = rph[pi];
-          if (first[i]) {
-            Jii = {cc, 0.0};
-            Jpi = cscale(ph, -ss);
-          } else {
-            Jii = cscale(ph, cc);
-            Jpi = {ss, 0.0};
-          }
-        }
-        if (aj) {
-          double cc = rc[pj], ss = rs[pj];
-          cx ph = rph[pj];
-          if (first[j]) {
-            Jjj = {cc, 0.0};
-            Jpj = cscale(ph, -ss);
-          } else {
-            Jjj = cscale(ph, cc);
-            Jpj = {ss, 0.0};
-          }
-        }
-        if (ai && pi == pj) {
+        const int ip = rr_partner(i, r, me), jp = rr_partner(j, r, me);
+        const Rot ri = make_rot(A, LD, min(i, ip), max(i, ip), m);
+        const Rot rj = make_rot(A, LD, min(j, jp), max(j, jp), m);
+        cx Jii, Jpi, Jjj, Jpj;
+        rot_column(ri, i < ip, Jii, Jpi);
+        rot_column(rj, j < jp, Jjj, Jpj);
+        if (ri.active && (j == i || j == ip)) {
           // inside one rotated 2x2 block: exact diagonal form
-          if (i == j)
-            na = {A[i * LD + i].re + (first[i] ? -rtb[pi] : rtb[pi]), 0.0};
+          if (i == j) na = {A[i * LD + i].re + (i < ip ? -ri.tb : ri.tb), 0.0};
         } else {
           // sum over a in {i, ip}, b in {j, jp} of conj(J[a][i]) A[a][b] J[b][j]
           cx t0 = cmul(A[i * LD + j], Jjj);
-          if (aj) t0 = cadd(t0, cmul(A[i * LD + jp], Jpj));
+          if (rj.active) t0 = cadd(t0, cmul(A[i * LD + jp], Jpj));
           na = cmul(cconj(Jii), t0);
-          if (ai) {
+          if (ri.active) {
             cx t1 = cmul(A[ip * LD + j], Jjj);
-            if (aj) t1 = cadd(t1, cmul(A[ip * LD + jp], Jpj));
+            if (rj.active) t1 = cadd(t1, cmul(A[ip * LD + jp], Jpj));
             na = cadd(na, cmul(cconj(Jpi), t1));
           }
         }
         nv = cmul(V[i * LD + j], Jjj);
-        if (aj) nv = cadd(nv, cmul(V[i * LD + jp], Jpj));
+        if (rj.active) nv = cadd(nv, cmul(V[i * LD + jp], Jpj));
       }
-      __syncthreads();
-      if (owner) {
-        A[ei * LD + ej] = na;
-        V[ei * LD + ej] = nv;
+      if (kDouble) {
+        cur ^= 1;
+        A = Ab[cur];
+        V = Vb[cur];
+        if (owner) {
+          A[ei * LD + ej] = na;
+          V[ei * LD + ej] = nv;
+        }
+        __syncthreads();
+      } else {
+        __syncthreads();
+        if (owner) {
+          A[ei * LD + ej] = na;
+          V[ei * LD + ej] = nv;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
 

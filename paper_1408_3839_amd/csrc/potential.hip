@@ -64,68 +64,124 @@ struct QuadArgs {  // the exponential-sum table, passed by value
   double w[TL_MAX_R];
 };
 
-// ---- a2: master vectors b~_q[j], j = -J..J
-__global__ __launch_bounds__(256) void master_kernel(QuadArgs quad, int R, int J, double h,
-                                                     double* __restrict__ master) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t width = 2 * (int64_t)J + 1;
-  if (idx >= (int64_t)R * width) return;
-  int q = (int)(idx / width);
-  int j = (int)(idx - (int64_t)q * width) - J;
-  master[idx] = cell_int(quad.t[q], (double)j * h, h, 0.0);
+// ---- a2 + open transverse dims in one launch.
+// Blocks [0, master_blocks): master vectors b~_q[j], j = -J..J.
+// Blocks after that: the y / z factors of open dims (one per group and
+// term), b_q(x_i; y_g), which need no lattice sum.
+struct DirectArgs {
+  int R, J, master_blocks;
+  double h;
+  // open transverse dims (y = 1, z = 2)
+  int n_open;                 // number of open transverse dims handled here (0..2)
+  int open_dim[2];
+  int n[2];
+  double x0[2];
+  int64_t out_off[2];         // element offset of the dim in P
+  int blocks_per_term[2];
+  int T;                      // terms = groups * R
+  double gpos[2][TL_MAX_SITES];  // group coordinate on each open dim
+};
+
+__global__ __launch_bounds__(256) void direct_kernel(DirectArgs a, QuadArgs quad,
+                                                     double* __restrict__ master,
+                                                     double* __restrict__ P) {
+  int b = blockIdx.x;
+  if (b < a.master_blocks) {
+    int64_t idx = (int64_t)b * blockDim.x + threadIdx.x;
+    int64_t width = 2 * (int64_t)a.J + 1;
+    if (idx >= (int64_t)a.R * width) return;
+    int q = (int)(idx / width);
+    int j = (int)(idx - (int64_t)q * width) - a.J;
+    master[idx] = cell_int(quad.t[q], (double)j * a.h, a.h, 0.0);
+    return;
+  }
+  b -= a.master_blocks;
+  int od = 0;
+  int span0 = a.T * a.blocks_per_term[0];
+  if (a.n_open == 2 && b >= span0) {
+    od = 1;
+    b -= span0;
+  }
+  int t = b / a.blocks_per_term[od];
+  int chunk = b - t * a.blocks_per_term[od];
+  int i = chunk * blockDim.x + threadIdx.x;
+  if (i >= a.n[od]) return;
+  int g = t / a.R, q = t - g * a.R;
+  double x = a.x0[od] + a.h * (double)i;
+  P[a.out_off[od] + (int64_t)t * a.n[od] + i] = cell_int(quad.t[q], x, a.h, a.gpos[od][g]);
 }
 
 struct FoldArgs {
   int n_sites;
   int site_group[TL_MAX_SITES];
-  int site_off[TL_MAX_SITES];   // site offset on this dim, in nodes
+  int site_off[3][TL_MAX_SITES];   // site offset per dim, in nodes
   double site_Z[TL_MAX_SITES];
-  int group_off[TL_MAX_SITES];  // representative offset of each group on this dim
-  int dim, R, c, K, J, n;
+  int group_off[3][TL_MAX_SITES];  // representative offset of each group per dim
+  int dims[3];                     // periodic dims handled by this launch
+  int c[3], K[3], n[3];
+  int64_t out_off[3];
+  int R, J;
 };
 
-// ---- a3 (torus dims): one workgroup per term t = g*R + q; window values in
-// LDS, then the replicated vector is streamed out.
+// ---- a3 (torus dims): workgroup per (term, periodic dim).  Threads split the
+// image sum of every window node, partial sums meet in LDS, the window is
+// then replicated over the torus.
 __global__ __launch_bounds__(256) void fold_kernel(FoldArgs p, QuadArgs quad,
                                                    const double* __restrict__ master,
                                                    double* __restrict__ P) {
-  extern __shared__ double win[];
-  int t = blockIdx.x;
-  int g = t / p.R;
-  int q = t - g * p.R;
+  extern __shared__ double sh[];  // win[c] then part[256]
+  const int slot = blockIdx.y;
+  const int dim = p.dims[slot];
+  const int c = p.c[slot], K = p.K[slot], n = p.n[slot];
+  double* win = sh;
+  double* part = sh + c;
+  const int t = blockIdx.x;
+  const int g = t / p.R;
+  const int q = t - g * p.R;
   const double* mq = master + (int64_t)q * (2 * p.J + 1) + p.J;  // mq[j], j in [-J, J]
-  int half = p.c / 2;
-  for (int r = threadIdx.x; r < p.c; r += blockDim.x) {
-    int rr = r - half;  // node offset from the cell origin
+  const int half = c / 2;
+  const int tid = threadIdx.x;
+  auto image_sum = [&](int rr, int k_first, int k_step) {
     double acc = 0.0;
-    if (p.dim == 0) {
-      for (int s = 0; s < p.n_sites; ++s) {
-        if (p.site_group[s] != g) continue;
-        double part = 0.0;
-        for (int k = -p.K; k <= p.K; ++k) part += mq[rr - p.site_off[s] - k * p.c];
-        acc += p.site_Z[s] * part;
+    for (int k = -K + k_first; k <= K; k += k_step) {
+      if (dim == 0) {
+        for (int s = 0; s < p.n_sites; ++s)
+          if (p.site_group[s] == g) acc += p.site_Z[s] * mq[rr - p.site_off[0][s] - k * c];
+      } else {
+        acc += mq[rr - p.group_off[dim][g] - k * c];
       }
-      acc *= quad.w[q];
-    } else {
-      for (int k = -p.K; k <= p.K; ++k) acc += mq[rr - p.group_off[g] - k * p.c];
     }
-    win[r] = acc;
+    return acc;
+  };
+  const double wscale = dim == 0 ? quad.w[q] : 1.0;
+  if (c <= 256) {
+    const int np = 256 / c;
+    if (tid < np * c) part[tid] = image_sum(tid % c - half, tid / c, np);
+    __syncthreads();
+    if (tid < c) {
+      double v = 0.0;
+      for (int s2 = 0; s2 < np; ++s2) v += part[tid + s2 * c];
+      win[tid] = v * wscale;
+    }
+  } else {
+    for (int r = tid; r < c; r += blockDim.x) win[r] = image_sum(r - half, 0, 1) * wscale;
   }
   __syncthreads();
-  double* out = P + (int64_t)t * p.n;
-  for (int i = threadIdx.x; i < p.n; i += blockDim.x) out[i] = win[(i + half) % p.c];
+  double* out = P + p.out_off[slot] + (int64_t)t * n;
+  for (int i = tid; i < n; i += blockDim.x) out[i] = win[(i + half) % c];
 }
 
 constexpr int kNucChunk = 80;
 struct BoxArgs {
-  double pos[kNucChunk];  // nucleus coordinate on this dim (dim 0) or group coordinate
+  double pos[kNucChunk];  // nucleus x coordinate
   double Z[kNucChunk];
   int group[kNucChunk];
-  int count, dim, R, n, accumulate;
+  int count, R, n, accumulate;
   double x0, h;
 };
 
-// ---- a3 (open dims): thread per (term, node), direct cell integrals.
+// ---- a3 (open dim 0, box mode): thread per (term, node), direct cell
+// integrals of every nucleus of the chunk.
 __global__ __launch_bounds__(256) void box_potential_kernel(BoxArgs p, QuadArgs quad,
                                                             double* __restrict__ P) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,7 +196,7 @@ __global__ __launch_bounds__(256) void box_potential_kernel(BoxArgs p, QuadArgs 
     if (p.group[s] != g) continue;
     acc += p.Z[s] * cell_int(tt, x, p.h, p.pos[s]);
   }
-  if (p.dim == 0) acc *= quad.w[q];
+  acc *= quad.w[q];
   double* out = P + (int64_t)t * p.n + idx;
   if (p.accumulate)
     *out += acc;
@@ -209,74 +265,94 @@ tl_status lattice_sum_potential(const Geometry& g, const tl_system* s, double* P
   }
   GroupInfo gi = make_groups(s);
   int J = master_half_width(g, s);
-  if (J > 0) {
-    int64_t total = (int64_t)g.R * (2 * J + 1);
-    hipLaunchKernelGGL(master_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream,
-                       quad, g.R, J, g.h, master);
-    TL_CHECK_LAUNCH();
+  const int T = (int)g.pot_terms;
+  // launch 1: master vectors + open transverse dims
+  {
+    DirectArgs da;
+    std::memset(&da, 0, sizeof(da));
+    da.R = g.R;
+    da.J = J;
+    da.h = g.h;
+    da.T = T;
+    da.master_blocks = J > 0 ? (int)ceil_div((int64_t)g.R * (2 * J + 1), 256) : 0;
+    int total_blocks = da.master_blocks;
+    for (int d = 1; d < 3; ++d) {
+      if (g.periodic[d]) continue;
+      int od = da.n_open++;
+      da.open_dim[od] = d;
+      da.n[od] = g.n[d];
+      da.x0[od] = g.x0[d];
+      da.out_off[od] = g.pot_off[d];
+      da.blocks_per_term[od] = (int)ceil_div(g.n[d], 256);
+      for (int gr = 0; gr < g.n_groups; ++gr) da.gpos[od][gr] = d == 1 ? gi.y[gr] : gi.z[gr];
+      total_blocks += T * da.blocks_per_term[od];
+    }
+    if (total_blocks > 0) {
+      hipLaunchKernelGGL(direct_kernel, dim3((unsigned)total_blocks), dim3(256), 0, stream, da,
+                         quad, master, P);
+      TL_CHECK_LAUNCH();
+    }
   }
-  for (int d = 0; d < 3; ++d) {
-    double* Pd = P + g.pot_off[d];
-    if (g.periodic[d]) {
-      FoldArgs fa;
-      std::memset(&fa, 0, sizeof(fa));
-      fa.n_sites = s->n_nuc;
-      for (int nu = 0; nu < s->n_nuc; ++nu) {
-        fa.site_group[nu] = gi.of_nucleus[nu];
-        fa.site_off[nu] = (int)std::lround(s->nuc_pos[3 * nu + d] / g.h);
-        fa.site_Z[nu] = s->nuc_Z[nu];
-      }
-      for (int gr = 0; gr < g.n_groups; ++gr) {
-        double c = d == 1 ? gi.y[gr] : (d == 2 ? gi.z[gr] : 0.0);
-        fa.group_off[gr] = (int)std::lround(c / g.h);
-      }
-      fa.dim = d;
-      fa.R = g.R;
-      fa.c = g.cell_nodes[d];
-      fa.K = g.K[d];
-      fa.J = J;
-      fa.n = g.n[d];
-      size_t shmem = sizeof(double) * (size_t)fa.c;
+  // launch 2: lattice sums of every torus dim
+  {
+    FoldArgs fa;
+    std::memset(&fa, 0, sizeof(fa));
+    fa.n_sites = s->n_nuc;
+    fa.R = g.R;
+    fa.J = J;
+    for (int nu = 0; nu < s->n_nuc; ++nu) {
+      fa.site_group[nu] = gi.of_nucleus[nu];
+      fa.site_Z[nu] = s->nuc_Z[nu];
+      for (int d = 0; d < 3; ++d)
+        fa.site_off[d][nu] = (int)std::lround(s->nuc_pos[3 * nu + d] / g.h);
+    }
+    for (int gr = 0; gr < g.n_groups; ++gr) {
+      fa.group_off[1][gr] = (int)std::lround(gi.y[gr] / g.h);
+      fa.group_off[2][gr] = (int)std::lround(gi.z[gr] / g.h);
+    }
+    int slots = 0;
+    int cmax = 0;
+    for (int d = 0; d < 3; ++d) {
+      if (!g.periodic[d]) continue;
+      fa.dims[slots] = d;
+      fa.c[slots] = g.cell_nodes[d];
+      fa.K[slots] = g.K[d];
+      fa.n[slots] = g.n[d];
+      fa.out_off[slots] = g.pot_off[d];
+      cmax = std::max(cmax, g.cell_nodes[d]);
+      ++slots;
+    }
+    if (slots > 0) {
+      size_t shmem = sizeof(double) * ((size_t)cmax + 256);
       if (shmem > 64 * 1024) {
-        set_error("cell of %d nodes exceeds the LDS window", fa.c);
+        set_error("cell of %d nodes exceeds the LDS window", cmax);
         return TL_EUNSUPPORTED;
       }
-      hipLaunchKernelGGL(fold_kernel, dim3((unsigned)g.pot_terms), dim3(256), shmem, stream, fa,
-                         quad, master, Pd);
+      hipLaunchKernelGGL(fold_kernel, dim3((unsigned)T, (unsigned)slots), dim3(256), shmem, stream,
+                         fa, quad, master, P);
       TL_CHECK_LAUNCH();
-    } else {
-      BoxArgs ba;
-      std::memset(&ba, 0, sizeof(ba));
-      ba.dim = d;
-      ba.R = g.R;
-      ba.n = g.n[d];
-      ba.x0 = g.x0[d];
-      ba.h = g.h;
-      dim3 grid((unsigned)ceil_div(g.n[d], 256), (unsigned)g.pot_terms);
-      if (d == 0) {
-        for (int start = 0; start < s->n_nuc; start += kNucChunk) {
-          int cnt = std::min(kNucChunk, s->n_nuc - start);
-          ba.count = cnt;
-          ba.accumulate = start > 0;
-          for (int k = 0; k < cnt; ++k) {
-            ba.pos[k] = s->nuc_pos[3 * (start + k)];
-            ba.Z[k] = s->nuc_Z[start + k];
-            ba.group[k] = gi.of_nucleus[start + k];
-          }
-          hipLaunchKernelGGL(box_potential_kernel, grid, dim3(256), 0, stream, ba, quad, Pd);
-          TL_CHECK_LAUNCH();
-        }
-      } else {
-        ba.count = g.n_groups;
-        ba.accumulate = 0;
-        for (int gr = 0; gr < g.n_groups; ++gr) {
-          ba.pos[gr] = d == 1 ? gi.y[gr] : gi.z[gr];
-          ba.Z[gr] = 1.0;
-          ba.group[gr] = gr;
-        }
-        hipLaunchKernelGGL(box_potential_kernel, grid, dim3(256), 0, stream, ba, quad, Pd);
-        TL_CHECK_LAUNCH();
+    }
+  }
+  // box mode: dim 0 sums every nucleus directly, in chunks
+  if (!g.periodic[0]) {
+    BoxArgs ba;
+    std::memset(&ba, 0, sizeof(ba));
+    ba.R = g.R;
+    ba.n = g.n[0];
+    ba.x0 = g.x0[0];
+    ba.h = g.h;
+    dim3 grid((unsigned)ceil_div(g.n[0], 256), (unsigned)T);
+    for (int start = 0; start < s->n_nuc; start += kNucChunk) {
+      int cnt = std::min(kNucChunk, s->n_nuc - start);
+      ba.count = cnt;
+      ba.accumulate = start > 0;
+      for (int k = 0; k < cnt; ++k) {
+        ba.pos[k] = s->nuc_pos[3 * (start + k)];
+        ba.Z[k] = s->nuc_Z[start + k];
+        ba.group[k] = gi.of_nucleus[start + k];
       }
+      hipLaunchKernelGGL(box_potential_kernel, grid, dim3(256), 0, stream, ba, quad, P);
+      TL_CHECK_LAUNCH();
     }
   }
   return TL_OK;

@@ -82,3 +82,20 @@ class PeriodicPipeline:
         self.block_fft(stream)
         self.heigh(stream)
         return self.evals
+
+    def capture(self):
+        """Capture one whole run() into a HIP graph (every launch of the path,
+        no allocation, no memset); replay() then re-executes all of it."""
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            self.run()
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+        return self.evals

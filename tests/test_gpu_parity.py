@@ -112,9 +112,15 @@ def test_assembly_parity(name):
     H = pl.H.cpu().numpy()
     S = pl.S.cpu().numpy()
     Hr, Sr, scale = oracle.core_hamiltonian_blocks(sys)
-    eh = np.abs(H - Hr) / scale
+    # entries whose every product underflows are exactly 0 on both sides
+    assert np.all(H[scale == 0] == 0) and np.all(S[scale == 0] == 0)
+    # FP64 MFMA flushes denormal products: entries below 1e-290 are compared
+    # absolutely, everything else relative to its no-cancellation magnitude
+    eh = np.abs(H - Hr) / np.where(scale > 0, scale, 1.0)
     es = np.abs(S - Sr) / np.maximum(np.abs(Sr), 1e-300)
-    assert eh.max() <= 1e-10, (name, float(eh.max()))
+    bad = (np.abs(H - Hr) > 1e-10 * scale + 1e-290)
+    w = np.unravel_index(np.argmax(eh), eh.shape)
+    assert not bad.any(), (name, float(eh.max()), w, float(Hr[w]), float(H[w]), float(scale[w]))
     assert np.all(np.abs(S - Sr) <= 1e-10 * np.abs(Sr) + 1e-14 * np.abs(Sr).max()), \
         (name, float(es.max()))
 
@@ -243,3 +249,26 @@ def test_end_to_end_eigenvalues(name):
         lam, U = sla.eigh(Hf[j], Sf[j])
         tol = _eig_tol(Hf[j], Sf[j], lam, U)
         assert np.all(np.abs(ev[j] - lam) <= tol), (name, j, ev[j] - lam, tol)
+
+
+def test_graph_replay_matches_eager():
+    """The whole path captured in a HIP graph: every replay, with eager work
+    and synchronisations in between, reproduces the eager result bit for bit."""
+    sys = wl.config(2)
+    pl = _pipeline(sys)
+    pl.run()
+    torch.cuda.synchronize()
+    H0 = pl.H.clone()
+    ev0 = pl.evals.clone()
+    pl.capture()
+    for rep in range(3):
+        pl.HS.fill_(0.0)
+        pl.evals.fill_(0.0)
+        torch.cuda.synchronize()
+        pl.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(pl.H, H0), rep
+        assert torch.equal(pl.evals, ev0), rep
+        pl.run()            # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(pl.evals, ev0), rep
