@@ -49,22 +49,6 @@ struct ContractArgs {
   int m0, T;
 };
 
-// X[(t, nu)][i] for one staged element (0 outside the matrix / chunk).
-__device__ inline double x_value(const DimArgs& p, int m0, int T, int row, int i) {
-  int t = row / m0, nu = row - t * m0;
-  int64_t gi = (int64_t)nu * p.n + i;
-  if (t < T) return p.P[(int64_t)t * p.n + i] * p.G[gi];
-  return t == T ? p.AG[gi] : p.SG[gi];
-}
-
-// Y[(mu, s)][i] = g_mu(x_{i - s c}) (cyclic).
-__device__ inline double y_value(const DimArgs& p, int col, int i) {
-  int mu = col / p.S, s = col - mu * p.S;
-  int src = i - s * p.cn;
-  if (src < 0) src += p.n;
-  return p.G[(int64_t)mu * p.n + src];
-}
-
 // One launch for the three dimensions.  Workgroup = 4 waves = a 32 x 32 tile
 // of C_l over one chunk of nodes; each wave owns a 16 x 16 block and issues
 // V_MFMA_F64_16X16X4_F64 from LDS.  The next 64-node stage is loaded into
@@ -87,26 +71,50 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(ContractArgs a) {
   const int kend = min(p.n, kbeg + p.kchunk);
   const int wm = wave >> 1, wn = wave & 1;
   double xr[kPerThread], yr[kPerThread];
+  // the rows and columns a thread stages are the same in every stage:
+  // resolve (term, nu) and (mu, shift) once
+  const double* xa[kPerThread];   // P row of the term (or null)
+  const double* xb[kPerThread];   // G, AG or SG row of nu
+  const double* yb[kPerThread];   // G row of mu
+  int ysh[kPerThread];
+  bool xok[kPerThread], yok[kPerThread];
+#pragma unroll
+  for (int j = 0; j < kPerThread; ++j) {
+    const int r = (tid + 256 * j) / kKT;
+    const int row = row0 + r, col = col0 + r;
+    xok[j] = row < p.M;
+    yok[j] = col < p.N;
+    const int t = xok[j] ? row / a.m0 : 0, nu = xok[j] ? row - t * a.m0 : 0;
+    xa[j] = t < a.T ? p.P + (int64_t)t * p.n : nullptr;
+    xb[j] = (t < a.T ? p.G : (t == a.T ? p.AG : p.SG)) + (int64_t)nu * p.n;
+    const int mu = yok[j] ? col / p.S : 0, sh = yok[j] ? col - mu * p.S : 0;
+    yb[j] = p.G + (int64_t)mu * p.n;
+    ysh[j] = sh * p.cn;
+  }
 
   auto stage = [&](int k0) {
 #pragma unroll
     for (int j = 0; j < kPerThread; ++j) {
-      int e = tid + 256 * j;
-      int r = e / kKT, kk = e - r * kKT;
-      int i = k0 + kk;
-      bool in_k = i < kend;
-      int row = row0 + r, col = col0 + r;
-      xr[j] = (row < p.M && in_k) ? x_value(p, a.m0, a.T, row, i) : 0.0;
-      yr[j] = (col < p.N && in_k) ? y_value(p, col, i) : 0.0;
+      const int kk = (tid + 256 * j) & (kKT - 1);
+      const int i = k0 + kk;
+      const bool in_k = i < kend;
+      double xv = 0.0, yv = 0.0;
+      if (xok[j] && in_k) xv = xa[j] ? xa[j][i] * xb[j][i] : xb[j][i];
+      if (yok[j] && in_k) {
+        int src = i - ysh[j];
+        if (src < 0) src += p.n;
+        yv = yb[j][src];
+      }
+      xr[j] = xv;
+      yr[j] = yv;
     }
   };
   auto commit = [&]() {
 #pragma unroll
     for (int j = 0; j < kPerThread; ++j) {
-      int e = tid + 256 * j;
-      int r = e / kKT, kk = e - r * kKT;
-      Xs[r][kk] = xr[j];
-      Ys[r][kk] = yr[j];
+      const int e = tid + 256 * j;
+      Xs[e / kKT][e & (kKT - 1)] = xr[j];
+      Ys[e / kKT][e & (kKT - 1)] = yr[j];
     }
   };
 
@@ -142,7 +150,7 @@ struct ReduceArgs {
   double* C[3];
   int64_t MN[3];
   int ks[3];
-  int64_t begin[3];  // flat start of each dim; begin[3] implied by total
+  int64_t begin[3];  // flat start of each dim
 };
 
 // Sums the node-chunk partial sums into the compact C_l (all dims at once).
@@ -158,7 +166,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(ReduceArgs a, int6
 }
 
 struct CombineArgs {
-  const double* C[3];
+  const double* C[3];   // compact C_l [M][N]
   int S[3], L[3], periodic[3], N[3];
   int m0, T;
   double* H;

@@ -38,51 +38,30 @@ __device__ inline int rr_partner(int x, int r, int me) {
   return y < 0 ? y + n1 : y;
 }
 
+// Jacobi rotation zeroing A[p][q] of the Hermitian 2x2 [[a, b], [conj b, d]]
+// (Golub & Van Loan, sym.schur2, after removing the phase of b):
+// J = D R, D = diag(1, exp(-i phi)), R = [[c, s], [-s, c]], so
+// J[p][p] = c, J[q][p] = -s e^{-i phi}, J[p][q] = s, J[q][q] = c e^{-i phi};
+// the diagonal becomes a - t|b|, d + t|b|.  b = 0 (or a padding index q)
+// gives the identity.
 struct Rot {
-  double c, s, tb;  // cos, sin, t*|b| (shift of the diagonal)
-  cx ph;            // exp(-i phi), b = |b| exp(i phi)
-  bool active;
+  double c, s, tb, ph_re, ph_im;
 };
 
-// Jacobi rotation zeroing A[p][q] of the Hermitian 2x2 [[a, b], [conj b, d]]
-// (Golub & Van Loan, sym.schur2, after removing the phase of b).
-__device__ inline Rot make_rot(const cx* A, int LD, int p, int q, int m) {
-  Rot r;
-  r.active = false;
-  r.c = 1.0;
-  r.s = 0.0;
-  r.tb = 0.0;
-  r.ph = {1.0, 0.0};
-  if (q >= m) return r;
-  double a = A[p * LD + p].re, d = A[q * LD + q].re;
-  cx b = A[p * LD + q];
-  double ab = sqrt(cabs2(b));
-  if (!(ab > 0.0)) return r;
-  double tau = (d - a) / (2.0 * ab);
-  double t = fabs(tau) > 1e150 ? 0.5 / tau
-                               : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  r.c = 1.0 / sqrt(1.0 + t * t);
+__device__ inline Rot make_rot(double a, double d, cx b, bool valid) {
+  Rot r = {1.0, 0.0, 0.0, 1.0, 0.0};
+  double b2 = cabs2(b);
+  if (!valid || !(b2 > 0.0)) return r;
+  double inv_ab = rsqrt(b2);
+  double tau = 0.5 * (d - a) * inv_ab;
+  double at = fabs(tau);
+  double t = at > 1e150 ? 0.5 / tau : copysign(1.0 / (at + sqrt(fma(tau, tau, 1.0))), tau);
+  r.c = rsqrt(fma(t, t, 1.0));
   r.s = t * r.c;
-  r.tb = t * ab;
-  r.ph = cscale(cconj(b), 1.0 / ab);
-  r.active = true;
+  r.tb = t * (b2 * inv_ab);
+  r.ph_re = b.re * inv_ab;
+  r.ph_im = -b.im * inv_ab;
   return r;
-}
-
-// Column x of the rotation J (rows x and its partner xp), J = D R with
-// D = diag(1, exp(-i phi)) on (p, q): J[p][p] = c, J[q][p] = -s e^{-i phi},
-// J[p][q] = s, J[q][q] = c e^{-i phi}.
-__device__ inline void rot_column(const Rot& r, bool first, cx& Jxx, cx& Jpx) {
-  if (!r.active) {
-    Jxx = {1.0, 0.0};
-    Jpx = {0.0, 0.0};
-  } else if (first) {
-    Jxx = {r.c, 0.0};
-    Jpx = cscale(r.ph, -r.s);
-  } else {
-    Jxx = cscale(r.ph, r.c);
-    Jpx = {r.s, 0.0};
-  }
 }
 
 template <int MAXM>
@@ -99,6 +78,10 @@ __global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ 
   __shared__ cx Ab[NB][MAXM * LD];
   __shared__ cx Vb[NB][MAXM * LD];
   __shared__ cx B[MAXM * LD];
+  // round-robin schedule: partner and pair slot of every index in every round
+  __shared__ unsigned char s_partner[MAXM][MAXM];
+  __shared__ unsigned char s_slot[MAXM][MAXM];
+  __shared__ Rot s_rot[MAXM / 2];
   __shared__ int rank_of[MAXM];
   __shared__ int fail;
   __shared__ double red[2];
@@ -199,11 +182,30 @@ __global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ 
     __syncthreads();
   }
 
-  // 3. Jacobi sweeps, round-robin pairing of the (even-padded) indices.  Every
-  // thread forms the rotations of its row pair and column pair itself.
+  // 3. Jacobi sweeps with the round-robin ordering of the (even-padded)
+  // indices: in every round the me/2 rotations are formed by one thread each
+  // and shared through LDS, then every thread updates its own entry of C and
+  // of V from the four entries of its 2x2 coupling.
   int converged = (m == 1);
   int cur = 0;
   const int me = m + (m & 1);
+  for (int e = tid; e < (me - 1) * me; e += nt) {
+    int r = e / me, x = e - r * me;
+    int y = rr_partner(x, r, me);
+    s_partner[r][x] = (unsigned char)y;
+    // slot: 0 for the pair containing me-1, else the distance k in {r+k, r-k}
+    int p = min(x, y);
+    int slot;
+    if (y == me - 1 || x == me - 1) {
+      slot = 0;
+    } else {
+      int k = (p - r) % (me - 1);
+      if (k < 0) k += me - 1;
+      slot = k <= (me - 1) / 2 ? k : (me - 1) - k;
+    }
+    s_slot[r][x] = (unsigned char)slot;
+  }
+  __syncthreads();
   for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
     // convergence: off-diagonal Frobenius norm against the whole norm
     if (tid < 2) red[tid] = 0.0;
@@ -228,31 +230,57 @@ __global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ 
       break;
     }
     for (int r = 0; r < me - 1; ++r) {
+      if (tid < me / 2) {
+        // pair of slot tid in round r
+        int p, q;
+        if (tid == 0) {
+          p = r;
+          q = me - 1;
+        } else {
+          p = (r + tid) % (me - 1);
+          q = (r - tid + me - 1) % (me - 1);
+        }
+        if (p > q) {
+          int t = p;
+          p = q;
+          q = t;
+        }
+        bool valid = q < m;
+        cx b = valid ? A[p * LD + q] : cx{0.0, 0.0};
+        double a = valid ? A[p * LD + p].re : 0.0;
+        double d = valid ? A[q * LD + q].re : 0.0;
+        s_rot[tid] = make_rot(a, d, b, valid);
+      }
+      __syncthreads();
       cx na = {0.0, 0.0}, nv = {0.0, 0.0};
       if (owner) {
         const int i = ei, j = ej;
-        const int ip = rr_partner(i, r, me), jp = rr_partner(j, r, me);
-        const Rot ri = make_rot(A, LD, min(i, ip), max(i, ip), m);
-        const Rot rj = make_rot(A, LD, min(j, jp), max(j, jp), m);
-        cx Jii, Jpi, Jjj, Jpj;
-        rot_column(ri, i < ip, Jii, Jpi);
-        rot_column(rj, j < jp, Jjj, Jpj);
-        if (ri.active && (j == i || j == ip)) {
+        const int ip = s_partner[r][i], jp = s_partner[r][j];
+        const Rot ri = s_rot[s_slot[r][i]];
+        const Rot rj = s_rot[s_slot[r][j]];
+        // column i of J: J[i][i] and J[ip][i]
+        const bool fi = i < ip, fj = j < jp;
+        cx Jii = fi ? cx{ri.c, 0.0} : cx{ri.ph_re * ri.c, ri.ph_im * ri.c};
+        cx Jpi = fi ? cx{-ri.ph_re * ri.s, -ri.ph_im * ri.s} : cx{ri.s, 0.0};
+        cx Jjj = fj ? cx{rj.c, 0.0} : cx{rj.ph_re * rj.c, rj.ph_im * rj.c};
+        cx Jpj = fj ? cx{-rj.ph_re * rj.s, -rj.ph_im * rj.s} : cx{rj.s, 0.0};
+        if (j == i || j == ip) {
           // inside one rotated 2x2 block: exact diagonal form
-          if (i == j) na = {A[i * LD + i].re + (i < ip ? -ri.tb : ri.tb), 0.0};
+          if (i == j) na = {A[i * LD + i].re + (fi ? -ri.tb : ri.tb), 0.0};
         } else {
           // sum over a in {i, ip}, b in {j, jp} of conj(J[a][i]) A[a][b] J[b][j]
+          const bool jin = jp < m, iin = ip < m;
           cx t0 = cmul(A[i * LD + j], Jjj);
-          if (rj.active) t0 = cadd(t0, cmul(A[i * LD + jp], Jpj));
+          if (jin) t0 = cadd(t0, cmul(A[i * LD + jp], Jpj));
           na = cmul(cconj(Jii), t0);
-          if (ri.active) {
+          if (iin) {
             cx t1 = cmul(A[ip * LD + j], Jjj);
-            if (rj.active) t1 = cadd(t1, cmul(A[ip * LD + jp], Jpj));
+            if (jin) t1 = cadd(t1, cmul(A[ip * LD + jp], Jpj));
             na = cadd(na, cmul(cconj(Jpi), t1));
           }
         }
         nv = cmul(V[i * LD + j], Jjj);
-        if (rj.active) nv = cadd(nv, cmul(V[i * LD + jp], Jpj));
+        if (jp < m) nv = cadd(nv, cmul(V[i * LD + jp], Jpj));
       }
       if (kDouble) {
         cur ^= 1;
