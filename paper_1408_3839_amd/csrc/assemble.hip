@@ -28,6 +28,7 @@ namespace tl {
 namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBM = 32;   // rows of a workgroup tile (2 MFMA row blocks)
 constexpr int kBN = 32;   // columns of a workgroup tile (2 MFMA column blocks)
@@ -142,6 +143,320 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(ContractArgs a) {
   for (int r = 0; r < 4; ++r) {
     int row = row0 + wm * 16 + (lane >> 4) + 4 * r;
     if (row < p.M && col < p.N) p.part[((int64_t)z * p.M + row) * p.N + col] = acc[r];
+  }
+}
+
+// ---------------------------------------------------------------- FP32 mode
+// Same tiling; the operands are rounded to FP32 in the staging step and
+// multiplied with V_MFMA_F32_16X16X4_F32; each 64-node stage's FP32 sums are
+// added into FP64 accumulators.
+__global__ __launch_bounds__(256) void contract_f32_kernel(ContractArgs a) {
+  __shared__ float Xs[kBM][kLDP];
+  __shared__ float Ys[kBN][kLDP];
+  const int b = blockIdx.x;
+  const int dd = b >= a.d[2].block_begin ? 2 : (b >= a.d[1].block_begin ? 1 : 0);
+  const DimArgs& p = a.d[dd];
+  const int local = b - p.block_begin;
+  const int z = local % p.ks;
+  const int rest = local / p.ks;
+  const int col0 = (rest % p.tiles_n) * kBN;
+  const int row0 = (rest / p.tiles_n) * kBM;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int kbeg = z * p.kchunk;
+  const int kend = min(p.n, kbeg + p.kchunk);
+  const int wm = wave >> 1, wn = wave & 1;
+  float xr[kPerThread], yr[kPerThread];
+  const double* xa[kPerThread];
+  const double* xb[kPerThread];
+  const double* yb[kPerThread];
+  int ysh[kPerThread];
+  bool xok[kPerThread], yok[kPerThread];
+#pragma unroll
+  for (int j = 0; j < kPerThread; ++j) {
+    const int r = (tid + 256 * j) / kKT;
+    const int row = row0 + r, col = col0 + r;
+    xok[j] = row < p.M;
+    yok[j] = col < p.N;
+    const int t = xok[j] ? row / a.m0 : 0, nu = xok[j] ? row - t * a.m0 : 0;
+    xa[j] = t < a.T ? p.P + (int64_t)t * p.n : nullptr;
+    xb[j] = (t < a.T ? p.G : (t == a.T ? p.AG : p.SG)) + (int64_t)nu * p.n;
+    const int mu = yok[j] ? col / p.S : 0, sh = yok[j] ? col - mu * p.S : 0;
+    yb[j] = p.G + (int64_t)mu * p.n;
+    ysh[j] = sh * p.cn;
+  }
+  auto stage = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) {
+      const int kk = (tid + 256 * j) & (kKT - 1);
+      const int i = k0 + kk;
+      const bool in_k = i < kend;
+      double xv = 0.0, yv = 0.0;
+      if (xok[j] && in_k) xv = xa[j] ? xa[j][i] * xb[j][i] : xb[j][i];
+      if (yok[j] && in_k) {
+        int src = i - ysh[j];
+        if (src < 0) src += p.n;
+        yv = yb[j][src];
+      }
+      xr[j] = (float)xv;
+      yr[j] = (float)yv;
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) {
+      const int e = tid + 256 * j;
+      Xs[e / kKT][e & (kKT - 1)] = xr[j];
+      Ys[e / kKT][e & (kKT - 1)] = yr[j];
+    }
+  };
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  stage(kbeg);
+  commit();
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += kKT) {
+    const bool more = k0 + kKT < kend;
+    if (more) stage(k0 + kKT);
+    f32x4 acc32 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < kKT; kk += 4) {
+      float av = Xs[wm * 16 + (lane & 15)][kk + (lane >> 4)];
+      float bv = Ys[wn * 16 + (lane & 15)][kk + (lane >> 4)];
+      acc32 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc32, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] += (double)acc32[r];
+    __syncthreads();
+    if (more) commit();
+    __syncthreads();
+  }
+  // f32 16x16x4 result layout: register r of lane l holds D[4 (l / 16) + r][l % 16]
+  const int col = col0 + wn * 16 + (lane & 15);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int row = row0 + wm * 16 + 4 * (lane >> 4) + r;
+    if (row < p.M && col < p.N) p.part[((int64_t)z * p.M + row) * p.N + col] = acc[r];
+  }
+}
+
+// ---------------------------------------------------------------- split modes
+// Operand splitting in the manner of Ozaki, Ogita, Oishi & Rump (2012): each
+// row r of X (and of G) is scaled by a power of two sigma_r >= max|row|, and
+// the scaled values are cut into integer slices
+//   x/sigma = sum_k n_k 2^(-k beta),  |n_1| <= 2^beta, |n_k| <= 2^(beta-1),
+// each exactly representable in bf16 (beta = 8) or fp16 (beta = 9).  A slice
+// product summed over one 32-node MFMA (16x16x32) stays below 2^24 and is
+// exact in FP32; all products of one level a + b are accumulated in FP32 over
+// one MFMA step and then added to a per-level FP64 accumulator.  Only the
+// products with a + b <= s + 1 are formed (triangular truncation).
+
+constexpr int kMaxSlices = 8;
+constexpr int kSKT = 32;             // nodes per LDS stage = one MFMA K step
+constexpr int kSLD = kSKT + 8;       // padded LDS row (elements)
+
+template <typename T>
+struct LowTraits;
+template <>
+struct LowTraits<__bf16> {
+  static constexpr int beta = 8;
+};
+template <>
+struct LowTraits<_Float16> {
+  static constexpr int beta = 9;
+};
+
+struct SliceArgs {
+  const double* P[3];
+  const double* G[3];
+  const double* AG[3];
+  const double* SG[3];
+  void* xs[3];          // [s][M][n] slices of X rows
+  void* ys[3];          // [s][m0][n] slices of G rows
+  double* xscale[3];    // [M]
+  double* yscale[3];    // [m0]
+  int n[3], M[3];
+  int rows_begin[7];    // X rows of dims 0..2, then G rows of dims 0..2
+  int m0, T, s;
+};
+
+// Workgroup per row: max |value| (power-of-two scale), then the slices.
+template <typename LowT>
+__global__ __launch_bounds__(256) void slice_kernel(SliceArgs a) {
+  constexpr int beta = LowTraits<LowT>::beta;
+  __shared__ double wmax[4];
+  const int b = blockIdx.x;
+  int k = 0;
+  while (k < 6 && b >= a.rows_begin[k + 1]) ++k;
+  const bool isx = k < 3;
+  const int d = isx ? k : k - 3;
+  const int row = b - a.rows_begin[k];
+  const int n = a.n[d];
+  const double* base;
+  const double* pot = nullptr;
+  if (isx) {
+    const int t = row / a.m0, nu = row - t * a.m0;
+    base = (t < a.T ? a.G[d] : (t == a.T ? a.AG[d] : a.SG[d])) + (int64_t)nu * n;
+    if (t < a.T) pot = a.P[d] + (int64_t)t * n;
+  } else {
+    base = a.G[d] + (int64_t)row * n;
+  }
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = pot ? pot[i] * base[i] : base[i];
+    mx = fmax(mx, fabs(v));
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+  // sigma = 2^e >= mx, so |x / sigma| <= 1 exactly
+  int e = 0;
+  if (mx > 0.0) {
+    frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+  }
+  const double sigma = ldexp(1.0, e), inv = ldexp(1.0, -e);
+  if (threadIdx.x == 0) (isx ? a.xscale[d] : a.yscale[d])[row] = sigma;
+  LowT* out = (LowT*)(isx ? a.xs[d] : a.ys[d]);
+  const int64_t rows = isx ? a.M[d] : a.m0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = (pot ? pot[i] * base[i] : base[i]) * inv;
+    for (int q = 1; q <= a.s; ++q) {
+      double sc = ldexp(1.0, q * beta);
+      double nk = rint(v * sc);
+      v = fma(-nk, ldexp(1.0, -q * beta), v);
+      out[((int64_t)(q - 1) * rows + row) * n + i] = (LowT)nk;
+    }
+  }
+}
+
+struct SplitDimArgs {
+  const void* xs;       // [s][M][n]
+  const void* ys;       // [s][m0][n]
+  const double* xscale;
+  const double* yscale;
+  double* part;
+  int n, S, cn, M, N, kchunk, ks, tiles_n, block_begin;
+};
+struct SplitArgs {
+  SplitDimArgs d[3];
+  int m0, s;
+};
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <typename LowT>
+struct Vec8;
+template <>
+struct Vec8<__bf16> {
+  typedef bf16x8 type;
+  static __device__ inline f32x4 mfma(type a, type b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Vec8<_Float16> {
+  typedef f16x8 type;
+  static __device__ inline f32x4 mfma(type a, type b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename LowT, int S>
+__global__ __launch_bounds__(256) void contract_split_kernel(SplitArgs a) {
+  typedef typename Vec8<LowT>::type v8;
+  constexpr int beta = LowTraits<LowT>::beta;
+  __shared__ __attribute__((aligned(16))) LowT Xl[S][kBM][kSLD];
+  __shared__ __attribute__((aligned(16))) LowT Yl[S][kBN][kSLD];
+  const int b = blockIdx.x;
+  const int dd = b >= a.d[2].block_begin ? 2 : (b >= a.d[1].block_begin ? 1 : 0);
+  const SplitDimArgs& p = a.d[dd];
+  const int local = b - p.block_begin;
+  const int z = local % p.ks;
+  const int rest = local / p.ks;
+  const int col0 = (rest % p.tiles_n) * kBN;
+  const int row0 = (rest / p.tiles_n) * kBM;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int kbeg = z * p.kchunk;
+  const int kend = min(p.n, kbeg + p.kchunk);
+  const int wm = wave >> 1, wn = wave & 1;
+  const LowT* xs = (const LowT*)p.xs;
+  const LowT* ys = (const LowT*)p.ys;
+  // staging: thread stages 4 consecutive nodes of one X row and one Y column
+  const int sr = tid >> 3;             // row / column within the tile (0..31)
+  const int sk = (tid & 7) * 4;        // first node within the stage
+  const int xrow = row0 + sr, ycol = col0 + sr;
+  const bool xok = xrow < p.M, yok = ycol < p.N;
+  const int mu = yok ? ycol / p.S : 0;
+  const int ysh = yok ? (ycol - mu * p.S) * p.cn : 0;
+  LowT xr[S][4], yr[S][4];
+  auto stage = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = k0 + sk + e;
+      const bool in_k = i < kend;
+      int src = i - ysh;
+      if (src < 0) src += p.n;
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        xr[q][e] = (xok && in_k) ? xs[((int64_t)q * p.M + xrow) * p.n + i] : (LowT)0.0f;
+        yr[q][e] = (yok && in_k) ? ys[((int64_t)q * a.m0 + mu) * p.n + src] : (LowT)0.0f;
+      }
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        Xl[q][sr][sk + e] = xr[q][e];
+        Yl[q][sr][sk + e] = yr[q][e];
+      }
+  };
+  double acc[S][4];
+#pragma unroll
+  for (int l = 0; l < S; ++l)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[l][r] = 0.0;
+  stage(kbeg);
+  commit();
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += kSKT) {
+    const bool more = k0 + kSKT < kend;
+    if (more) stage(k0 + kSKT);
+    v8 av[S], bv[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      av[q] = *(const v8*)&Xl[q][wm * 16 + (lane & 15)][8 * (lane >> 4)];
+      bv[q] = *(const v8*)&Yl[q][wn * 16 + (lane & 15)][8 * (lane >> 4)];
+    }
+    // level l = qa + qb (0-based slices), l = 0..S-1
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+      f32x4 c32 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int qa = 0; qa <= l; ++qa) c32 = Vec8<LowT>::mfma(av[qa], bv[l - qa], c32);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[l][r] += (double)c32[r];
+    }
+    __syncthreads();
+    if (more) commit();
+    __syncthreads();
+  }
+  const int col = col0 + wn * 16 + (lane & 15);
+  const double ysc = col < p.N ? p.yscale[col / p.S] : 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int row = row0 + wm * 16 + 4 * (lane >> 4) + r;
+    if (row < p.M && col < p.N) {
+      double v = 0.0;
+#pragma unroll
+      for (int l = S - 1; l >= 0; --l) v += ldexp(acc[l][r], -(l + 2) * beta);
+      p.part[((int64_t)z * p.M + row) * p.N + col] = v * p.xscale[row] * ysc;
+    }
   }
 }
 
@@ -263,26 +578,126 @@ Plan make_plan(const Geometry& g) {
   return p;
 }
 
+// Extra workspace of the split modes: slices of X and G rows and their scales.
+struct SplitPlan {
+  size_t xs_off[3], ys_off[3], xsc_off[3], ysc_off[3];
+  size_t bytes;
+};
+
+SplitPlan make_split_plan(const Geometry& g, const Plan& plan, int s, size_t base) {
+  SplitPlan sp;
+  size_t off = base;
+  for (int d = 0; d < 3; ++d) {
+    sp.xs_off[d] = off;
+    off += align_up(2 * (size_t)s * plan.M[d] * g.n[d], 256);
+    sp.ys_off[d] = off;
+    off += align_up(2 * (size_t)s * g.m0 * g.n[d], 256);
+    sp.xsc_off[d] = off;
+    off += align_up(sizeof(double) * (size_t)plan.M[d], 256);
+    sp.ysc_off[d] = off;
+    off += align_up(sizeof(double) * (size_t)g.m0, 256);
+  }
+  sp.bytes = off;
+  return sp;
+}
+
+bool is_split(tl_precision prec) { return prec == TL_SPLIT_BF16 || prec == TL_SPLIT_FP16; }
+
+int default_slices(tl_precision prec) { return prec == TL_SPLIT_FP16 ? 5 : 6; }
+
+template <typename LowT>
+tl_status launch_split(const Geometry& g, const Plan& plan, const SplitPlan& sp, char* wsb,
+                       const double* G, const double* AG, const double* SG, const double* P,
+                       int S, hipStream_t stream) {
+  SliceArgs sa;
+  std::memset(&sa, 0, sizeof(sa));
+  sa.m0 = g.m0;
+  sa.T = (int)g.pot_terms;
+  sa.s = S;
+  int rb = 0;
+  for (int d = 0; d < 3; ++d) {
+    sa.P[d] = P + g.pot_off[d];
+    sa.G[d] = G + g.basis_off[d];
+    sa.AG[d] = AG + g.basis_off[d];
+    sa.SG[d] = SG + g.basis_off[d];
+    sa.xs[d] = wsb + sp.xs_off[d];
+    sa.ys[d] = wsb + sp.ys_off[d];
+    sa.xscale[d] = (double*)(wsb + sp.xsc_off[d]);
+    sa.yscale[d] = (double*)(wsb + sp.ysc_off[d]);
+    sa.n[d] = g.n[d];
+    sa.M[d] = plan.M[d];
+  }
+  for (int d = 0; d < 3; ++d) {
+    sa.rows_begin[d] = rb;
+    rb += plan.M[d];
+  }
+  for (int d = 0; d < 3; ++d) {
+    sa.rows_begin[3 + d] = rb;
+    rb += g.m0;
+  }
+  sa.rows_begin[6] = rb;
+  hipLaunchKernelGGL(slice_kernel<LowT>, dim3((unsigned)rb), dim3(256), 0, stream, sa);
+  TL_CHECK_LAUNCH();
+  SplitArgs a;
+  a.m0 = g.m0;
+  a.s = S;
+  int begin = 0;
+  for (int d = 0; d < 3; ++d) {
+    SplitDimArgs& q = a.d[d];
+    q.xs = wsb + sp.xs_off[d];
+    q.ys = wsb + sp.ys_off[d];
+    q.xscale = (const double*)(wsb + sp.xsc_off[d]);
+    q.yscale = (const double*)(wsb + sp.ysc_off[d]);
+    q.part = (double*)(wsb + plan.part_off[d]);
+    q.n = g.n[d];
+    q.S = g.shifts[d];
+    q.cn = g.periodic[d] ? g.cell_nodes[d] : 0;
+    q.M = plan.M[d];
+    q.N = plan.N[d];
+    q.kchunk = plan.kchunk[d];
+    q.ks = plan.ks[d];
+    q.tiles_n = plan.tiles_n[d];
+    q.block_begin = begin;
+    begin += plan.blocks[d];
+  }
+  if (g_ev_start) TL_HIP(hipEventRecord(g_ev_start, stream));
+  dim3 grid((unsigned)plan.total_blocks), blk(256);
+  switch (S) {
+    case 2: hipLaunchKernelGGL((contract_split_kernel<LowT, 2>), grid, blk, 0, stream, a); break;
+    case 3: hipLaunchKernelGGL((contract_split_kernel<LowT, 3>), grid, blk, 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((contract_split_kernel<LowT, 4>), grid, blk, 0, stream, a); break;
+    case 5: hipLaunchKernelGGL((contract_split_kernel<LowT, 5>), grid, blk, 0, stream, a); break;
+    case 6: hipLaunchKernelGGL((contract_split_kernel<LowT, 6>), grid, blk, 0, stream, a); break;
+    case 7: hipLaunchKernelGGL((contract_split_kernel<LowT, 7>), grid, blk, 0, stream, a); break;
+    default: hipLaunchKernelGGL((contract_split_kernel<LowT, 8>), grid, blk, 0, stream, a); break;
+  }
+  TL_CHECK_LAUNCH();
+  if (g_ev_stop) TL_HIP(hipEventRecord(g_ev_stop, stream));
+  return TL_OK;
+}
+
 }  // namespace
 
 size_t assemble_workspace_bytes(const Geometry& g, tl_precision prec, int n_slices) {
-  (void)prec;
-  (void)n_slices;
   if (g.mode != TL_MODE_PERIODIC) return 0;
-  return make_plan(g).bytes;
+  Plan plan = make_plan(g);
+  if (!is_split(prec)) return plan.bytes;
+  int S = n_slices > 0 ? n_slices : default_slices(prec);
+  return make_split_plan(g, plan, S, plan.bytes).bytes;
 }
 
 tl_status assemble_periodic(const Geometry& g, const double* G, const double* AG,
                             const double* SG, const double* P, tl_precision prec, int n_slices,
                             double* H, double* S, void* ws, size_t ws_bytes, hipStream_t stream) {
-  (void)n_slices;
-  if (prec != TL_FP64) {
-    set_error("precision mode %d not available for the periodic assembly yet", (int)prec);
-    return TL_EUNSUPPORTED;
-  }
   Plan plan = make_plan(g);
-  if (ws == nullptr || ws_bytes < plan.bytes) {
-    set_error("assembly workspace: need %zu bytes, got %zu", plan.bytes, ws_bytes);
+  const int nsl = is_split(prec) ? (n_slices > 0 ? n_slices : default_slices(prec)) : 0;
+  if (is_split(prec) && (nsl < 2 || nsl > kMaxSlices)) {
+    set_error("n_slices = %d outside [2, %d]", n_slices, kMaxSlices);
+    return TL_EINVAL;
+  }
+  const size_t need = is_split(prec) ? make_split_plan(g, plan, nsl, plan.bytes).bytes : plan.bytes;
+  if (ws == nullptr || ws_bytes < need) {
+    set_error("assembly workspace: need %zu bytes, got %zu", need, ws_bytes);
     return TL_EWORKSPACE;
   }
   char* wsb = (char*)ws;
@@ -308,11 +723,23 @@ tl_status assemble_periodic(const Geometry& g, const double* G, const double* AG
     p.block_begin = begin;
     begin += plan.blocks[d];
   }
-  if (g_ev_start) TL_HIP(hipEventRecord(g_ev_start, stream));
-  hipLaunchKernelGGL(contract_f64_kernel, dim3((unsigned)plan.total_blocks), dim3(256), 0, stream,
-                     a);
-  TL_CHECK_LAUNCH();
-  if (g_ev_stop) TL_HIP(hipEventRecord(g_ev_stop, stream));
+  if (prec == TL_SPLIT_BF16) {
+    TL_TRY(launch_split<__bf16>(g, plan, make_split_plan(g, plan, nsl, plan.bytes), wsb, G, AG, SG,
+                                P, nsl, stream));
+  } else if (prec == TL_SPLIT_FP16) {
+    TL_TRY(launch_split<_Float16>(g, plan, make_split_plan(g, plan, nsl, plan.bytes), wsb, G, AG,
+                                  SG, P, nsl, stream));
+  } else {
+    if (g_ev_start) TL_HIP(hipEventRecord(g_ev_start, stream));
+    if (prec == TL_FP32)
+      hipLaunchKernelGGL(contract_f32_kernel, dim3((unsigned)plan.total_blocks), dim3(256), 0,
+                         stream, a);
+    else
+      hipLaunchKernelGGL(contract_f64_kernel, dim3((unsigned)plan.total_blocks), dim3(256), 0,
+                         stream, a);
+    TL_CHECK_LAUNCH();
+    if (g_ev_stop) TL_HIP(hipEventRecord(g_ev_stop, stream));
+  }
   ReduceArgs ra;
   int64_t tot = 0;
   for (int d = 0; d < 3; ++d) {

@@ -1,0 +1,103 @@
+"""Reduced-precision contraction modes against the FP64 oracle.
+
+FP32: operands rounded to FP32, MFMA f32, FP64 stage sums.
+split-bf16 / split-fp16: power-of-two row scaling, integer slices of 8 (bf16)
+or 9 (fp16) bits, exact FP32 slice products, FP64 level sums, s slices.
+The entry error is measured against the largest entry of the block column
+(the scale at which the eigenvalues see it) and must shrink with the slice
+count as 2^(-beta s); eigenvalues are checked with the first-order bound
+plus the entry perturbation.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from paper_1408_3839_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CASES = {"c1": lambda: wl.config(1), "c2": lambda: wl.config(2),
+         "tiny_3d": lambda: wl.tiny_periodic(L=(3, 2, 2), m0=4, c=4, h=0.5, R=6, K=(1, 1, 1),
+                                             sites=((0, 0, 0), (0.5, 0.5, -0.5)), Z=(1.0, 2.0)),
+         "tiny_L5_c7": lambda: wl.tiny_periodic(L=(5, 1, 1), m0=5, c=7, h=0.25, R=9,
+                                                alpha_range=(0.3, 4.0))}
+_ref_cache = {}
+
+
+def _ref(name):
+    if name not in _ref_cache:
+        sys = CASES[name]()
+        H, S, scale = oracle.core_hamiltonian_blocks(sys)
+        _ref_cache[name] = (sys, H, S, scale)
+    return _ref_cache[name]
+
+
+def _run(sys, precision, n_slices):
+    from paper_1408_3839_amd.pipeline import PeriodicPipeline
+    pl = PeriodicPipeline(sys, precision=precision, n_slices=n_slices)
+    pl.run()
+    torch.cuda.synchronize()
+    return pl
+
+
+# (precision, slices, bound on max|dH| / max|H|)
+MODES = [("fp32", 0, 3e-6), ("split_bf16", 3, 3e-6), ("split_bf16", 4, 1e-8),
+         ("split_bf16", 5, 3e-11), ("split_bf16", 6, 1e-13), ("split_bf16", 7, 1e-14),
+         ("split_fp16", 3, 3e-7), ("split_fp16", 4, 1e-9), ("split_fp16", 5, 3e-12),
+         ("split_fp16", 6, 1e-14)]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("mode", MODES, ids=lambda m: f"{m[0]}-{m[1]}")
+def test_lowp_entries(name, mode):
+    prec, s, bound = mode
+    sys, Hr, Sr, scale = _ref(name)
+    pl = _run(sys, prec, s)
+    H = pl.H.cpu().numpy()
+    S = pl.S.cpu().numpy()
+    eh = np.abs(H - Hr).max() / np.abs(Hr).max()
+    es = np.abs(S - Sr).max() / np.abs(Sr).max()
+    print(f"\n{name} {prec} s={s}: max|dH|/max|H| = {eh:.3e}  max|dS|/max|S| = {es:.3e}")
+    assert eh <= bound and es <= bound, (eh, es, bound)
+
+
+@pytest.mark.parametrize("mode", [("fp32", 0), ("split_bf16", 6), ("split_fp16", 5)],
+                         ids=lambda m: f"{m[0]}-{m[1]}")
+def test_lowp_eigenvalues_c2(mode):
+    """k-block eigenvalues of the reduced-precision path: within the
+    first-order bound of the measured entry perturbation for every
+    eigenvalue, and within 1e-6 Ha wherever that bound is below 1e-7."""
+    prec, s = mode
+    sys, Hr, Sr, _ = _ref("c2")
+    pl = _run(sys, prec, s)
+    ev = pl.evals.cpu().numpy()
+    info = pl.info.cpu().numpy()
+    dH = np.abs(pl.H.cpu().numpy() - Hr).max()
+    dS = np.abs(pl.S.cpu().numpy() - Sr).max()
+    Hb = oracle.block_dft_1level(Hr).reshape(-1, sys.m0, sys.m0)
+    Sb = oracle.block_dft_1level(Sr).reshape(-1, sys.m0, sys.m0)
+    L = sys.ncells
+    worst_ok = 0.0
+    for j in range(Hb.shape[0]):
+        if info[j] != 0:
+            # a perturbed Sbar_j may lose definiteness only if it was within
+            # the perturbation of singular
+            assert prec == "fp32" and info[j] > 0
+            assert np.linalg.eigvalsh(Sb[j])[0] <= 4 * L * sys.m0 * dS, j
+            continue
+        lam, U = sla.eigh(Hb[j], Sb[j])
+        un = np.sum(np.abs(U) ** 2, axis=0)
+        eps = 2.0 ** -52
+        bound = (L * sys.m0 * (dH + np.abs(lam) * dS)
+                 + 256 * eps * (np.linalg.norm(Hb[j], 2) + np.abs(lam) * np.linalg.norm(Sb[j], 2))) * un
+        d = np.abs(ev[j] - lam)
+        assert np.all(d <= 4 * bound + 1e-10 * np.maximum(1, np.abs(lam))), (j, d, bound)
+        ok = bound < 1e-7
+        if ok.any():
+            worst_ok = max(worst_ok, float(d[ok].max()))
+    if prec != "fp32":
+        assert np.all(info == 0)
+    print(f"\nc2 {prec} s={s}: max |d lambda| where the bound < 1e-7: {worst_ok:.3e} Ha")
+    assert worst_ok <= 1e-6
