@@ -93,13 +93,64 @@ def eig_errors(ev_gpu, Hb, Sb, m0):
             "max_eig_condition": cmax}
 
 
+def measure(sys_, precision, n_slices, steps, warmup):
+    """Time K graph replays of the whole step and K eager steps with HIP
+    events around the contraction kernel; return timings and outputs."""
+    import torch
+    from paper_1408_3839_amd import tl
+    from paper_1408_3839_amd.pipeline import PeriodicPipeline
+
+    pl = PeriodicPipeline(sys_, precision=precision, n_slices=n_slices, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        pl.run()
+    torch.cuda.synchronize()
+    # timed region 1: K whole steps, each one replay of the captured HIP graph
+    pl.capture()
+    for _ in range(warmup):
+        pl.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pl.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # timed region 2: the same K steps launched eagerly, HIP events recorded
+    # on the launch stream around the contraction kernel
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for a, b in evs:
+        a.record(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    te0 = time.perf_counter()
+    for k in range(steps):
+        tl.tl_set_contraction_events(evs[k][0].cuda_event, evs[k][1].cuda_event)
+        pl.run()
+    torch.cuda.synchronize()
+    te1 = time.perf_counter()
+    tl.tl_set_contraction_events(None, None)
+    contr_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    return {
+        "ms_per_step": 1e3 * (t1 - t0) / steps,
+        "eager_ms_per_step": 1e3 * (te1 - te0) / steps,
+        "contraction_ms": contr_ms,
+        "H": pl.H.cpu().numpy(), "S": pl.S.cpu().numpy(),
+        "evals": pl.evals.cpu().numpy(), "info": pl.info.cpu().numpy(),
+        "sizes": pl.sizes,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--precision", default="fp64",
+                    help="headline mode: fp64 | fp32 | split_bf16 | split_fp16")
+    ap.add_argument("--slices", type=int, default=0, help="slices of the split modes (0: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-modes", action="store_true", help="time the headline mode only")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -108,91 +159,102 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_1408_3839_amd import tl, workloads
-    from paper_1408_3839_amd.pipeline import PeriodicPipeline
+    from paper_1408_3839_amd import workloads
 
     sys_ = workloads.config(2)
-    pl = PeriodicPipeline(sys_, precision=args.precision, device="cuda:0")
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        pl.run()
-    torch.cuda.synchronize()
+    default_slices = {"split_bf16": 6, "split_fp16": 5}
+    head_slices = args.slices or default_slices.get(args.precision, 0)
+    modes = [(args.precision, head_slices)]
+    if not args.no_modes:
+        for m in (("fp64", 0), ("split_bf16", 6), ("split_bf16", 7), ("split_fp16", 5),
+                  ("fp32", 0)):
+            if m not in modes:
+                modes.append(m)
+    results = {}
+    for prec, nsl in modes:
+        results[(prec, nsl)] = measure(sys_, prec, nsl, args.steps, args.warmup)
+    head = results[(args.precision, head_slices)]
 
-    # timed region 1: K whole steps, each one replay of the captured HIP graph
-    pl.capture()
-    for _ in range(args.warmup):
-        pl.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pl.replay()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-
-    # timed region 2: the same K steps launched eagerly, with HIP events
-    # recorded around the contraction kernel on its stream
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for a, b in evs:
-        a.record(stream)
-        b.record(stream)
-    torch.cuda.synchronize()
-    te0 = time.perf_counter()
-    for k in range(args.steps):
-        tl.tl_set_contraction_events(evs[k][0].cuda_event, evs[k][1].cuda_event)
-        pl.run()
-    torch.cuda.synchronize()
-    te1 = time.perf_counter()
-    tl.tl_set_contraction_events(None, None)
-
-    dt = t1 - t0
-    ms = 1e3 * dt / args.steps
     entries = sys_.ncells * sys_.m0 * sys_.m0
-    contr_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    flops = contraction_flops(sys_, pl.sizes)
-    achieved = flops / (contr_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
+    flops = contraction_flops(sys_, head["sizes"])
+
+    def roofline(prec, nsl, r):
+        # executed MFMA flops: a split product set is s(s+1)/2 slice GEMMs
+        mult = nsl * (nsl + 1) // 2 if prec.startswith("split") else 1
+        achieved = flops * mult / (r["contraction_ms"] * 1e-3) / 1e12
+        peak = PEAK_TFLOPS[prec]
+        return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "kernel": ("contract_split_kernel" if prec.startswith("split") else
+                           f"contract_{'f32' if prec == 'fp32' else 'f64'}_kernel")
+                + " (1D contractions of the three dims, one launch)",
+                "algorithmic_flops_per_step": flops, "executed_flops_per_step": flops * mult,
+                "avg_kernel_ms": r["contraction_ms"]}
+
+    dtype = {"fp64": "f64", "fp32": "f32+f64", "split_bf16": f"bf16x{head_slices}+f64",
+             "split_fp16": f"f16x{head_slices}+f64"}[args.precision]
     out = {
         "metric": METRIC,
-        "value": entries * args.steps / dt,
+        "value": entries / (head["ms_per_step"] * 1e-3),
         "unit": "entries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "dtype": dtype,
         "data": "synthetic",
         "config": {
             "workload": "periodic (64,1,1) chain, a=2.0 bohr, Z=1; m0=8 (4s+px,py,pz,px), "
                         "alpha log-uniform [0.1,30], seed 2; grid 2048x256x256, h=0.0625; "
                         "R=24 sinc terms, images -32..32",
             "precision": args.precision,
+            "slices": head_slices,
             "step": "one HIP-graph replay of the whole path",
-            "eager_ms_per_step": 1e3 * (te1 - te0) / args.steps,
+            "eager_ms_per_step": head["eager_ms_per_step"],
             "entries_per_step": entries,
             "k_blocks_per_step": sys_.ncells,
         },
-        "eigs_per_s": sys_.ncells * args.steps / dt,
-        "roofline": {
-            "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None,
-            "kernel": "contract_f64_kernel (1D contractions of the three dims, one launch)",
-            "flops_per_step": flops, "avg_kernel_ms": contr_ms,
-        },
+        "eigs_per_s": sys_.ncells / (head["ms_per_step"] * 1e-3),
+        "roofline": roofline(args.precision, head_slices, head),
     }
+    ref = None
     if not args.no_cpu_baseline:
-        cb, (Hr, Sr, Hb, Sb, ev_ref) = cpu_baseline(sys_, args.cpu_budget)
+        cb, ref = cpu_baseline(sys_, args.cpu_budget)
         out["cpu_baseline"] = cb
-        H = pl.H.cpu().numpy()
-        _, _, scale = __import__("oracle").core_hamiltonian_blocks(sys_)
-        acc = {"max_rel_dH_over_scale":
-               float(np.max(np.abs(H - Hr) / np.where(scale > 0, scale, 1.0)))}
-        acc.update(eig_errors(pl.evals.cpu().numpy(), Hb, Sb, sys_.m0))
-        out["accuracy_vs_fp64_oracle"] = acc
+    if ref is not None or not args.no_modes:
+        import oracle
+        if ref is None:
+            H, S, _ = oracle.core_hamiltonian_blocks(sys_)
+            ref = (H, S, oracle.block_dft_1level(H), oracle.block_dft_1level(S), None)
+        Hr, Sr, Hb, Sb, _ = ref
+        _, _, scale = oracle.core_hamiltonian_blocks(sys_)
+        table = {}
+        for (prec, nsl), r in results.items():
+            acc = {"ms_per_step": r["ms_per_step"], "contraction_ms": r["contraction_ms"],
+                   "entries_per_s": entries / (r["ms_per_step"] * 1e-3),
+                   "max_abs_dH_over_max_H": float(np.abs(r["H"] - Hr).max() / np.abs(Hr).max()),
+                   # entries above the denormal range (MFMA flushes denormals)
+                   "max_rel_dH_over_scale":
+                       float(np.max(np.where(scale > 1e-280, np.abs(r["H"] - Hr)
+                                             / np.where(scale > 0, scale, 1.0), 0.0))),
+                   "k_blocks_not_definite": int(np.sum(r["info"] > 0))}
+            ok = r["info"] == 0
+            if ok.any():
+                e = eig_errors(np.where(ok[:, None], r["evals"], 0.0)[ok], Hb.reshape(
+                    -1, sys_.m0, sys_.m0)[ok], Sb.reshape(-1, sys_.m0, sys_.m0)[ok], sys_.m0)
+                acc.update(e)
+            acc["roofline_frac"] = roofline(prec, nsl, r)["frac"]
+            table[f"{prec}" + (f"x{nsl}" if nsl else "")] = acc
+        out["precision_modes"] = table
+        fp64 = results.get(("fp64", 0))
+        if fp64 is not None:
+            out["split_vs_plain_speedup"] = {
+                k: fp64["ms_per_step"] / v["ms_per_step"] for k, v in table.items()}
+            out["split_vs_plain_contraction_speedup"] = {
+                k: fp64["contraction_ms"] / v["contraction_ms"] for k, v in table.items()}
     print(json.dumps(out))
 
 
