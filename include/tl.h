@@ -221,6 +221,60 @@ tl_status tl_block_fft(const double* in_dev, int L1, int L2, int L3, int m0, int
 tl_status tl_batched_heigh(const double* H_dev, const double* S_dev, int count, int m0,
                            double* evals_dev, double* evecs_dev, int* info_dev, void* stream);
 
+/*
+ * Batched path (many periodic (L,1,1) lattices of uneven L and m0): the
+ * whole chain basis -> potential -> assembly -> block FFT -> k-block
+ * eigensolves with ONE launch per stage for the whole batch.
+ *
+ *   tl_batch_plan_create  sizes every buffer for `count` systems (host only).
+ *   tl_batch_write_descriptor  writes, into caller host memory of
+ *       plan.desc_bytes bytes, every instance's launch arguments with device
+ *       addresses inside the caller's buffers; the caller copies it to device
+ *       memory once.  Buffers (device, caller-owned, contiguous per instance
+ *       in the order of `systems`):
+ *         G, AG, SG   basis_elems doubles each
+ *         P           pot_elems doubles
+ *         HS          hs_elems doubles: per instance H then S (block column)
+ *         HSbar       2*hs_elems doubles: per instance Hbar then Sbar (complex)
+ *         evals       eval_elems doubles: per instance [L][m0] ascending
+ *         info        kblocks ints (as tl_batched_heigh)
+ *         ws          ws_bytes bytes of workspace
+ *   tl_batch_run  enqueues the stages on `stream`; needs the host copy of
+ *       the descriptor (launch geometry) and its device copy (arguments).
+ *       Allocates nothing and copies nothing: capturable in a HIP graph.
+ * want_blocks is the tiling target of the contraction (workgroups per
+ * instance; 0 = library default), the parameter the autotuner chooses.
+ * Same arithmetic per instance as the single-system calls (bitwise equal
+ * for equal want_blocks).
+ */
+#define TL_MAX_BATCH 256
+typedef struct {
+  int count, precision, n_slices, want_blocks;
+  int max_m0, max_len;
+  int64_t basis_elems, pot_elems, hs_elems, eval_elems, kblocks;
+  size_t ws_bytes, desc_bytes;
+} tl_batch_plan;
+
+typedef struct {
+  double* G;
+  double* AG;
+  double* SG;
+  double* P;
+  double* HS;
+  double* HSbar;
+  double* evals;
+  int* info;
+  void* ws;
+} tl_batch_buffers;
+
+tl_status tl_batch_plan_create(const tl_system* systems, int count, tl_precision prec,
+                               int n_slices, int want_blocks, tl_batch_plan* out);
+tl_status tl_batch_write_descriptor(const tl_system* systems, int count,
+                                    const tl_batch_plan* plan, const tl_batch_buffers* buffers,
+                                    void* host_desc, size_t desc_bytes);
+tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_desc, const void* desc_dev,
+                       void* stream);
+
 #ifdef __cplusplus
 }
 #endif

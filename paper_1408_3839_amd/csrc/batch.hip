@@ -1,0 +1,366 @@
+// Step a9: a ragged batch of periodic lattice systems through the whole path
+// with one launch per stage.  The host writes, once, a descriptor holding
+// every instance's launch arguments (the same structs the single-system
+// entry points launch with) and the block prefix of every stage; the caller
+// uploads it.  Each stage kernel finds its instance by a binary search of
+// its block index in that prefix and runs the same device code as the
+// single-system kernel on its share.  Nothing is allocated and no host copy
+// is made during a run, so a run can be captured in a HIP graph.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "host_plans.h"
+
+namespace tl {
+namespace {
+
+enum Stage {
+  kBasis = 0,
+  kDirect,
+  kFold,
+  kSlice,
+  kContract,
+  kReduce,
+  kCombine,
+  kDft,
+  kHeigh,
+  kStages
+};
+
+struct InstanceJob {
+  dev::BasisArgs basis;
+  double* G;
+  double* AG;
+  double* SG;
+  PotentialPlan pot;
+  int T;  // potential terms
+  AssemblyPlan asmb;
+  dev::DftArgs dft;
+  int dft_rchunks;
+  const double* Hb;
+  const double* Sb;
+  double* evals;
+  int* info;
+  int m0;
+};
+
+struct BatchDesc {
+  int count;
+  int64_t prefix[kStages][TL_MAX_BATCH + 1];
+  InstanceJob job[TL_MAX_BATCH];
+};
+
+__device__ inline int find_job(const int64_t* prefix, int count, int64_t b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+#define TL_BATCH_LOCATE(stage)                                   \
+  const int64_t gb_ = blockIdx.x;                                \
+  const int ji_ = find_job(d->prefix[stage], d->count, gb_);     \
+  const InstanceJob& J = d->job[ji_];                            \
+  const int64_t lb = gb_ - d->prefix[stage][ji_];
+
+__global__ __launch_bounds__(256) void batch_basis_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kBasis)
+  dev::basis_body(J.basis, J.G, J.AG, J.SG, lb);
+}
+
+__global__ __launch_bounds__(256) void batch_direct_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kDirect)
+  dev::direct_body(J.pot.direct, J.pot.quad, J.pot.master, J.pot.P, (int)lb);
+}
+
+__global__ __launch_bounds__(256) void batch_fold_kernel(const BatchDesc* __restrict__ d) {
+  extern __shared__ double sh[];
+  TL_BATCH_LOCATE(kFold)
+  dev::fold_body(J.pot.fold, J.pot.quad, J.pot.master, J.pot.P, (int)(lb % J.T), (int)(lb / J.T),
+                 sh);
+}
+
+template <typename LowT>
+__global__ __launch_bounds__(256) void batch_slice_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kSlice)
+  dev::slice_body<LowT>(J.asmb.slice, (int)lb);
+}
+
+__global__ __launch_bounds__(256) void batch_contract_f64_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kContract)
+  dev::contract_f64_body(J.asmb.contract, (int)lb);
+}
+
+__global__ __launch_bounds__(256) void batch_contract_f32_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kContract)
+  dev::contract_f32_body(J.asmb.contract, (int)lb);
+}
+
+template <typename LowT, int S>
+__global__ __launch_bounds__(256) void batch_contract_split_kernel(
+    const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kContract)
+  dev::contract_split_body<LowT, S>(J.asmb.split, (int)lb);
+}
+
+__global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kReduce)
+  dev::reduce_partials_body(J.asmb.reduce, J.asmb.reduce_total, lb);
+}
+
+__global__ __launch_bounds__(256) void batch_combine_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kCombine)
+  dev::combine_periodic_body(J.asmb.combine, J.asmb.combine_total, lb);
+}
+
+__global__ __launch_bounds__(256) void batch_dft_kernel(const BatchDesc* __restrict__ d) {
+  extern __shared__ double tw[];
+  TL_BATCH_LOCATE(kDft)
+  dev::dft_axis_body<true, true>(J.dft, lb / J.dft_rchunks, lb % J.dft_rchunks, tw);
+}
+
+template <int MAXM>
+__global__ __launch_bounds__(MAXM * MAXM < 64 ? 64 : MAXM * MAXM) void batch_heigh_kernel(
+    const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kHeigh)
+  dev::heigh_body<MAXM>(J.Hb, J.Sb, J.m0, J.evals, nullptr, J.info, lb);
+}
+
+struct InstanceSizes {
+  Geometry g;
+  size_t pot_ws, asm_ws;
+};
+
+tl_status instance_sizes(const tl_system* s, tl_precision prec, int n_slices, int want,
+                         InstanceSizes* out) {
+  TL_TRY(digest(s, &out->g));
+  const Geometry& g = out->g;
+  if (g.mode != TL_MODE_PERIODIC) {
+    set_error("the batched path takes periodic-mode systems");
+    return TL_EUNSUPPORTED;
+  }
+  int axes = (g.L[0] > 1) + (g.L[1] > 1) + (g.L[2] > 1);
+  if (axes > 1 || (axes == 1 && g.L[0] == 1)) {
+    set_error("the batched path takes (L,1,1) lattices");
+    return TL_EUNSUPPORTED;
+  }
+  if (g.L[0] > 4096) {
+    set_error("the batched path takes L <= 4096");
+    return TL_EUNSUPPORTED;
+  }
+  if (!g.periodic[0] && g.L[0] > 1) {
+    set_error("batched lattice axis must be periodic");
+    return TL_EUNSUPPORTED;
+  }
+  if (!g.periodic[0]) {
+    set_error("the batched path needs a periodic x axis");
+    return TL_EUNSUPPORTED;
+  }
+  out->pot_ws = align_up(potential_workspace_bytes(g, s), 256);
+  out->asm_ws = align_up(assemble_workspace_bytes(g, prec, n_slices, want), 256);
+  return TL_OK;
+}
+
+}  // namespace
+
+}  // namespace tl
+
+using namespace tl;
+
+extern "C" tl_status tl_batch_plan_create(const tl_system* systems, int count, tl_precision prec,
+                                          int n_slices, int want_blocks, tl_batch_plan* out) {
+  clear_error();
+  TL_REQUIRE(systems && out, "null argument");
+  TL_REQUIRE(count >= 1 && count <= TL_MAX_BATCH, "count = %d outside [1, %d]", count,
+             TL_MAX_BATCH);
+  TL_REQUIRE(prec >= TL_FP64 && prec <= TL_SPLIT_FP16, "unknown precision %d", (int)prec);
+  if (want_blocks <= 0) want_blocks = kDefaultContractBlocks;
+  std::memset(out, 0, sizeof(*out));
+  out->count = count;
+  out->precision = (int)prec;
+  out->n_slices = (prec == TL_SPLIT_BF16 || prec == TL_SPLIT_FP16)
+                      ? (n_slices > 0 ? n_slices : (prec == TL_SPLIT_FP16 ? 5 : 6))
+                      : 0;
+  out->want_blocks = want_blocks;
+  out->desc_bytes = sizeof(BatchDesc);
+  for (int i = 0; i < count; ++i) {
+    InstanceSizes is;
+    tl_status st = instance_sizes(&systems[i], prec, out->n_slices, want_blocks, &is);
+    if (st != TL_OK) {
+      char msg[1024];
+      std::snprintf(msg, sizeof(msg), "instance %d: %s", i, tl_last_error());
+      set_error("%s", msg);
+      return st;
+    }
+    const Geometry& g = is.g;
+    out->basis_elems += g.basis_elems;
+    out->pot_elems += g.pot_elems;
+    out->hs_elems += 2 * g.block_elems;
+    out->eval_elems += (int64_t)g.L[0] * g.m0;
+    out->kblocks += g.L[0];
+    out->ws_bytes += is.pot_ws + is.asm_ws;
+    out->max_m0 = std::max(out->max_m0, g.m0);
+    out->max_len = std::max(out->max_len, g.L[0]);
+  }
+  return TL_OK;
+}
+
+extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int count,
+                                               const tl_batch_plan* plan,
+                                               const tl_batch_buffers* buf, void* host_desc,
+                                               size_t desc_bytes) {
+  clear_error();
+  TL_REQUIRE(systems && plan && buf && host_desc, "null argument");
+  TL_REQUIRE(count == plan->count, "count differs from the plan");
+  TL_REQUIRE(desc_bytes >= sizeof(BatchDesc), "descriptor buffer needs %zu bytes",
+             sizeof(BatchDesc));
+  TL_REQUIRE(buf->G && buf->AG && buf->SG && buf->P && buf->HS && buf->HSbar && buf->evals &&
+                 buf->info && buf->ws,
+             "null device buffer");
+  const tl_precision prec = (tl_precision)plan->precision;
+  std::vector<char> storage(sizeof(BatchDesc));
+  BatchDesc* d = (BatchDesc*)storage.data();
+  std::memset(d, 0, sizeof(BatchDesc));
+  d->count = count;
+  int64_t ob = 0, op = 0, ohs = 0, oev = 0, okb = 0;
+  size_t ows = 0;
+  size_t fold_shmem = 0;
+  for (int i = 0; i < count; ++i) {
+    const tl_system* s = &systems[i];
+    InstanceSizes is;
+    TL_TRY(instance_sizes(s, prec, plan->n_slices, plan->want_blocks, &is));
+    const Geometry& g = is.g;
+    InstanceJob& J = d->job[i];
+    make_basis_args(g, s, &J.basis);
+    J.G = buf->G + ob;
+    J.AG = buf->AG + ob;
+    J.SG = buf->SG + ob;
+    double* P = buf->P + op;
+    char* ws = (char*)buf->ws + ows;
+    TL_TRY(plan_potential(g, s, P, ws, is.pot_ws, &J.pot));
+    J.T = (int)g.pot_terms;
+    double* H = buf->HS + ohs;
+    double* S = H + g.block_elems;
+    TL_TRY(plan_assembly(g, J.G, J.AG, J.SG, P, prec, plan->n_slices, H, S, ws + is.pot_ws,
+                         is.asm_ws, plan->want_blocks, &J.asmb));
+    // one lattice axis: transform H and S (outer = 2) along L
+    double* Hbar = buf->HSbar + 2 * ohs;
+    J.dft.in = H;
+    J.dft.out = Hbar;
+    J.dft.len = g.L[0];
+    J.dft.inner = (int64_t)g.m0 * g.m0;
+    J.dft.real_in = 1;
+    J.dft_rchunks = (int)ceil_div(J.dft.inner, 256);
+    J.Hb = Hbar;
+    J.Sb = Hbar + 2 * g.block_elems;
+    J.evals = buf->evals + oev;
+    J.info = buf->info + okb;
+    J.m0 = g.m0;
+    // stage block counts of this instance
+    int64_t blocks[kStages];
+    blocks[kBasis] = ceil_div(g.basis_elems, 256);
+    blocks[kDirect] = J.pot.direct_blocks;
+    blocks[kFold] = (int64_t)J.T * J.pot.fold_slots;
+    blocks[kSlice] = J.asmb.slice_blocks;
+    blocks[kContract] = J.asmb.contract_blocks;
+    blocks[kReduce] = ceil_div(J.asmb.reduce_total, 256);
+    blocks[kCombine] = ceil_div(J.asmb.combine_total, 4);
+    blocks[kDft] = 2LL * g.L[0] * J.dft_rchunks;
+    blocks[kHeigh] = g.L[0];
+    for (int st = 0; st < kStages; ++st) d->prefix[st][i + 1] = d->prefix[st][i] + blocks[st];
+    fold_shmem = std::max(fold_shmem, J.pot.fold_shmem);
+    ob += g.basis_elems;
+    op += g.pot_elems;
+    ohs += 2 * g.block_elems;
+    oev += (int64_t)g.L[0] * g.m0;
+    okb += g.L[0];
+    ows += is.pot_ws + is.asm_ws;
+  }
+  std::memcpy(host_desc, d, sizeof(BatchDesc));
+  return TL_OK;
+}
+
+namespace {
+
+template <typename LowT>
+void launch_batch_split(int S, unsigned grid, const BatchDesc* d, hipStream_t stream) {
+  switch (S) {
+    case 2: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 2>), dim3(grid), dim3(256), 0, stream, d); break;
+    case 3: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 3>), dim3(grid), dim3(256), 0, stream, d); break;
+    case 4: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 4>), dim3(grid), dim3(256), 0, stream, d); break;
+    case 5: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 5>), dim3(grid), dim3(256), 0, stream, d); break;
+    case 6: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 6>), dim3(grid), dim3(256), 0, stream, d); break;
+    case 7: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 7>), dim3(grid), dim3(256), 0, stream, d); break;
+    default: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 8>), dim3(grid), dim3(256), 0, stream, d); break;
+  }
+}
+
+}  // namespace
+
+extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_desc,
+                                  const void* desc_dev, void* stream_) {
+  clear_error();
+  TL_REQUIRE(plan && host_desc && desc_dev, "null argument");
+  hipStream_t stream = (hipStream_t)stream_;
+  const BatchDesc* hd = (const BatchDesc*)host_desc;
+  const BatchDesc* d = (const BatchDesc*)desc_dev;
+  TL_REQUIRE(hd->count == plan->count, "descriptor does not match the plan");
+  auto blocks = [&](int st) { return (unsigned)hd->prefix[st][hd->count]; };
+  size_t fold_shmem = 0;
+  for (int i = 0; i < hd->count; ++i) fold_shmem = std::max(fold_shmem, hd->job[i].pot.fold_shmem);
+  const tl_precision prec = (tl_precision)plan->precision;
+  hipEvent_t ev0, ev1;
+  contraction_events(&ev0, &ev1);
+
+  hipLaunchKernelGGL(batch_basis_kernel, dim3(blocks(kBasis)), dim3(256), 0, stream, d);
+  TL_CHECK_LAUNCH();
+  if (blocks(kDirect)) {
+    hipLaunchKernelGGL(batch_direct_kernel, dim3(blocks(kDirect)), dim3(256), 0, stream, d);
+    TL_CHECK_LAUNCH();
+  }
+  if (blocks(kFold)) {
+    hipLaunchKernelGGL(batch_fold_kernel, dim3(blocks(kFold)), dim3(256), fold_shmem, stream, d);
+    TL_CHECK_LAUNCH();
+  }
+  if (prec == TL_SPLIT_BF16) {
+    hipLaunchKernelGGL(batch_slice_kernel<__bf16>, dim3(blocks(kSlice)), dim3(256), 0, stream, d);
+    TL_CHECK_LAUNCH();
+  } else if (prec == TL_SPLIT_FP16) {
+    hipLaunchKernelGGL(batch_slice_kernel<_Float16>, dim3(blocks(kSlice)), dim3(256), 0, stream,
+                       d);
+    TL_CHECK_LAUNCH();
+  }
+  if (ev0) TL_HIP(hipEventRecord(ev0, stream));
+  if (prec == TL_SPLIT_BF16)
+    launch_batch_split<__bf16>(plan->n_slices, blocks(kContract), d, stream);
+  else if (prec == TL_SPLIT_FP16)
+    launch_batch_split<_Float16>(plan->n_slices, blocks(kContract), d, stream);
+  else if (prec == TL_FP32)
+    hipLaunchKernelGGL(batch_contract_f32_kernel, dim3(blocks(kContract)), dim3(256), 0, stream, d);
+  else
+    hipLaunchKernelGGL(batch_contract_f64_kernel, dim3(blocks(kContract)), dim3(256), 0, stream, d);
+  TL_CHECK_LAUNCH();
+  if (ev1) TL_HIP(hipEventRecord(ev1, stream));
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3(blocks(kReduce)), dim3(256), 0, stream, d);
+  TL_CHECK_LAUNCH();
+  hipLaunchKernelGGL(batch_combine_kernel, dim3(blocks(kCombine)), dim3(256), 0, stream, d);
+  TL_CHECK_LAUNCH();
+  hipLaunchKernelGGL(batch_dft_kernel, dim3(blocks(kDft)), dim3(256),
+                     sizeof(double) * 2 * (size_t)plan->max_len, stream, d);
+  TL_CHECK_LAUNCH();
+  if (plan->max_m0 <= 8)
+    hipLaunchKernelGGL(batch_heigh_kernel<8>, dim3(blocks(kHeigh)), dim3(64), 0, stream, d);
+  else if (plan->max_m0 <= 16)
+    hipLaunchKernelGGL(batch_heigh_kernel<16>, dim3(blocks(kHeigh)), dim3(256), 0, stream, d);
+  else
+    hipLaunchKernelGGL(batch_heigh_kernel<32>, dim3(blocks(kHeigh)), dim3(1024), 0, stream, d);
+  TL_CHECK_LAUNCH();
+  return TL_OK;
+}

@@ -1,0 +1,328 @@
+// Device code of step a7 (batched generalized Hermitian eigensolver of the
+// k-block pencils), shared by the single-system and the batched launches.
+#pragma once
+#include "common.h"
+
+namespace tl {
+namespace dev {
+
+struct cx {
+  double re, im;
+};
+__device__ inline cx cmul(cx a, cx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline cx cconj(cx a) { return {a.re, -a.im}; }
+__device__ inline cx cadd(cx a, cx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline cx csub(cx a, cx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline cx cscale(cx a, double s) { return {a.re * s, a.im * s}; }
+__device__ inline double cabs2(cx a) { return a.re * a.re + a.im * a.im; }
+
+constexpr int kMaxSweeps = 60;
+
+// Partner of index x in round r of the round-robin ordering of `me` (even)
+// indices: me-1 meets r, every other pair {r+k, r-k} (mod me-1).
+__device__ inline int rr_partner(int x, int r, int me) {
+  const int n1 = me - 1;
+  if (x == n1) return r;
+  if (x == r) return n1;
+  int y = (2 * r - x) % n1;
+  return y < 0 ? y + n1 : y;
+}
+
+// Jacobi rotation zeroing A[p][q] of the Hermitian 2x2 [[a, b], [conj b, d]]
+// (Golub & Van Loan, sym.schur2, after removing the phase of b):
+// J = D R, D = diag(1, exp(-i phi)), R = [[c, s], [-s, c]], so
+// J[p][p] = c, J[q][p] = -s e^{-i phi}, J[p][q] = s, J[q][q] = c e^{-i phi};
+// the diagonal becomes a - t|b|, d + t|b|.  b = 0 (or a padding index q)
+// gives the identity.
+struct Rot {
+  double c, s, tb, ph_re, ph_im;
+};
+
+__device__ inline Rot make_rot(double a, double d, cx b, bool valid) {
+  Rot r = {1.0, 0.0, 0.0, 1.0, 0.0};
+  double b2 = cabs2(b);
+  if (!valid || !(b2 > 0.0)) return r;
+  double inv_ab = rsqrt(b2);
+  double tau = 0.5 * (d - a) * inv_ab;
+  double at = fabs(tau);
+  double t = at > 1e150 ? 0.5 / tau : copysign(1.0 / (at + sqrt(fma(tau, tau, 1.0))), tau);
+  r.c = rsqrt(fma(t, t, 1.0));
+  r.s = t * r.c;
+  r.tb = t * (b2 * inv_ab);
+  r.ph_re = b.re * inv_ab;
+  r.ph_im = -b.im * inv_ab;
+  return r;
+}
+
+// One k-block per workgroup; blk is the block index (H, S, evals, evecs and
+// info are indexed by it).
+template <int MAXM>
+__device__ inline void heigh_body(const double* __restrict__ H, const double* __restrict__ S,
+                                  int m, double* __restrict__ evals, double* __restrict__ evecs,
+                                  int* __restrict__ info, int64_t blk_) {
+  constexpr int LD = MAXM + 1;
+  // two copies of C and of V so that a Jacobi round needs one barrier
+  // (read one copy, write the other); L is the Cholesky factor.
+  constexpr bool kDouble = MAXM <= 16;
+  constexpr int NB = kDouble ? 2 : 1;
+  __shared__ cx Ab[NB][MAXM * LD];
+  __shared__ cx Vb[NB][MAXM * LD];
+  __shared__ cx B[MAXM * LD];
+  // round-robin schedule: partner and pair slot of every index in every round
+  __shared__ unsigned char s_partner[MAXM][MAXM];
+  __shared__ unsigned char s_slot[MAXM][MAXM];
+  __shared__ Rot s_rot[MAXM / 2];
+  __shared__ int rank_of[MAXM];
+  __shared__ int fail;
+  __shared__ double red[2];
+
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int64_t blk = blk_;
+  const int mm = m * m;
+  const cx* Hb = (const cx*)H + blk * mm;
+  const cx* Sb = S ? (const cx*)S + blk * mm : nullptr;
+  cx* A = Ab[0];
+  cx* V = Vb[0];
+
+  for (int e = tid; e < mm; e += nt) {
+    int i = e / m, j = e - i * m;
+    A[i * LD + j] = Hb[e];
+    B[i * LD + j] = Sb ? Sb[e] : cx{i == j ? 1.0 : 0.0, 0.0};
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
+
+  // 1. Cholesky, right-looking, lower triangle of B.
+  if (Sb) {
+    for (int k = 0; k < m; ++k) {
+      if (tid == 0) {
+        double d = B[k * LD + k].re;
+        if (!(d > 0.0) || !isfinite(d))
+          fail = k + 1;
+        else
+          B[k * LD + k] = {sqrt(d), 0.0};
+      }
+      __syncthreads();
+      if (fail) break;
+      double inv = 1.0 / B[k * LD + k].re;
+      for (int i = k + 1 + tid; i < m; i += nt) B[i * LD + k] = cscale(B[i * LD + k], inv);
+      __syncthreads();
+      int w = m - k - 1;
+      for (int e = tid; e < w * w; e += nt) {
+        int i = k + 1 + e / w, j = k + 1 + e % w;
+        if (j <= i) B[i * LD + j] = csub(B[i * LD + j], cmul(B[i * LD + k], cconj(B[j * LD + k])));
+      }
+      __syncthreads();
+    }
+  }
+  if (fail) {
+    for (int i = tid; i < m; i += nt) evals[blk * m + i] = NAN;
+    if (evecs)
+      for (int e = tid; e < mm; e += nt) ((cx*)evecs)[blk * mm + e] = {0.0, 0.0};
+    if (tid == 0) info[blk] = fail;
+    return;
+  }
+
+  // 2. C = L^-1 Hbar L^-H.  W = L^-1 Hbar in place in A, then Z = L^-1 W^H in
+  // V, C = Z^H back in A.
+  if (Sb) {
+    for (int i = 0; i < m; ++i) {
+      for (int j = tid; j < m; j += nt) {
+        cx s = A[i * LD + j];
+        for (int k = 0; k < i; ++k) s = csub(s, cmul(B[i * LD + k], A[k * LD + j]));
+        A[i * LD + j] = cscale(s, 1.0 / B[i * LD + i].re);
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < mm; e += nt) {
+      int i = e / m, j = e - i * m;
+      V[i * LD + j] = cconj(A[j * LD + i]);
+    }
+    __syncthreads();
+    for (int i = 0; i < m; ++i) {
+      for (int j = tid; j < m; j += nt) {
+        cx s = V[i * LD + j];
+        for (int k = 0; k < i; ++k) s = csub(s, cmul(B[i * LD + k], V[k * LD + j]));
+        V[i * LD + j] = cscale(s, 1.0 / B[i * LD + i].re);
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < mm; e += nt) {
+      int i = e / m, j = e - i * m;
+      A[i * LD + j] = cconj(V[j * LD + i]);
+    }
+    __syncthreads();
+  }
+  // Hermitian average (removes the rounding asymmetry), V = I.  The launch
+  // has at least m*m threads: thread e owns entry (e / m, e % m).
+  const bool owner = tid < mm;
+  const int ei = owner ? tid / m : 0, ej = owner ? tid - (tid / m) * m : 0;
+  {
+    cx mine = {0.0, 0.0};
+    if (owner) {
+      cx a = A[ei * LD + ej], b = A[ej * LD + ei];
+      mine = ei == ej ? cx{a.re, 0.0} : cscale(cadd(a, cconj(b)), 0.5);
+    }
+    __syncthreads();
+    if (owner) {
+      A[ei * LD + ej] = mine;
+      V[ei * LD + ej] = {ei == ej ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+  }
+
+  // 3. Jacobi sweeps with the round-robin ordering of the (even-padded)
+  // indices: in every round the me/2 rotations are formed by one thread each
+  // and shared through LDS, then every thread updates its own entry of C and
+  // of V from the four entries of its 2x2 coupling.
+  int converged = (m == 1);
+  int cur = 0;
+  const int me = m + (m & 1);
+  for (int e = tid; e < (me - 1) * me; e += nt) {
+    int r = e / me, x = e - r * me;
+    int y = rr_partner(x, r, me);
+    s_partner[r][x] = (unsigned char)y;
+    // slot: 0 for the pair containing me-1, else the distance k in {r+k, r-k}
+    int p = min(x, y);
+    int slot;
+    if (y == me - 1 || x == me - 1) {
+      slot = 0;
+    } else {
+      int k = (p - r) % (me - 1);
+      if (k < 0) k += me - 1;
+      slot = k <= (me - 1) / 2 ? k : (me - 1) - k;
+    }
+    s_slot[r][x] = (unsigned char)slot;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+    // convergence: off-diagonal Frobenius norm against the whole norm
+    if (tid < 2) red[tid] = 0.0;
+    __syncthreads();
+    double off = 0.0, all = 0.0;
+    if (owner) {
+      double v = cabs2(A[ei * LD + ej]);
+      all = v;
+      if (ei != ej) off = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      all += __shfl_xor(all, o);
+    }
+    if ((tid & 63) == 0) {
+      atomicAdd(&red[0], off);
+      atomicAdd(&red[1], all);
+    }
+    __syncthreads();
+    if (red[0] <= 1e-32 * red[1]) {
+      converged = 1;
+      break;
+    }
+    for (int r = 0; r < me - 1; ++r) {
+      if (tid < me / 2) {
+        // pair of slot tid in round r
+        int p, q;
+        if (tid == 0) {
+          p = r;
+          q = me - 1;
+        } else {
+          p = (r + tid) % (me - 1);
+          q = (r - tid + me - 1) % (me - 1);
+        }
+        if (p > q) {
+          int t = p;
+          p = q;
+          q = t;
+        }
+        bool valid = q < m;
+        cx b = valid ? A[p * LD + q] : cx{0.0, 0.0};
+        double a = valid ? A[p * LD + p].re : 0.0;
+        double d = valid ? A[q * LD + q].re : 0.0;
+        s_rot[tid] = make_rot(a, d, b, valid);
+      }
+      __syncthreads();
+      cx na = {0.0, 0.0}, nv = {0.0, 0.0};
+      if (owner) {
+        const int i = ei, j = ej;
+        const int ip = s_partner[r][i], jp = s_partner[r][j];
+        const Rot ri = s_rot[s_slot[r][i]];
+        const Rot rj = s_rot[s_slot[r][j]];
+        // column i of J: J[i][i] and J[ip][i]
+        const bool fi = i < ip, fj = j < jp;
+        cx Jii = fi ? cx{ri.c, 0.0} : cx{ri.ph_re * ri.c, ri.ph_im * ri.c};
+        cx Jpi = fi ? cx{-ri.ph_re * ri.s, -ri.ph_im * ri.s} : cx{ri.s, 0.0};
+        cx Jjj = fj ? cx{rj.c, 0.0} : cx{rj.ph_re * rj.c, rj.ph_im * rj.c};
+        cx Jpj = fj ? cx{-rj.ph_re * rj.s, -rj.ph_im * rj.s} : cx{rj.s, 0.0};
+        if (j == i || j == ip) {
+          // inside one rotated 2x2 block: exact diagonal form
+          if (i == j) na = {A[i * LD + i].re + (fi ? -ri.tb : ri.tb), 0.0};
+        } else {
+          // sum over a in {i, ip}, b in {j, jp} of conj(J[a][i]) A[a][b] J[b][j]
+          const bool jin = jp < m, iin = ip < m;
+          cx t0 = cmul(A[i * LD + j], Jjj);
+          if (jin) t0 = cadd(t0, cmul(A[i * LD + jp], Jpj));
+          na = cmul(cconj(Jii), t0);
+          if (iin) {
+            cx t1 = cmul(A[ip * LD + j], Jjj);
+            if (jin) t1 = cadd(t1, cmul(A[ip * LD + jp], Jpj));
+            na = cadd(na, cmul(cconj(Jpi), t1));
+          }
+        }
+        nv = cmul(V[i * LD + j], Jjj);
+        if (jp < m) nv = cadd(nv, cmul(V[i * LD + jp], Jpj));
+      }
+      if (kDouble) {
+        cur ^= 1;
+        A = Ab[cur];
+        V = Vb[cur];
+        if (owner) {
+          A[ei * LD + ej] = na;
+          V[ei * LD + ej] = nv;
+        }
+        __syncthreads();
+      } else {
+        __syncthreads();
+        if (owner) {
+          A[ei * LD + ej] = na;
+          V[ei * LD + ej] = nv;
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  // 4. sort ascending, back-transform u = L^-H v, write out.
+  for (int i = tid; i < m; i += nt) {
+    double li = A[i * LD + i].re;
+    int rk = 0;
+    for (int k = 0; k < m; ++k) {
+      double lk = A[k * LD + k].re;
+      if (lk < li || (lk == li && k < i)) ++rk;
+    }
+    rank_of[i] = rk;
+    evals[blk * m + rk] = li;
+  }
+  if (tid == 0) info[blk] = converged ? 0 : -1;
+  __syncthreads();
+  if (evecs) {
+    if (Sb) {
+      for (int i = m - 1; i >= 0; --i) {
+        for (int j = tid; j < m; j += nt) {
+          cx s = V[i * LD + j];
+          for (int k = i + 1; k < m; ++k) s = csub(s, cmul(cconj(B[k * LD + i]), V[k * LD + j]));
+          V[i * LD + j] = cscale(s, 1.0 / B[i * LD + i].re);
+        }
+        __syncthreads();
+      }
+    }
+    cx* out = (cx*)evecs + blk * mm;
+    for (int e = tid; e < mm; e += nt) {
+      int i = e / m, j = e - i * m;
+      out[i * m + rank_of[j]] = V[i * LD + j];
+    }
+  }
+}
+
+}  // namespace dev
+}  // namespace tl

@@ -1,0 +1,55 @@
+// Host-side launch plans shared by the single-system entry points and the
+// batched path: every stage is described by the kernel-argument structs it
+// launches with, built once on the host.
+#pragma once
+#include "common.h"
+#include "dev_assemble.h"
+#include "dev_basis.h"
+#include "dev_fft.h"
+#include "dev_heigh.h"
+#include "dev_potential.h"
+
+namespace tl {
+
+constexpr int kDefaultContractBlocks = 512;  // workgroups the contraction aims for
+
+struct AssemblyPlan {
+  tl_precision prec;
+  int n_slices;
+  dev::ContractArgs contract;
+  dev::SliceArgs slice;
+  dev::SplitArgs split;
+  int contract_blocks, slice_blocks;
+  dev::ReduceArgs reduce;
+  int64_t reduce_total;
+  dev::CombineArgs combine;
+  int64_t combine_total;
+};
+
+size_t assemble_workspace_bytes(const Geometry& g, tl_precision prec, int n_slices,
+                                int want_blocks);
+tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, const double* SG,
+                        const double* P, tl_precision prec, int n_slices, double* H, double* S,
+                        void* ws, size_t ws_bytes, int want_blocks, AssemblyPlan* out);
+tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream);
+void contraction_events(hipEvent_t* start, hipEvent_t* stop);
+
+struct PotentialPlan {
+  dev::QuadArgs quad;
+  dev::DirectArgs direct;
+  int direct_blocks;
+  dev::FoldArgs fold;
+  int fold_slots;
+  size_t fold_shmem;
+  double* master;
+  double* P;
+  int box_dim0;   // open dim 0: nuclei summed directly (single-system path only)
+};
+
+size_t potential_workspace_bytes(const Geometry& g, const tl_system* s);
+tl_status plan_potential(const Geometry& g, const tl_system* s, double* P, void* ws,
+                         size_t ws_bytes, PotentialPlan* out);
+
+void make_basis_args(const Geometry& g, const tl_system* s, dev::BasisArgs* p);
+
+}  // namespace tl

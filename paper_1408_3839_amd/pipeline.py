@@ -99,3 +99,67 @@ class PeriodicPipeline:
     def replay(self):
         self.graph.replay()
         return self.evals
+
+
+class BatchPipeline:
+    """Buffers and descriptor for a ragged batch of periodic (L,1,1) lattices;
+    run() enqueues the whole chain with one launch per stage."""
+
+    def __init__(self, systems, precision: str = "fp64", n_slices: int = 0,
+                 want_blocks: int = 0, device: str = "cuda:0"):
+        import numpy as np
+        tl.load()
+        self.systems = list(systems)
+        self.sarr = tl.SystemArray(self.systems)
+        self.device = torch.device(device)
+        self.plan = tl.tl_batch_plan_create(self.sarr, tl.PRECISIONS[precision], n_slices,
+                                            want_blocks)
+        p = self.plan
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.buf = {
+            "G": torch.empty(max(1, p.basis_elems), **f64),
+            "AG": torch.empty(max(1, p.basis_elems), **f64),
+            "SG": torch.empty(max(1, p.basis_elems), **f64),
+            "P": torch.empty(max(1, p.pot_elems), **f64),
+            "HS": torch.empty(max(1, p.hs_elems), **f64),
+            "HSbar": torch.empty(max(1, 2 * p.hs_elems), **f64),
+            "evals": torch.empty(max(1, p.eval_elems), **f64),
+            "info": torch.empty(max(1, p.kblocks), dtype=torch.int32, device=self.device),
+            "ws": torch.empty(max(1, p.ws_bytes), dtype=torch.uint8, device=self.device),
+        }
+        self.host_desc = np.zeros(p.desc_bytes, dtype=np.uint8)
+        tl.tl_batch_write_descriptor(self.sarr, p, self.buf, self.host_desc)
+        self.desc = torch.from_numpy(self.host_desc).to(self.device)
+        torch.cuda.synchronize(self.device)
+        # per-instance views
+        self.views = []
+        oh = oe = ok = 0
+        for s in self.systems:
+            L, m0 = int(s.L[0]), s.m0
+            be = L * m0 * m0
+            self.views.append({
+                "H": self.buf["HS"][oh:oh + be].view(L, 1, 1, m0, m0),
+                "S": self.buf["HS"][oh + be:oh + 2 * be].view(L, 1, 1, m0, m0),
+                "evals": self.buf["evals"][oe:oe + L * m0].view(L, m0),
+                "info": self.buf["info"][ok:ok + L],
+            })
+            oh += 2 * be
+            oe += L * m0
+            ok += L
+
+    def run(self, stream=None):
+        tl.tl_batch_run(self.plan, self.host_desc, self.desc, stream)
+
+    def capture(self):
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            self.run()
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()

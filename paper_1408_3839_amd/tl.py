@@ -61,6 +61,24 @@ class TlSizes(ctypes.Structure):
     ]
 
 
+TL_MAX_BATCH = 256
+
+
+class TlBatchPlan(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int), ("precision", ctypes.c_int), ("n_slices", ctypes.c_int),
+        ("want_blocks", ctypes.c_int), ("max_m0", ctypes.c_int), ("max_len", ctypes.c_int),
+        ("basis_elems", ctypes.c_int64), ("pot_elems", ctypes.c_int64),
+        ("hs_elems", ctypes.c_int64), ("eval_elems", ctypes.c_int64), ("kblocks", ctypes.c_int64),
+        ("ws_bytes", ctypes.c_size_t), ("desc_bytes", ctypes.c_size_t),
+    ]
+
+
+class TlBatchBuffers(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("G", "AG", "SG", "P", "HS", "HSbar", "evals", "info", "ws")]
+
+
 # name -> (restype, argtypes) of every exported symbol of include/tl.h
 SIGNATURES = {
     "tl_version": (ctypes.c_char_p, []),
@@ -89,6 +107,15 @@ SIGNATURES = {
     "tl_batched_heigh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "tl_batch_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_int,
+                                            ctypes.POINTER(TlBatchPlan)]),
+    "tl_batch_write_descriptor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                                 ctypes.POINTER(TlBatchPlan),
+                                                 ctypes.POINTER(TlBatchBuffers), ctypes.c_void_p,
+                                                 ctypes.c_size_t]),
+    "tl_batch_run": (ctypes.c_int, [ctypes.POINTER(TlBatchPlan), ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _lib = None
@@ -262,3 +289,43 @@ def tl_block_fft(inp, L1, L2, L3, m0, batch, out, ws=None, ws_bytes=0, stream=No
 def tl_batched_heigh(H, S, count, m0, evals, evecs, info, stream=None):
     _check(load().tl_batched_heigh(_ptr(H), _ptr(S), int(count), int(m0), _ptr(evals),
                                    _ptr(evecs), _ptr(info), _stream(stream)), "tl_batched_heigh")
+
+
+class SystemArray:
+    """A contiguous C array of TlSystem for the batched entry points."""
+
+    def __init__(self, systems):
+        self.handles = [SystemHandle(s) for s in systems]
+        self.array = (TlSystem * len(systems))(*[h.struct for h in self.handles])
+
+    @property
+    def ptr(self):
+        return ctypes.cast(self.array, ctypes.c_void_p)
+
+    def __len__(self):
+        return len(self.handles)
+
+
+def tl_batch_plan_create(systems, precision=TL_FP64, n_slices=0, want_blocks=0) -> TlBatchPlan:
+    arr = systems if isinstance(systems, SystemArray) else SystemArray(systems)
+    plan = TlBatchPlan()
+    _check(load().tl_batch_plan_create(arr.ptr, len(arr), int(precision), int(n_slices),
+                                       int(want_blocks), ctypes.byref(plan)),
+           "tl_batch_plan_create")
+    return plan
+
+
+def tl_batch_write_descriptor(systems, plan, buffers: dict, host_desc) -> None:
+    """buffers: name -> device tensor (G AG SG P HS HSbar evals info ws);
+    host_desc: writable host buffer (numpy uint8 array) of plan.desc_bytes."""
+    arr = systems if isinstance(systems, SystemArray) else SystemArray(systems)
+    b = TlBatchBuffers(*[_ptr(buffers[n]) for n in
+                         ("G", "AG", "SG", "P", "HS", "HSbar", "evals", "info", "ws")])
+    _check(load().tl_batch_write_descriptor(arr.ptr, len(arr), ctypes.byref(plan),
+                                            ctypes.byref(b), host_desc.ctypes.data,
+                                            host_desc.nbytes), "tl_batch_write_descriptor")
+
+
+def tl_batch_run(plan, host_desc, desc_dev, stream=None) -> None:
+    _check(load().tl_batch_run(ctypes.byref(plan), host_desc.ctypes.data, _ptr(desc_dev),
+                               _stream(stream)), "tl_batch_run")

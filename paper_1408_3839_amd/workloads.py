@@ -184,7 +184,7 @@ def _finish(name, mode, L, periodic, n, h, x0, a, K, nuc_pos, nuc_Z, cell_origin
 
 def periodic_system(name: str, L, a, h: float, box_len, sites, Z, m0: int,
                     alpha_range, R: int, seed: int, K=None,
-                    periodic=None) -> System:
+                    periodic=None, quad_rho=None) -> System:
     """Periodic (torus) lattice in the dims with L > 1 (or as given by
     `periodic`), open Dirichlet box of length box_len[l] in the others."""
     L = np.asarray(L, dtype=np.int64)
@@ -211,8 +211,11 @@ def periodic_system(name: str, L, a, h: float, box_len, sites, Z, m0: int,
     ext = np.array([(K[d] + 0.5) * a[d] + np.max(np.abs(sites[:, d])) if periodic[d]
                     else 0.5 * n[d] * h + np.max(np.abs(sites[:, d])) for d in range(3)])
     rho_max = float(np.sqrt(np.sum(ext ** 2)))
+    rho_min = 0.5 * h
+    if quad_rho is not None:      # one table shared by a family of systems
+        rho_min, rho_max = quad_rho
     return _finish(name, "periodic", L, periodic, n, h, x0, a, K, sites, Z, None,
-                   centers, ls, alphas, coef, R, 0.5 * h, rho_max, seed)
+                   centers, ls, alphas, coef, R, rho_min, rho_max, seed)
 
 
 def box_chain_system(name: str, ncell: int, spacing: float, Z_pattern, h: float,
@@ -268,9 +271,11 @@ def batch_instance(i: int) -> System:
     m0 = int(rng.choice([4, 8, 13]))
     h = 0.0625
     a = round(float(rng.uniform(1.6, 2.4)) / h) * h
+    # one exponential-sum table for the whole batch: distances up to the
+    # largest chain ((256 + 1/2) * 2.4 bohr) plus the transverse box
     return periodic_system(f"c4_inst{i}_L{L}_m{m0}", [L, 1, 1], [a, 0, 0], h,
                            [0, 16.0, 16.0], [[0, 0, 0]], [1.0], m0, (0.1, 30.0), 24,
-                           seed=4000 + i)
+                           seed=4000 + i, quad_rho=(0.5 * h, 640.0))
 
 
 def batch(count: int = 64) -> List[System]:
