@@ -112,10 +112,11 @@ SplitPlan make_split_plan(const Geometry& g, const Plan& plan, int s, size_t bas
   SplitPlan sp;
   size_t off = base;
   for (int d = 0; d < 3; ++d) {
+    const size_t ld = align_up((size_t)g.n[d], kSliceAlign);
     sp.xs_off[d] = off;
-    off += align_up(2 * (size_t)s * plan.M[d] * g.n[d], 256);
+    off += align_up(2 * (size_t)s * plan.M[d] * ld, 256);
     sp.ys_off[d] = off;
-    off += align_up(2 * (size_t)s * g.m0 * g.n[d], 256);
+    off += align_up(2 * (size_t)s * g.m0 * ld, 256);
     sp.xsc_off[d] = off;
     off += align_up(sizeof(double) * (size_t)plan.M[d], 256);
     sp.ysc_off[d] = off;
@@ -202,6 +203,7 @@ tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, co
       sa.yscale[d] = (double*)(wsb + sp.ysc_off[d]);
       sa.n[d] = g.n[d];
       sa.M[d] = plan.M[d];
+      sa.ld[d] = (int)align_up((size_t)g.n[d], kSliceAlign);
     }
     for (int d = 0; d < 3; ++d) {
       sa.rows_begin[d] = rb;
@@ -224,6 +226,7 @@ tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, co
       r.yscale = (const double*)(wsb + sp.ysc_off[d]);
       r.part = a.d[d].part;
       r.n = g.n[d];
+      r.ld = (int)align_up((size_t)g.n[d], kSliceAlign);
       r.S = g.shifts[d];
       r.cn = a.d[d].cn;
       r.M = plan.M[d];

@@ -230,8 +230,7 @@ __device__ inline void contract_f32_body(const ContractArgs& a, int b) {
 // products with a + b <= s + 1 are formed (triangular truncation).
 
 constexpr int kMaxSlices = 8;
-constexpr int kSKT = 32;             // nodes per LDS stage = one MFMA K step
-constexpr int kSLD = kSKT + 8;       // padded LDS row (elements)
+constexpr int kSliceAlign = 8;       // slice rows padded to a multiple of 8 nodes
 
 template <typename T>
 struct LowTraits;
@@ -253,7 +252,7 @@ struct SliceArgs {
   void* ys[3];          // [s][m0][n] slices of G rows
   double* xscale[3];    // [M]
   double* yscale[3];    // [m0]
-  int n[3], M[3];
+  int n[3], M[3], ld[3];  // ld: padded row stride of the slices
   int rows_begin[7];    // X rows of dims 0..2, then G rows of dims 0..2
   int m0, T, s;
 };
@@ -296,24 +295,29 @@ __device__ inline void slice_body(const SliceArgs& a, int b) {
   if (threadIdx.x == 0) (isx ? a.xscale[d] : a.yscale[d])[row] = sigma;
   LowT* out = (LowT*)(isx ? a.xs[d] : a.ys[d]);
   const int64_t rows = isx ? a.M[d] : a.m0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  const int ld = a.ld[d];
+  for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+    if (i >= n) {  // zero padding up to the aligned stride
+      for (int q = 1; q <= a.s; ++q) out[((int64_t)(q - 1) * rows + row) * ld + i] = (LowT)0.0f;
+      continue;
+    }
     double v = (pot ? pot[i] * base[i] : base[i]) * inv;
     for (int q = 1; q <= a.s; ++q) {
       double sc = ldexp(1.0, q * beta);
       double nk = rint(v * sc);
       v = fma(-nk, ldexp(1.0, -q * beta), v);
-      out[((int64_t)(q - 1) * rows + row) * n + i] = (LowT)nk;
+      out[((int64_t)(q - 1) * rows + row) * ld + i] = (LowT)nk;
     }
   }
 }
 
 struct SplitDimArgs {
-  const void* xs;       // [s][M][n]
-  const void* ys;       // [s][m0][n]
+  const void* xs;       // [s][M][ld]
+  const void* ys;       // [s][m0][ld]
   const double* xscale;
   const double* yscale;
   double* part;
-  int n, S, cn, M, N, kchunk, ks, tiles_n, block_begin;
+  int n, ld, S, cn, M, N, kchunk, ks, tiles_n, block_begin;
 };
 struct SplitArgs {
   SplitDimArgs d[3];
@@ -340,12 +344,26 @@ struct Vec8<_Float16> {
   }
 };
 
+template <typename T, int N>
+struct VecN {
+  typedef T type __attribute__((ext_vector_type(N)));
+};
+
+// Stages of 64 nodes (32 for more than six slices, to fit LDS); a thread
+// stages NPT consecutive nodes of one X row and of one Y column per slice
+// with one vector load and one vector LDS store each.  All products of a
+// level are accumulated in FP32 over the stage (exact for the integer
+// slices, see above) and added once to the level's FP64 accumulator.
 template <typename LowT, int S>
 __device__ inline void contract_split_body(const SplitArgs& a, int b) {
   typedef typename Vec8<LowT>::type v8;
   constexpr int beta = LowTraits<LowT>::beta;
-  __shared__ __attribute__((aligned(16))) LowT Xl[S][kBM][kSLD];
-  __shared__ __attribute__((aligned(16))) LowT Yl[S][kBN][kSLD];
+  constexpr int STG = S <= 6 ? 64 : 32;
+  constexpr int NPT = STG / 8;
+  constexpr int LDS_ROW = STG + 8;
+  typedef typename VecN<LowT, NPT>::type vrun;
+  __shared__ __attribute__((aligned(16))) LowT Xl[S][kBM][LDS_ROW];
+  __shared__ __attribute__((aligned(16))) LowT Yl[S][kBN][LDS_ROW];
   const int dd = b >= a.d[2].block_begin ? 2 : (b >= a.d[1].block_begin ? 1 : 0);
   const SplitDimArgs& p = a.d[dd];
   const int local = b - p.block_begin;
@@ -361,36 +379,52 @@ __device__ inline void contract_split_body(const SplitArgs& a, int b) {
   const int wm = wave >> 1, wn = wave & 1;
   const LowT* xs = (const LowT*)p.xs;
   const LowT* ys = (const LowT*)p.ys;
-  // staging: thread stages 4 consecutive nodes of one X row and one Y column
-  const int sr = tid >> 3;             // row / column within the tile (0..31)
-  const int sk = (tid & 7) * 4;        // first node within the stage
+  const int sr = tid >> 3;              // row / column within the tile (0..31)
+  const int sk = (tid & 7) * NPT;       // first node of the thread's run
   const int xrow = row0 + sr, ycol = col0 + sr;
   const bool xok = xrow < p.M, yok = ycol < p.N;
   const int mu = yok ? ycol / p.S : 0;
   const int ysh = yok ? (ycol - mu * p.S) * p.cn : 0;
-  LowT xr[S][4], yr[S][4];
+  const int64_t xstride = (int64_t)p.M * p.ld, ystride = (int64_t)a.m0 * p.ld;
+  const LowT* xbase = xs + (int64_t)xrow * p.ld;
+  const LowT* ybase = ys + (int64_t)mu * p.ld;
+  vrun xr[S], yr[S];
   auto stage = [&](int k0) {
+    const int i0 = k0 + sk;
+    // X: rows are padded to a multiple of 8 nodes, runs are aligned
+    if (xok && i0 + NPT <= kend) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int i = k0 + sk + e;
-      const bool in_k = i < kend;
-      int src = i - ysh;
-      if (src < 0) src += p.n;
+      for (int q = 0; q < S; ++q) xr[q] = *(const vrun*)(xbase + q * xstride + i0);
+    } else {
 #pragma unroll
-      for (int q = 0; q < S; ++q) {
-        xr[q][e] = (xok && in_k) ? xs[((int64_t)q * p.M + xrow) * p.n + i] : (LowT)0.0f;
-        yr[q][e] = (yok && in_k) ? ys[((int64_t)q * a.m0 + mu) * p.n + src] : (LowT)0.0f;
+      for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int e = 0; e < NPT; ++e)
+          xr[q][e] = (xok && i0 + e < kend) ? xbase[q * xstride + i0 + e] : (LowT)0.0f;
+    }
+    // Y: the cyclic shift may misalign the run or wrap around the torus
+    int src0 = i0 - ysh;
+    if (src0 < 0) src0 += p.n;
+    if (yok && i0 + NPT <= kend && src0 % NPT == 0 && src0 + NPT <= p.n) {
+#pragma unroll
+      for (int q = 0; q < S; ++q) yr[q] = *(const vrun*)(ybase + q * ystride + src0);
+    } else {
+#pragma unroll
+      for (int e = 0; e < NPT; ++e) {
+        int src = src0 + e;
+        if (src >= p.n) src -= p.n;
+        const bool ok = yok && i0 + e < kend;
+#pragma unroll
+        for (int q = 0; q < S; ++q) yr[q][e] = ok ? ybase[q * ystride + src] : (LowT)0.0f;
       }
     }
   };
   auto commit = [&]() {
 #pragma unroll
-    for (int q = 0; q < S; ++q)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        Xl[q][sr][sk + e] = xr[q][e];
-        Yl[q][sr][sk + e] = yr[q][e];
-      }
+    for (int q = 0; q < S; ++q) {
+      *(vrun*)&Xl[q][sr][sk] = xr[q];
+      *(vrun*)&Yl[q][sr][sk] = yr[q];
+    }
   };
   double acc[S][4];
 #pragma unroll
@@ -400,24 +434,32 @@ __device__ inline void contract_split_body(const SplitArgs& a, int b) {
   stage(kbeg);
   commit();
   __syncthreads();
-  for (int k0 = kbeg; k0 < kend; k0 += kSKT) {
-    const bool more = k0 + kSKT < kend;
-    if (more) stage(k0 + kSKT);
-    v8 av[S], bv[S];
+  for (int k0 = kbeg; k0 < kend; k0 += STG) {
+    const bool more = k0 + STG < kend;
+    if (more) stage(k0 + STG);
+    f32x4 c32[S];
 #pragma unroll
-    for (int q = 0; q < S; ++q) {
-      av[q] = *(const v8*)&Xl[q][wm * 16 + (lane & 15)][8 * (lane >> 4)];
-      bv[q] = *(const v8*)&Yl[q][wn * 16 + (lane & 15)][8 * (lane >> 4)];
+    for (int l = 0; l < S; ++l) c32[l] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kstep = 0; kstep < STG / 32; ++kstep) {
+      v8 av[S], bv[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        av[q] = *(const v8*)&Xl[q][wm * 16 + (lane & 15)][32 * kstep + 8 * (lane >> 4)];
+        bv[q] = *(const v8*)&Yl[q][wn * 16 + (lane & 15)][32 * kstep + 8 * (lane >> 4)];
+      }
+      // level l = qa + qb (0-based slices), l = 0..S-1; consecutive MFMAs
+      // feed different levels so that none waits on the previous result
+#pragma unroll
+      for (int qa = 0; qa < S; ++qa)
+#pragma unroll
+        for (int qb = 0; qa + qb < S; ++qb)
+          c32[qa + qb] = Vec8<LowT>::mfma(av[qa], bv[qb], c32[qa + qb]);
     }
-    // level l = qa + qb (0-based slices), l = 0..S-1
 #pragma unroll
-    for (int l = 0; l < S; ++l) {
-      f32x4 c32 = {0.f, 0.f, 0.f, 0.f};
+    for (int l = 0; l < S; ++l)
 #pragma unroll
-      for (int qa = 0; qa <= l; ++qa) c32 = Vec8<LowT>::mfma(av[qa], bv[l - qa], c32);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[l][r] += (double)c32[r];
-    }
+      for (int r = 0; r < 4; ++r) acc[l][r] += (double)c32[l][r];
     __syncthreads();
     if (more) commit();
     __syncthreads();
