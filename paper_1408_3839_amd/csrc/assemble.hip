@@ -134,7 +134,6 @@ int default_slices(tl_precision prec) { return prec == TL_SPLIT_FP16 ? 5 : 6; }
 
 size_t assemble_workspace_bytes(const Geometry& g, tl_precision prec, int n_slices,
                                 int want_blocks) {
-  if (g.mode != TL_MODE_PERIODIC) return 0;
   Plan plan = make_plan(g, want_blocks);
   if (!is_split(prec)) return plan.bytes;
   int S = n_slices > 0 ? n_slices : default_slices(prec);
@@ -342,7 +341,9 @@ extern "C" tl_status tl_assemble_workspace_bytes(const tl_system* sys, tl_precis
   TL_REQUIRE(bytes != nullptr, "null output");
   tl::Geometry g;
   TL_TRY(tl::digest(sys, &g));
-  *bytes = tl::assemble_workspace_bytes(g, prec, n_slices, tl::kDefaultContractBlocks);
+  *bytes = g.mode == TL_MODE_BOX
+               ? tl::box_workspace_bytes(g)
+               : tl::assemble_workspace_bytes(g, prec, n_slices, tl::kDefaultContractBlocks);
   return TL_OK;
 }
 
@@ -361,6 +362,6 @@ extern "C" tl_status tl_assemble_core_hamiltonian_block(const tl_system* sys, co
   if (g.mode == TL_MODE_PERIODIC)
     return tl::assemble_periodic(g, G_dev, AG_dev, SG_dev, P_dev, prec, n_slices, H_dev, S_dev,
                                  ws_dev, ws_bytes, (hipStream_t)stream);
-  tl::set_error("box-mode assembly is not available yet");
-  return TL_EUNSUPPORTED;
+  return tl::assemble_box(g, sys, G_dev, AG_dev, SG_dev, P_dev, prec, H_dev, S_dev, ws_dev,
+                         ws_bytes, (hipStream_t)stream);
 }

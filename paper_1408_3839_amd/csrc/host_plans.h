@@ -52,4 +52,9 @@ tl_status plan_potential(const Geometry& g, const tl_system* s, double* P, void*
 
 void make_basis_args(const Geometry& g, const tl_system* s, dev::BasisArgs* p);
 
+size_t box_workspace_bytes(const Geometry& g);
+tl_status assemble_box(const Geometry& g, const tl_system* s, const double* G, const double* AG,
+                       const double* SG, const double* P, tl_precision prec, double* H,
+                       double* S, void* ws, size_t ws_bytes, hipStream_t stream);
+
 }  // namespace tl

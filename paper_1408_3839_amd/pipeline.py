@@ -163,3 +163,37 @@ class BatchPipeline:
 
     def replay(self):
         self.graph.replay()
+
+
+class BoxPipeline:
+    """Buffers and calls for an open-boundary chain: basis, potential and the
+    full N_b x N_b core Hamiltonian and mass matrix."""
+
+    def __init__(self, sys, device: str = "cuda:0"):
+        if sys.mode != "box":
+            raise ValueError("BoxPipeline needs a box-mode system")
+        tl.load()
+        self.sys = sys
+        self.handle = tl.SystemHandle(sys)
+        self.device = torch.device(device)
+        sz = tl.tl_query_sizes(self.handle)
+        self.sizes = sz
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.G = torch.empty(sz["basis_elems"], **f64)
+        self.AG = torch.empty(sz["basis_elems"], **f64)
+        self.SG = torch.empty(sz["basis_elems"], **f64)
+        self.P = torch.empty(sz["pot_elems"], **f64)
+        self.pot_ws_bytes = tl.tl_potential_workspace_bytes(self.handle)
+        self.pot_ws = torch.empty(max(1, self.pot_ws_bytes), dtype=torch.uint8, device=self.device)
+        self.asm_ws_bytes = tl.tl_assemble_workspace_bytes(self.handle, tl.TL_FP64, 0)
+        self.asm_ws = torch.empty(max(1, self.asm_ws_bytes), dtype=torch.uint8, device=self.device)
+        self.Nb = int(sz["basis_rows"][0])
+        self.H = torch.empty(self.Nb, self.Nb, **f64)
+        self.S = torch.empty(self.Nb, self.Nb, **f64)
+
+    def run(self, stream=None):
+        tl.tl_build_basis(self.handle, self.G, self.AG, self.SG, stream)
+        tl.tl_lattice_sum_potential(self.handle, self.P, self.pot_ws, self.pot_ws_bytes, stream)
+        tl.tl_assemble_core_hamiltonian_block(self.handle, self.G, self.AG, self.SG, self.P,
+                                              tl.TL_FP64, 0, self.H, self.S, self.asm_ws,
+                                              self.asm_ws_bytes, stream)

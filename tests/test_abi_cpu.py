@@ -97,3 +97,17 @@ def test_workspace_queries():
         assert tl.tl_assemble_workspace_bytes(s) % 256 == 0
     assert tl.tl_block_fft_workspace_bytes(64, 1, 1, 8, 2) == 0
     assert tl.tl_block_fft_workspace_bytes(8, 8, 8, 10, 2) == 8 * 2 * 512 * 100 * 2
+
+
+def test_box_mode_queries_and_rejections():
+    s = wl.config(3)
+    z = tl.tl_query_sizes(s)
+    nb = z["basis_rows"][0]
+    assert nb == 2048
+    wb = tl.tl_assemble_workspace_bytes(s)
+    assert wb > 0 and wb % 256 == 0
+    # the open-boundary assembly runs in FP64 only; the check precedes any launch
+    _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EUNSUPPORTED, s, 8, 8, 8, 8,
+            tl.TL_SPLIT_BF16, 6, 8, 8, 8, wb, 0)
+    _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EWORKSPACE, s, 8, 8, 8, 8,
+            tl.TL_FP64, 0, 8, 8, 8, wb - 256, 0)
