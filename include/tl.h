@@ -222,6 +222,33 @@ tl_status tl_batched_heigh(const double* H_dev, const double* S_dev, int count, 
                            double* evals_dev, double* evecs_dev, int* info_dev, void* stream);
 
 /*
+ * tl_dense_gen_eigh_lowest - the k lowest eigenpairs of the full symmetric
+ * pencil H u = lambda S u, S positive definite (the open-boundary chain's
+ * core Hamiltonian and mass matrix, Sec. 5's full eigensolver; Sec. 2.1
+ * eq. (HF-FSpace) with C^T S C = I).
+ *   H_dev, S_dev: N x N row-major doubles, device, both triangles stored
+ *     (the layout tl_assemble_core_hamiltonian_block writes in box mode);
+ *     read only.
+ *   evals_dev: k doubles, ascending.
+ *   evecs_dev (nullable): k x N row-major doubles, row m = eigenvector of
+ *     evals[m], normalised u^T S u = 1 (sign arbitrary).  NULL skips the
+ *     eigenvector stages.
+ *   info_dev: one int: 0 = ok; j > 0 = S not positive definite at pivot j
+ *     (the outputs are then meaningless but finite); -2 = eigenvectors of
+ *     a numerically degenerate cluster could not be separated.
+ *   ws_dev: tl_dense_gen_eigh_workspace_bytes(N, k) bytes, device.
+ * Limits: 1 <= N <= 7680, 1 <= k <= min(N, 64).
+ * Method (FP64 throughout): Cholesky S = L L^T, C = L^-1 H L^-T,
+ * Householder tridiagonalisation, Sturm multisection for the k lowest
+ * eigenvalues, inverse iteration + Cholesky-QR for the eigenvectors,
+ * back-transformation.  Asynchronous on `stream`; allocates nothing.
+ */
+tl_status tl_dense_gen_eigh_workspace_bytes(int N, int k, size_t* bytes);
+tl_status tl_dense_gen_eigh_lowest(const double* H_dev, const double* S_dev, int N, int k,
+                                   double* evals_dev, double* evecs_dev, int* info_dev,
+                                   void* ws_dev, size_t ws_bytes, void* stream);
+
+/*
  * Batched path (many periodic (L,1,1) lattices of uneven L and m0): the
  * whole chain basis -> potential -> assembly -> block FFT -> k-block
  * eigensolves with ONE launch per stage for the whole batch.

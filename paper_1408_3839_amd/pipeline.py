@@ -165,11 +165,32 @@ class BatchPipeline:
         self.graph.replay()
 
 
-class BoxPipeline:
-    """Buffers and calls for an open-boundary chain: basis, potential and the
-    full N_b x N_b core Hamiltonian and mass matrix."""
+class DenseEigh:
+    """Workspace and outputs of the dense lowest-k generalized eigensolver."""
 
-    def __init__(self, sys, device: str = "cuda:0"):
+    def __init__(self, N: int, k: int, with_evecs: bool = True, device: str = "cuda:0"):
+        tl.load()
+        self.N, self.k = int(N), int(k)
+        self.device = torch.device(device)
+        self.ws_bytes = tl.tl_dense_gen_eigh_workspace_bytes(N, k)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.evals = torch.empty(k, dtype=torch.float64, device=self.device)
+        self.evecs = (torch.empty(k, N, dtype=torch.float64, device=self.device)
+                      if with_evecs else None)
+        self.info = torch.empty(1, dtype=torch.int32, device=self.device)
+
+    def run(self, H, S, stream=None):
+        tl.tl_dense_gen_eigh_lowest(H, S, self.N, self.k, self.evals, self.evecs, self.info,
+                                    self.ws, self.ws_bytes, stream)
+        return self.evals
+
+
+class BoxPipeline:
+    """Buffers and calls for an open-boundary chain: basis, potential, the
+    full N_b x N_b core Hamiltonian and mass matrix, and (k > 0) the lowest k
+    generalized eigenpairs."""
+
+    def __init__(self, sys, k: int = 0, with_evecs: bool = True, device: str = "cuda:0"):
         if sys.mode != "box":
             raise ValueError("BoxPipeline needs a box-mode system")
         tl.load()
@@ -190,10 +211,16 @@ class BoxPipeline:
         self.Nb = int(sz["basis_rows"][0])
         self.H = torch.empty(self.Nb, self.Nb, **f64)
         self.S = torch.empty(self.Nb, self.Nb, **f64)
+        self.eig = DenseEigh(self.Nb, k, with_evecs, device) if k > 0 else None
 
-    def run(self, stream=None):
+    def assemble(self, stream=None):
         tl.tl_build_basis(self.handle, self.G, self.AG, self.SG, stream)
         tl.tl_lattice_sum_potential(self.handle, self.P, self.pot_ws, self.pot_ws_bytes, stream)
         tl.tl_assemble_core_hamiltonian_block(self.handle, self.G, self.AG, self.SG, self.P,
                                               tl.TL_FP64, 0, self.H, self.S, self.asm_ws,
                                               self.asm_ws_bytes, stream)
+
+    def run(self, stream=None):
+        self.assemble(stream)
+        if self.eig is not None:
+            self.eig.run(self.H, self.S, stream)

@@ -107,6 +107,12 @@ SIGNATURES = {
     "tl_batched_heigh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "tl_dense_gen_eigh_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int,
+                                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "tl_dense_gen_eigh_lowest": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                                ctypes.c_void_p]),
     "tl_batch_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_int, ctypes.c_int,
                                             ctypes.POINTER(TlBatchPlan)]),
@@ -289,6 +295,19 @@ def tl_block_fft(inp, L1, L2, L3, m0, batch, out, ws=None, ws_bytes=0, stream=No
 def tl_batched_heigh(H, S, count, m0, evals, evecs, info, stream=None):
     _check(load().tl_batched_heigh(_ptr(H), _ptr(S), int(count), int(m0), _ptr(evals),
                                    _ptr(evecs), _ptr(info), _stream(stream)), "tl_batched_heigh")
+
+
+def tl_dense_gen_eigh_workspace_bytes(N, k) -> int:
+    v = ctypes.c_size_t()
+    _check(load().tl_dense_gen_eigh_workspace_bytes(int(N), int(k), ctypes.byref(v)),
+           "tl_dense_gen_eigh_workspace_bytes")
+    return v.value
+
+
+def tl_dense_gen_eigh_lowest(H, S, N, k, evals, evecs, info, ws, ws_bytes, stream=None):
+    _check(load().tl_dense_gen_eigh_lowest(_ptr(H), _ptr(S), int(N), int(k), _ptr(evals),
+                                           _ptr(evecs), _ptr(info), _ptr(ws), int(ws_bytes),
+                                           _stream(stream)), "tl_dense_gen_eigh_lowest")
 
 
 class SystemArray:

@@ -111,3 +111,15 @@ def test_box_mode_queries_and_rejections():
             tl.TL_SPLIT_BF16, 6, 8, 8, 8, wb, 0)
     _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EWORKSPACE, s, 8, 8, 8, 8,
             tl.TL_FP64, 0, 8, 8, 8, wb - 256, 0)
+
+
+def test_dense_eigh_validation():
+    b = tl.tl_dense_gen_eigh_workspace_bytes(2048, 64)
+    assert b >= 4 * 2048 * 2048 * 8 and b % 256 == 0
+    assert tl.tl_dense_gen_eigh_workspace_bytes(1, 1) > 0
+    for N, k in [(0, 1), (10, 0), (10, 11), (200, 65), (7681, 1)]:
+        with pytest.raises(tl.TlError):
+            tl.tl_dense_gen_eigh_workspace_bytes(N, k)
+    _expect(tl.tl_dense_gen_eigh_lowest, tl.TL_EINVAL, 8, 8, 100, 101, 8, 8, 8, 8, 1 << 30, 0)
+    _expect(tl.tl_dense_gen_eigh_lowest, tl.TL_EINVAL, 0, 8, 100, 10, 8, 8, 8, 8, 1 << 30, 0)
+    _expect(tl.tl_dense_gen_eigh_lowest, tl.TL_EWORKSPACE, 8, 8, 100, 10, 8, 8, 8, 8, 1024, 0)

@@ -324,3 +324,43 @@ def test_box_single_cell_equals_open_molecule():
     H, S, _ = oracle.core_hamiltonian_blocks(m)
     np.testing.assert_allclose(Hb, H[0, 0, 0], atol=1e-13)
     np.testing.assert_allclose(Sb, S[0, 0, 0], atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# the dense generalized eigensolver of the open-boundary chain
+
+
+def test_lowest_generalized_eigs_fem_laplacian_closed_form():
+    """Linear-FEM Dirichlet Laplacian on n interior nodes: stiffness
+    (1/h) tridiag(-1,2,-1), mass (h/6) tridiag(1,4,1).  The sine vectors
+    diagonalise both, so lambda_j = (6/h^2)(1 - cos t_j)/(2 + cos t_j),
+    t_j = j pi/(n+1), and u_j is proportional to sin(i t_j)."""
+    n, h, k = 180, 0.05, 24
+    K = (np.diag(np.full(n, 2.0)) - np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1)) / h
+    M = (np.diag(np.full(n, 4.0)) + np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)) * h / 6
+    t = np.arange(1, k + 1) * np.pi / (n + 1)
+    lam = 6.0 / h ** 2 * (1 - np.cos(t)) / (2 + np.cos(t))
+    w, v = oracle.lowest_generalized_eigs(K, M, k)
+    assert np.allclose(w, lam, rtol=1e-12, atol=0)
+    i = np.arange(1, n + 1)
+    for j in range(k):
+        s = np.sin(i * t[j])
+        cosang = abs(s @ v[:, j]) / (np.linalg.norm(s) * np.linalg.norm(v[:, j]))
+        assert cosang > 1 - 1e-10
+    assert np.allclose(v.T @ M @ v, np.eye(k), atol=1e-12)
+
+
+def test_lowest_generalized_eigs_equal_symmetric_reduction():
+    """Brute force on a small random pencil: the k lowest eigenvalues of
+    S^-1/2 H S^-1/2 (symmetric square root from the eigendecomposition of S)."""
+    rng = np.random.default_rng(7)
+    n, k = 40, 9
+    A = rng.standard_normal((n, n))
+    H = A + A.T
+    B = rng.standard_normal((n, n))
+    S = B @ B.T / n + 0.5 * np.eye(n)
+    s, Q = np.linalg.eigh(S)
+    Sm = Q @ np.diag(s ** -0.5) @ Q.T
+    ref = np.sort(np.linalg.eigvalsh(Sm @ H @ Sm))[:k]
+    w, _ = oracle.lowest_generalized_eigs(H, S, k)
+    assert np.allclose(w, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
