@@ -10,11 +10,11 @@
 //   2. L^-1 by recursive doubling of the diagonal-block inverses
 //      (inv [[A,0],[B,C]] = [[A^-1,0],[-C^-1 B A^-1, C^-1]]), batched GEMMs.
 //   3. C = L^-1 H L^-T: two triangle-aware GEMMs, lower tiles mirrored.
-//   4. Householder tridiagonalisation C = Q T Q^T, one column per step: a
-//      one-workgroup kernel forms the reflector, a row-parallel kernel applies
-//      the previous step's rank-2 update to the trailing matrix and multiplies
-//      it by the new reflector in the same pass (one read and one write of the
-//      trailing matrix per column).
+//   4. Householder tridiagonalisation C = Q T Q^T, one launch per column:
+//      every workgroup forms the column's reflector (a few vectors from L2),
+//      then applies the previous step's rank-2 update to its trailing rows
+//      and multiplies them by the reflector in the same pass (one read and
+//      one write of the trailing matrix per column).
 //   5. The k lowest eigenvalues of T by Sturm-count multisection (256 points
 //      per workgroup and round).
 //   6. Eigenvectors of T by inverse iteration (partial-pivoting tridiagonal
@@ -210,61 +210,119 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ S
   Linv[idx] = 0.0;
 }
 
+// Cholesky factor and inverse of a 64 x 64 symmetric block held in
+// registers: thread (r, g) = (tid % 64, tid / 64) of a 256-thread workgroup
+// keeps row r, columns g, g+4, ..., g+60 of the lower triangle in ar (on
+// return: of L) and of L^-1 in xr.  The current column or row is broadcast
+// through double-buffered LDS lines, one barrier per step, and every update
+// is branch-free.  A pivot not above pmin is replaced by 1; the return value
+// is the first such column + 1 (0 if none).
+struct CholLds {
+  double line[2][kNB];
+  double xrow[2][kNB];
+  double lcol[2][kNB];
+  double diag[kNB];
+};
+
+__device__ int chol_inv_64(double (&ar)[16], double (&xr)[16], double pmin, CholLds& sh) {
+  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) xr[q] = (g + 4 * q) == r ? 1.0 : 0.0;
+  int fail = 0;
+  for (int c = 0; c < kNB; ++c) {
+    const int go = c & 3, qo = c >> 2;
+    double* col = sh.line[c & 1];
+    if (g == go) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (q == qo) v = ar[q];
+      col[r] = v;
+    }
+    __syncthreads();
+    double piv = col[c];
+    if (!(piv > pmin)) {
+      if (fail == 0) fail = c + 1;
+      piv = 1.0;
+    }
+    const double lcc = sqrt(piv), rinv = 1.0 / lcc;
+    const double lrc = r > c ? col[r] * rinv : (r == c ? lcc : 0.0);
+    double cv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cv[q] = col[g + 4 * q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int cc = g + 4 * q;
+      const double upd = ar[q] - lrc * (cv[q] * rinv);
+      ar[q] = (q == qo && g == go && r >= c) ? lrc : ((r > c && cc > c && cc <= r) ? upd : ar[q]);
+    }
+  }
+  if (g == (r & 3)) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q == (r >> 2)) v = ar[q];
+    sh.diag[r] = v;
+  }
+  __syncthreads();
+  // X = L^-1 by forward elimination on the identity: step i finalises row i
+  // (scaled by 1 / L[i][i]) and removes L[r][i] * row i from rows r > i
+  for (int i = 0; i < kNB; ++i) {
+    double* rowi = sh.xrow[i & 1];
+    double* coli = sh.lcol[i & 1];
+    if (r == i) {
+      const double sc = 1.0 / sh.diag[i];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        xr[q] *= sc;
+        rowi[g + 4 * q] = xr[q];
+      }
+    }
+    if (g == (i & 3)) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (q == (i >> 2)) v = ar[q];
+      coli[r] = v;
+    }
+    __syncthreads();
+    const double l = coli[r];
+    double rv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) rv[q] = rowi[g + 4 * q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int jj = g + 4 * q;
+      const double upd = xr[q] - l * rv[q];
+      xr[q] = (r > i && jj <= i) ? upd : xr[q];
+    }
+  }
+  return fail;
+}
+
 // Factor the diagonal block at (p, p) in place (lower) and write its inverse
 // into the same block of Linv.  A non-positive pivot records the first
 // failing column (1-based) in *info and continues with pivot 1.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ L,
                                                          double* __restrict__ Linv, int64_t ld,
                                                          int p, int* info) {
-  __shared__ double a[kNB][kNB + 1];
-  __shared__ double x[kNB][kNB + 1];
-  __shared__ int fail;
-  const int tid = threadIdx.x;
-  if (tid == 0) fail = 0;
-  for (int e = tid; e < kNB * kNB; e += 256) {
-    const int r = e / kNB, c = e % kNB;
-    a[r][c] = c <= r ? L[(int64_t)(p + r) * ld + p + c] : 0.0;
+  __shared__ CholLds sh;
+  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
+  double ar[16], xr[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = g + 4 * q;
+    ar[q] = c <= r ? L[(int64_t)(p + r) * ld + p + c] : 0.0;
   }
-  __syncthreads();
-  for (int c = 0; c < kNB; ++c) {
-    double piv = a[c][c];
-    if (!(piv > 0.0)) {
-      if (tid == 0 && fail == 0) fail = p + c + 1;
-      piv = 1.0;
-    }
-    const double lcc = sqrt(piv), rinv = 1.0 / lcc;
-    __syncthreads();
-    if (tid < kNB) {
-      if (tid > c) a[tid][c] *= rinv;
-      if (tid == c) a[c][c] = lcc;
-    }
-    __syncthreads();
-    const int n2 = kNB - 1 - c;
-    for (int e = tid; e < n2 * n2; e += 256) {
-      const int r = c + 1 + e / n2, cc = c + 1 + e % n2;
-      if (cc <= r) a[r][cc] -= a[r][c] * a[cc][c];
-    }
-    __syncthreads();
-  }
-  // inverse of the lower-triangular block, one column per thread
-  if (tid < kNB) {
-    const int j = tid;
-    for (int i = 0; i < j; ++i) x[i][j] = 0.0;
-    x[j][j] = 1.0 / a[j][j];
-    for (int i = j + 1; i < kNB; ++i) {
-      double s = 0.0;
-      for (int q = j; q < i; ++q) s += a[i][q] * x[q][j];
-      x[i][j] = -s / a[i][i];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < kNB * kNB; e += 256) {
-    const int r = e / kNB, c = e % kNB;
-    L[(int64_t)(p + r) * ld + p + c] = c <= r ? a[r][c] : 0.0;
-    Linv[(int64_t)(p + r) * ld + p + c] = c <= r ? x[r][c] : 0.0;
+  const int fail = chol_inv_64(ar, xr, 0.0, sh);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = g + 4 * q;
+    L[(int64_t)(p + r) * ld + p + c] = c <= r ? ar[q] : 0.0;
+    Linv[(int64_t)(p + r) * ld + p + c] = c <= r ? xr[q] : 0.0;
   }
   if (tid == 0 && fail != 0) {
-    if (*info == 0) *info = fail;
+    if (*info == 0) *info = p + fail;
   }
 }
 
@@ -272,8 +330,8 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ L,
 struct TridArgs {
   double* C;         // N x N symmetric, row stride ld, overwritten
   double* Vt;        // reflector j in row j (length N, zero up to index j, 1 at j+1)
-  double* y;         // tau_j * A22 v_j
-  double* w;         // w_{j-1}
+  double* y[2];      // y_j = tau_j A22 v_j, alternating by the parity of j
+  double* part[2];   // per-workgroup partial sums of y_j . v_j, alternating
   double* d;         // diagonal of T
   double* e;         // off-diagonal of T
   double* tau;
@@ -281,44 +339,118 @@ struct TridArgs {
   int N;
 };
 
-// Reflector of column j.  Finishes w_{j-1} = y - 1/2 tau (y.v) v, takes row j
-// of the matrix with the pending rank-2 update of step j-1 applied on the
-// fly, and forms v_j, tau_j (LAPACK dlarfg convention, beta = -sign(alpha)
-// ||x||), d_j and e_j.
-__global__ __launch_bounds__(256) void tridiag_house_kernel(TridArgs t, int j) {
-  __shared__ double red[4];
+constexpr int kTT = 256;  // threads of the tridiagonalisation kernel
+constexpr int kTR = 4;    // trailing rows per workgroup
+
+__device__ inline double block_sum_t(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kTT / 64; ++q) s += red[q];
+  return s;
+}
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// Step j, launched with one workgroup per kTR trailing rows (at least one).
+// Every workgroup first forms the reflector of column j itself: row j of
+// the matrix still carries step j-1's rank-2 update v w^T + w v^T, with
+// w = y_{j-1} - 1/2 tau_{j-1} (y_{j-1} . v) v, which is applied on the fly
+// (y . v is the sum of step j-1's nparts partials); v_j (LAPACK dlarfg
+// convention, beta = -sign(alpha) ||x||) is kept in LDS and workgroup 0
+// stores it with tau_j, d_j and e_j.  Then each workgroup applies step
+// j-1's update to its rows (columns > j) and forms y_j[r] = tau_j A[r] v_j in
+// the same pass: one read and one write of the trailing matrix per column,
+// 16-byte accesses on even column pairs (row stride and vector offsets are
+// even), columns <= j masked, and the 256 threads splitting the columns.
+constexpr int kPU = 8;   // prologue elements per thread held in registers (n <= 2048)
+constexpr int kPP = 2;   // partial sums per thread held in registers (nparts <= 512)
+
+__global__ __launch_bounds__(kTT) void tridiag_step_kernel(TridArgs t, int j, int nparts) {
+  extern __shared__ double vs[];  // N + 1 entries: x, then v_j
+  __shared__ double red[kTT / 64];
+  __shared__ double redr[kTT / 64][kTR];
   __shared__ double s_alpha;
-  const int N = t.N, tid = threadIdx.x;
-  const bool corr = j >= 1;  // the row kernel ran for every j <= N - 2
-  const double* vp = corr ? t.Vt + (int64_t)(j - 1) * t.ld : nullptr;
-  double* vj = t.Vt + (int64_t)j * t.ld;
-  const double* row = t.C + (int64_t)j * t.ld;
-  double cw = 0.0, wj = 0.0, vpj = 0.0;
-  if (corr) {
-    double s = 0.0;
-    for (int i = j + tid; i < N; i += 256) s += t.y[i] * vp[i];
-    s = block_sum(s, red);
-    cw = 0.5 * t.tau[j - 1] * s;
-    for (int i = j + tid; i < N; i += 256) t.w[i] = t.y[i] - cw * vp[i];
-    vpj = vp[j];
-    wj = t.y[j] - cw * vpj;
+  const int N = t.N, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool corr = j >= 1;
+  const double* __restrict__ yp = t.y[(j + 1) & 1];
+  const double* __restrict__ pp = t.part[(j + 1) & 1];
+  const double* __restrict__ vp = t.Vt + (int64_t)(corr ? j - 1 : j) * t.ld;
+  const double* __restrict__ rowj = t.C + (int64_t)j * t.ld;
+  const int r0 = j + 1 + kTR * blockIdx.x;
+  // ---- every global load that does not depend on a reduction, issued first
+  double pv_[kPP], rx[kPU], vx[kPU], yx[kPU];
+#pragma unroll
+  for (int u = 0; u < kPP; ++u) {
+    const int q = tid + kTT * u;
+    pv_[u] = (corr && q < nparts) ? pp[q] : 0.0;
   }
-  // x_i (i >= j) into vj[i]; zeros below
+#pragma unroll
+  for (int u = 0; u < kPU; ++u) {
+    const int i = j + tid + kTT * u;
+    const bool ok = i < N;
+    rx[u] = ok ? rowj[i] : 0.0;
+    vx[u] = (ok && corr) ? vp[i] : 0.0;
+    yx[u] = (ok && corr) ? yp[i] : 0.0;
+  }
+  const double taup = corr ? t.tau[j - 1] : 0.0;
+  const double vpj = corr ? vp[j] : 0.0, ypj = corr ? yp[j] : 0.0;
+  double vr[kTR], yr_[kTR];
+  double* row[kTR];
+#pragma unroll
+  for (int q = 0; q < kTR; ++q) {
+    const int r = r0 + q;
+    const bool ok = r < N;
+    row[q] = t.C + (int64_t)(ok ? r : j) * t.ld;
+    vr[q] = (corr && ok) ? vp[r] : 0.0;
+    yr_[q] = (corr && ok) ? yp[r] : 0.0;
+  }
+  const int cb = (j + 1) & ~1;
+  const bool rows = j < N - 1;
+  // first column pair of the trailing rows (consumed after the reflector)
+  int c = cb + 2 * tid;
+  f64x2 a[kTR], pv2 = {0.0, 0.0}, py2 = {0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < kTR; ++q)
+    a[q] = (rows && c < N && r0 + q < N) ? *(const f64x2*)(row[q] + c) : f64x2{0.0, 0.0};
+  if (rows && corr && c < N) {
+    pv2 = *(const f64x2*)(vp + c);
+    py2 = *(const f64x2*)(yp + c);
+  }
+  // ---- reflector of column j
+  double cw = 0.0;
+  if (corr) {
+    double sp = 0.0;
+#pragma unroll
+    for (int u = 0; u < kPP; ++u) sp += pv_[u];
+    for (int q = tid + kTT * kPP; q < nparts; q += kTT) sp += pp[q];
+    sp = block_sum_t(sp, red);
+    cw = 0.5 * taup * sp;
+  }
+  const double wj = ypj - cw * vpj;
   double sig = 0.0;
-  for (int i = tid; i < N; i += 256) {
-    if (i < j) {
-      vj[i] = 0.0;
-      continue;
-    }
-    double x = row[i];
-    if (corr) x -= vp[i] * wj + (t.y[i] - cw * vp[i]) * vpj;
-    vj[i] = x;
-    if (i == j) t.d[j] = x;
+  auto xval = [&](int i, double ri, double vi, double yi) {
+    double x = ri;
+    if (corr) x -= vi * wj + (yi - cw * vi) * vpj;
+    vs[i] = x;
     if (i == j + 1) s_alpha = x;
     if (i >= j + 2) sig += x * x;
+    if (i == j && blockIdx.x == 0) t.d[j] = x;
+  };
+#pragma unroll
+  for (int u = 0; u < kPU; ++u) {
+    const int i = j + tid + kTT * u;
+    if (i < N) xval(i, rx[u], vx[u], yx[u]);
   }
-  if (j >= N - 1) return;  // last column: only d
-  sig = block_sum(sig, red);  // contains the barrier that publishes s_alpha
+  for (int i = j + tid + kTT * kPU; i < N; i += kTT)
+    xval(i, rowj[i], corr ? vp[i] : 0.0, corr ? yp[i] : 0.0);
+  if (tid == 0) vs[N] = 0.0;
+  if (!rows) return;  // last column: only d
+  sig = block_sum_t(sig, red);  // its barriers publish s_alpha and vs
   const double alpha = s_alpha;
   double tau = 0.0, beta = alpha, scale = 0.0;
   if (sig > 0.0) {
@@ -326,59 +458,78 @@ __global__ __launch_bounds__(256) void tridiag_house_kernel(TridArgs t, int j) {
     tau = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
   }
-  for (int i = j + 1 + tid; i < N; i += 256) vj[i] = (i == j + 1) ? 1.0 : vj[i] * scale;
-  if (tid == 0) {
-    vj[j] = 0.0;  // held x_j until the barrier in block_sum
-    t.tau[j] = tau;
-    t.e[j] = beta;
-  }
-}
-
-// Rows r > j: apply step j-1's update A -= v w^T + w v^T (columns > j) and
-// form y_j[r] = tau_j sum_c A[r][c] v_j[c].  Two rows per wave.
-__global__ __launch_bounds__(256) void tridiag_update_kernel(TridArgs t, int j) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int N = t.N;
-  const int r0 = j + 1 + (blockIdx.x * 4 + wave) * 2;
-  if (r0 >= N) return;
-  const bool two = r0 + 1 < N;
-  const bool upd = j >= 1;
-  const double* vj = t.Vt + (int64_t)j * t.ld;
-  const double* vp = upd ? t.Vt + (int64_t)(j - 1) * t.ld : vj;
-  double* row0 = t.C + (int64_t)r0 * t.ld;
-  double* row1 = two ? row0 + t.ld : row0;
-  double vr0 = 0.0, wr0 = 0.0, vr1 = 0.0, wr1 = 0.0;
-  if (upd) {
-    vr0 = vp[r0];
-    wr0 = t.w[r0];
-    if (two) {
-      vr1 = vp[r0 + 1];
-      wr1 = t.w[r0 + 1];
+  for (int i = j + tid; i < N; i += kTT) vs[i] = i == j ? 0.0 : (i == j + 1 ? 1.0 : vs[i] * scale);
+  __syncthreads();  // v_j complete in LDS
+  if (blockIdx.x == 0) {
+    double* vrow = t.Vt + (int64_t)j * t.ld;
+    for (int i = tid; i < N; i += kTT) vrow[i] = i < j ? 0.0 : vs[i];
+    if (tid == 0) {
+      t.tau[j] = tau;
+      t.e[j] = beta;
     }
   }
-  double acc0 = 0.0, acc1 = 0.0;
-  for (int c = j + 1 + lane; c < N; c += 64) {
-    const double v = vj[c];
-    double a0 = row0[c];
-    double a1 = two ? row1[c] : 0.0;
-    if (upd) {
-      const double pv = vp[c], pw = t.w[c];
-      a0 -= vr0 * pw + wr0 * pv;
-      row0[c] = a0;
-      if (two) {
-        a1 -= vr1 * pw + wr1 * pv;
-        row1[c] = a1;
+  // ---- trailing rows r0 .. r0+kTR-1 (> j), one column pair ahead
+  double wr[kTR], acc[kTR];
+#pragma unroll
+  for (int q = 0; q < kTR; ++q) {
+    wr[q] = yr_[q] - cw * vr[q];
+    acc[q] = 0.0;
+  }
+  // N <= ld and ld is even, so the pair (c, c+1) with c < N is in the row
+  for (; c < N; c += 2 * kTT) {
+    const int cn = c + 2 * kTT;
+    f64x2 an[kTR], pvn = {0.0, 0.0}, pyn = {0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < kTR; ++q)
+      an[q] = (cn < N && r0 + q < N) ? *(const f64x2*)(row[q] + cn) : f64x2{0.0, 0.0};
+    if (corr && cn < N) {
+      pvn = *(const f64x2*)(vp + cn);
+      pyn = *(const f64x2*)(yp + cn);
+    }
+    const bool ok0 = c >= j + 1, ok1 = c + 1 < N;
+    const double m0 = ok0 ? 1.0 : 0.0, m1 = ok1 ? 1.0 : 0.0;
+    const double v0 = vs[c], v1 = vs[c + 1];
+    const f64x2 pw = py2 - cw * pv2;
+#pragma unroll
+    for (int q = 0; q < kTR; ++q) {
+      if (r0 + q >= N) continue;
+      if (corr) {
+        a[q] -= vr[q] * pw + wr[q] * pv2;
+        if (ok0 && ok1)
+          *(f64x2*)(row[q] + c) = a[q];
+        else if (ok1)
+          row[q][c + 1] = a[q].y;
+        else if (ok0)
+          row[q][c] = a[q].x;
       }
+      acc[q] += m0 * a[q].x * v0 + m1 * a[q].y * v1;
     }
-    acc0 += a0 * v;
-    acc1 += a1 * v;
+#pragma unroll
+    for (int q = 0; q < kTR; ++q) a[q] = an[q];
+    pv2 = pvn;
+    py2 = pyn;
   }
-  acc0 = wave_sum(acc0);
-  acc1 = wave_sum(acc1);
-  if (lane == 0) {
-    const double tj = t.tau[j];
-    t.y[r0] = tj * acc0;
-    if (two) t.y[r0 + 1] = tj * acc1;
+#pragma unroll
+  for (int q = 0; q < kTR; ++q) {
+    const double sq = wave_sum(acc[q]);
+    if (lane == 0) redr[wave][q] = sq;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double pz = 0.0;
+    double* __restrict__ yn = t.y[j & 1];
+#pragma unroll
+    for (int q = 0; q < kTR; ++q) {
+      const int r = r0 + q;
+      if (r >= N) continue;
+      double sq = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < kTT / 64; ++wv) sq += redr[wv][q];
+      const double yr = tau * sq;
+      yn[r] = yr;
+      pz += yr * vs[r];
+    }
+    t.part[j & 1][blockIdx.x] = pz;
   }
 }
 
@@ -438,26 +589,60 @@ __device__ inline void tri_bounds(const TriSpec& T, double* red, double& glo, do
   ghi += fudge;
 }
 
-// Eigenvalue m (0-based, ascending) of T per workgroup.
+// Eigenvalue m (0-based, ascending) of T per workgroup: each round counts
+// at 512 interior points (two interleaved Sturm sequences per thread, d and
+// e^2 staged through LDS) and keeps the sub-interval that holds index m.
+constexpr int kBisChunk = 1024;
+
 __global__ __launch_bounds__(256) void bisect_kernel(TriSpec T, double* __restrict__ evals) {
   __shared__ double red[12];
   __shared__ double s_lo, s_hi;
-  __shared__ double s_x[kMSect];
-  __shared__ int s_c[kMSect];
-  const int m = blockIdx.x, tid = threadIdx.x;
+  __shared__ double sd[kBisChunk], se2[kBisChunk];
+  __shared__ double s_x[2 * kMSect];
+  __shared__ int s_c[2 * kMSect];
+  const int m = blockIdx.x, tid = threadIdx.x, N = T.N;
   double glo, ghi, pivmin;
   tri_bounds(T, red, glo, ghi, pivmin);
   double lo = glo, hi = ghi;
+  constexpr double kPts = 2.0 * kMSect + 1.0;
   for (int round = 0; round < 24; ++round) {
     const double tol = 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin;
     if (hi - lo <= tol) break;  // uniform: lo, hi come from shared memory
-    const double x = lo + (hi - lo) * ((double)(tid + 1) / (double)(kMSect + 1));
-    s_x[tid] = x;
-    s_c[tid] = sturm_count(T, x, pivmin);
+    const double x0 = lo + (hi - lo) * ((double)(2 * tid + 1) / kPts);
+    const double x1 = lo + (hi - lo) * ((double)(2 * tid + 2) / kPts);
+    int c0 = 0, c1 = 0;
+    double q0 = T.d[0] - x0, q1 = T.d[0] - x1;
+    if (fabs(q0) < pivmin) q0 = -pivmin;
+    if (fabs(q1) < pivmin) q1 = -pivmin;
+    c0 += q0 < 0.0;
+    c1 += q1 < 0.0;
+    for (int base = 1; base < N; base += kBisChunk) {
+      const int len = min(kBisChunk, N - base);
+      __syncthreads();
+      for (int u = tid; u < len; u += 256) {
+        sd[u] = T.d[base + u];
+        const double e = T.e[base + u - 1];
+        se2[u] = e * e;
+      }
+      __syncthreads();
+      for (int u = 0; u < len; ++u) {
+        const double du = sd[u], eu = se2[u];
+        q0 = (du - x0) - eu / q0;
+        q1 = (du - x1) - eu / q1;
+        if (fabs(q0) < pivmin) q0 = -pivmin;
+        if (fabs(q1) < pivmin) q1 = -pivmin;
+        c0 += q0 < 0.0;
+        c1 += q1 < 0.0;
+      }
+    }
+    s_x[2 * tid] = x0;
+    s_x[2 * tid + 1] = x1;
+    s_c[2 * tid] = c0;
+    s_c[2 * tid + 1] = c1;
     __syncthreads();
     if (tid == 0) {
       double nlo = lo, nhi = hi;
-      for (int q = 0; q < kMSect; ++q) {
+      for (int q = 0; q < 2 * kMSect; ++q) {
         if (s_c[q] <= m)
           nlo = fmax(nlo, s_x[q]);
         else
@@ -495,7 +680,13 @@ __device__ inline uint64_t splitmix64(uint64_t x) {
 
 // One thread per eigenvalue: (T - lambda I) = P L U with partial pivoting,
 // tiny pivots of U replaced by eps ||T|| (sign kept), three solves from a
-// pseudo-random start, 2-norm normalisation.
+// pseudo-random start (SplitMix64 of (m, i), uniform in [-1, 1)), each
+// right-hand side scaled by the previous solve's max-norm, then 2-norm
+// normalisation.  The sequential passes run over chunks of kIC rows whose
+// loads are issued together; arrays are [i][k] so a wave's accesses are
+// contiguous.
+constexpr int kIC = 8;
+
 __global__ __launch_bounds__(64) void inverse_iter_kernel(InvArgs a) {
   // ||T|| from the Gershgorin interval, by this wave alone
   double lo = 1e308, hi = -1e308;
@@ -516,43 +707,55 @@ __global__ __launch_bounds__(64) void inverse_iter_kernel(InvArgs a) {
   if (m >= k) return;
   const double lam = a.evals[m];
   const int64_t P = (int64_t)N * k;
-  double* RU0 = a.f;
-  double* U1 = a.f + P;
-  double* U2 = a.f + 2 * P;
-  double* LM = a.f + 3 * P;
-  double* SW = a.f + 4 * P;
-  double* X = a.X;
-  // factorisation
-  double p = a.T.d[0] - lam, q = N > 1 ? a.T.e[0] : 0.0;
-  for (int i = 0; i + 1 < N; ++i) {
-    const double sub = a.T.e[i];
-    const double dn = a.T.d[i + 1] - lam;
-    const double en = i + 2 < N ? a.T.e[i + 1] : 0.0;
-    const int64_t o = (int64_t)i * k + m;
-    double u0, u1, u2, l, sw;
-    if (fabs(p) >= fabs(sub)) {
-      l = p != 0.0 ? sub / p : 0.0;
-      u0 = p;
-      u1 = q;
-      u2 = 0.0;
-      p = dn - l * q;
-      q = en;
-      sw = 0.0;
-    } else {
-      l = p / sub;
-      u0 = sub;
-      u1 = dn;
-      u2 = en;
-      p = q - l * dn;
-      q = -l * en;
-      sw = 1.0;
+  double* __restrict__ RU0 = a.f;
+  double* __restrict__ U1 = a.f + P;
+  double* __restrict__ U2 = a.f + 2 * P;
+  double* __restrict__ LM = a.f + 3 * P;
+  double* __restrict__ SW = a.f + 4 * P;
+  double* __restrict__ X = a.X;
+  const double* __restrict__ D = a.T.d;
+  const double* __restrict__ E = a.T.e;
+  // factorisation, rows i = 0 .. N-2 in chunks, then the last row
+  double p = D[0] - lam, q = N > 1 ? E[0] : 0.0;
+  for (int i0 = 0; i0 < N - 1; i0 += kIC) {
+    double dn[kIC], sub[kIC], en[kIC];
+#pragma unroll
+    for (int u = 0; u < kIC; ++u) {
+      const int i = i0 + u;
+      sub[u] = i < N - 1 ? E[i] : 0.0;
+      dn[u] = i < N - 1 ? D[i + 1] - lam : 0.0;
+      en[u] = i + 2 < N ? E[i + 1] : 0.0;
     }
-    if (fabs(u0) < pert) u0 = u0 < 0.0 ? -pert : pert;
-    RU0[o] = 1.0 / u0;
-    U1[o] = u1;
-    U2[o] = u2;
-    LM[o] = l;
-    SW[o] = sw;
+#pragma unroll
+    for (int u = 0; u < kIC; ++u) {
+      const int i = i0 + u;
+      if (i >= N - 1) break;
+      double u0, u1, u2, l, sw;
+      if (fabs(p) >= fabs(sub[u])) {
+        l = p != 0.0 ? sub[u] / p : 0.0;
+        u0 = p;
+        u1 = q;
+        u2 = 0.0;
+        p = dn[u] - l * q;
+        q = en[u];
+        sw = 0.0;
+      } else {
+        l = p / sub[u];
+        u0 = sub[u];
+        u1 = dn[u];
+        u2 = en[u];
+        p = q - l * dn[u];
+        q = -l * en[u];
+        sw = 1.0;
+      }
+      if (fabs(u0) < pert) u0 = u0 < 0.0 ? -pert : pert;
+      const int64_t o = (int64_t)i * k + m;
+      RU0[o] = 1.0 / u0;
+      U1[o] = u1;
+      U2[o] = u2;
+      LM[o] = l;
+      SW[o] = sw;
+    }
   }
   {
     const int64_t o = (int64_t)(N - 1) * k + m;
@@ -564,123 +767,283 @@ __global__ __launch_bounds__(64) void inverse_iter_kernel(InvArgs a) {
     LM[o] = 0.0;
     SW[o] = 0.0;
   }
-  // start vector in [-1, 1)
-  for (int i = 0; i < N; ++i) {
-    const uint64_t r = splitmix64(((uint64_t)m << 32) ^ (uint64_t)i);
-    X[(int64_t)i * k + m] = (double)(r >> 11) * (2.0 / 9007199254740992.0) - 1.0;
-  }
+  double scale = 1.0, ssq = 0.0;
   for (int it = 0; it < 3; ++it) {
-    // forward elimination of the right-hand side
-    double bi = X[m];
-    for (int i = 0; i + 1 < N; ++i) {
-      const int64_t o = (int64_t)i * k + m;
-      const double bn = X[o + k];
-      const double l = LM[o];
-      if (SW[o] != 0.0) {
-        X[o] = bn;
-        bi = bi - l * bn;
-      } else {
-        X[o] = bi;
-        bi = bn - l * bi;
+    // forward elimination of the right-hand side (it = 0: the start vector)
+    auto rhs = [&](int i) -> double {
+      if (it == 0) {
+        const uint64_t r = splitmix64(((uint64_t)m << 32) ^ (uint64_t)i);
+        return (double)(r >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+      }
+      return X[(int64_t)i * k + m] * scale;
+    };
+    double bi = rhs(0);
+    for (int i0 = 0; i0 < N - 1; i0 += kIC) {
+      double bn[kIC], l[kIC], sw[kIC];
+#pragma unroll
+      for (int u = 0; u < kIC; ++u) {
+        const int i = i0 + u;
+        const bool ok = i < N - 1;
+        const int64_t o = (int64_t)i * k + m;
+        bn[u] = ok ? rhs(i + 1) : 0.0;
+        l[u] = ok ? LM[o] : 0.0;
+        sw[u] = ok ? SW[o] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kIC; ++u) {
+        const int i = i0 + u;
+        if (i >= N - 1) break;
+        double out;
+        if (sw[u] != 0.0) {
+          out = bn[u];
+          bi = bi - l[u] * bn[u];
+        } else {
+          out = bi;
+          bi = bn[u] - l[u] * bi;
+        }
+        X[(int64_t)i * k + m] = out;
       }
     }
     X[(int64_t)(N - 1) * k + m] = bi;
-    // back substitution
+    // back substitution from the last row, chunks of kIC rows downwards
     double x1 = 0.0, x2 = 0.0, xmax = 0.0;
-    for (int i = N - 1; i >= 0; --i) {
-      const int64_t o = (int64_t)i * k + m;
-      const double xi = (X[o] - U1[o] * x1 - U2[o] * x2) * RU0[o];
-      X[o] = xi;
-      xmax = fmax(xmax, fabs(xi));
-      x2 = x1;
-      x1 = xi;
+    ssq = 0.0;
+    for (int i1 = N - 1; i1 >= 0; i1 -= kIC) {
+      double b[kIC], r0[kIC], c1[kIC], c2[kIC];
+#pragma unroll
+      for (int u = 0; u < kIC; ++u) {
+        const int i = i1 - u;
+        const bool ok = i >= 0;
+        const int64_t o = (int64_t)i * k + m;
+        b[u] = ok ? X[o] : 0.0;
+        r0[u] = ok ? RU0[o] : 0.0;
+        c1[u] = ok ? U1[o] : 0.0;
+        c2[u] = ok ? U2[o] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kIC; ++u) {
+        const int i = i1 - u;
+        if (i < 0) break;
+        const double xi = (b[u] - c1[u] * x1 - c2[u] * x2) * r0[u];
+        X[(int64_t)i * k + m] = xi;
+        xmax = fmax(xmax, fabs(xi));
+        ssq += xi * xi;
+        x2 = x1;
+        x1 = xi;
+      }
     }
-    const double s = xmax > 0.0 ? 1.0 / xmax : 1.0;
-    double nrm = 0.0;
-    for (int i = 0; i < N; ++i) {
-      const int64_t o = (int64_t)i * k + m;
-      const double v = X[o] * s;
-      X[o] = v;
-      nrm += v * v;
-    }
-    if (it == 2) {
-      const double sn = nrm > 0.0 ? 1.0 / sqrt(nrm) : 1.0;
-      for (int i = 0; i < N; ++i) X[(int64_t)i * k + m] *= sn;
-    }
+    scale = xmax > 0.0 ? 1.0 / xmax : 1.0;
   }
+  const double sn = ssq > 0.0 ? 1.0 / sqrt(ssq) : 1.0;
+  for (int i = 0; i < N; ++i) X[(int64_t)i * k + m] *= sn;
+}
+
+// The same iteration with one workgroup per eigenvalue and everything in
+// LDS: d and e staged once, the factors (1/u0, u1, multiplier, swap flag;
+// u2 is e[i+1] on swapped rows, else 0) and the iterate.  One lane runs the
+// recurrences, reading LDS in chunks of kIC; the wave writes the result.
+// LDS: 6 N doubles + N bytes.
+__global__ __launch_bounds__(64) void inverse_iter_lds_kernel(InvArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double s_ssq;
+  const int N = a.T.N, k = a.k, m = blockIdx.x, lane = threadIdx.x;
+  double* D = lds;
+  double* E = lds + N;            // E[i] = e[i] (i < N-1), E[N-1] = 0
+  double* RU0 = lds + 2 * N;
+  double* U1 = lds + 3 * N;
+  double* LM = lds + 4 * N;
+  double* X = lds + 5 * N;
+  unsigned char* SW = (unsigned char*)(lds + 6 * N);
+  double lo = 1e308, hi = -1e308;
+  for (int i = lane; i < N; i += 64) {
+    const double di = a.T.d[i], ei = i < N - 1 ? a.T.e[i] : 0.0;
+    const double el = i > 0 ? fabs(a.T.e[i - 1]) : 0.0;
+    D[i] = di;
+    E[i] = ei;
+    lo = fmin(lo, di - el - fabs(ei));
+    hi = fmax(hi, di + el + fabs(ei));
+    const uint64_t r = splitmix64(((uint64_t)m << 32) ^ (uint64_t)i);
+    X[i] = (double)(r >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+  }
+  const double tnorm = fmax(fabs(lo), fabs(hi));
+  const double pert = fmax(DBL_EPSILON * tnorm, DBL_MIN);
+  __syncthreads();
+  double ssq = 0.0;
+  if (lane == 0) {
+    const double lam = a.evals[m];
+    double p = D[0] - lam, q = E[0];
+    for (int i0 = 0; i0 < N - 1; i0 += kIC) {
+      double dn[kIC], sub[kIC], en[kIC];
+#pragma unroll
+      for (int u = 0; u < kIC; ++u) {
+        const int i = min(i0 + u, N - 2);
+        sub[u] = E[i];
+        dn[u] = D[i + 1] - lam;
+        en[u] = E[i + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < kIC; ++u) {
+        const int i = i0 + u;
+        if (i >= N - 1) break;
+        double u0, rcp, l;
+        if (fabs(p) >= fabs(sub[u])) {
+          u0 = fabs(p) < pert ? (p < 0.0 ? -pert : pert) : p;
+          rcp = 1.0 / u0;
+          l = p != 0.0 ? sub[u] * rcp : 0.0;
+          U1[i] = q;
+          SW[i] = 0;
+          p = dn[u] - l * q;
+          q = en[u];
+        } else {
+          const double rs = 1.0 / sub[u];  // |sub| > |p| >= 0
+          l = p * rs;
+          u0 = fabs(sub[u]) < pert ? (sub[u] < 0.0 ? -pert : pert) : sub[u];
+          rcp = u0 == sub[u] ? rs : 1.0 / u0;
+          U1[i] = dn[u];
+          SW[i] = 1;
+          p = q - l * dn[u];
+          q = -l * en[u];
+        }
+        RU0[i] = rcp;
+        LM[i] = l;
+      }
+    }
+    {
+      const double u0 = fabs(p) < pert ? (p < 0.0 ? -pert : pert) : p;
+      RU0[N - 1] = 1.0 / u0;
+      U1[N - 1] = 0.0;
+      LM[N - 1] = 0.0;
+      SW[N - 1] = 0;
+    }
+    double scale = 1.0;
+    for (int it = 0; it < 3; ++it) {
+      double bi = X[0] * scale;
+      for (int i0 = 0; i0 < N - 1; i0 += kIC) {
+        double bn[kIC], l[kIC];
+        unsigned char sw[kIC];
+#pragma unroll
+        for (int u = 0; u < kIC; ++u) {
+          const int i = min(i0 + u, N - 2);
+          bn[u] = X[i + 1] * scale;
+          l[u] = LM[i];
+          sw[u] = SW[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kIC; ++u) {
+          const int i = i0 + u;
+          if (i >= N - 1) break;
+          double out;
+          if (sw[u]) {
+            out = bn[u];
+            bi = bi - l[u] * bn[u];
+          } else {
+            out = bi;
+            bi = bn[u] - l[u] * bi;
+          }
+          X[i] = out;
+        }
+      }
+      X[N - 1] = bi;
+      double x1 = 0.0, x2 = 0.0, xmax = 0.0;
+      ssq = 0.0;
+      for (int i1 = N - 1; i1 >= 0; i1 -= kIC) {
+        double b[kIC], r0[kIC], c1[kIC], c2[kIC];
+#pragma unroll
+        for (int u = 0; u < kIC; ++u) {
+          const int i = max(i1 - u, 0);
+          b[u] = X[i];
+          r0[u] = RU0[i];
+          c1[u] = U1[i];
+          c2[u] = SW[i] ? E[i + 1 < N ? i + 1 : N - 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kIC; ++u) {
+          const int i = i1 - u;
+          if (i < 0) break;
+          const double xi = (b[u] - c1[u] * x1 - c2[u] * x2) * r0[u];
+          X[i] = xi;
+          xmax = fmax(xmax, fabs(xi));
+          ssq += xi * xi;
+          x2 = x1;
+          x1 = xi;
+        }
+      }
+      scale = xmax > 0.0 ? 1.0 / xmax : 1.0;
+    }
+    s_ssq = ssq;
+  }
+  __syncthreads();
+  const double ss = s_ssq;
+  const double sn = ss > 0.0 ? 1.0 / sqrt(ss) : 1.0;
+  for (int i = lane; i < N; i += 64) a.X[(int64_t)i * k + m] = X[i] * sn;
 }
 
 // ------------------------------------------------------------------ Cholesky-QR
-// Partial Gram matrices of 64-row chunks of X [N][k].
+// Partial Gram matrices of 256-row chunks of X [N][k] (4 LDS stages of 64).
+constexpr int kGramRows = 256;
+
 __global__ __launch_bounds__(256) void gram_partial_kernel(const double* __restrict__ X, int N,
                                                            int k, double* __restrict__ part) {
   __shared__ double xs[64][kMaxK + 1];
-  const int i0 = blockIdx.x * 64, tid = threadIdx.x;
-  for (int e = tid; e < 64 * k; e += 256) {
-    const int r = e / k, c = e % k;
-    xs[r][c] = i0 + r < N ? X[(int64_t)(i0 + r) * k + c] : 0.0;
+  const int tid = threadIdx.x;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int st = 0; st < kGramRows / 64; ++st) {
+    const int i0 = blockIdx.x * kGramRows + st * 64;
+    __syncthreads();
+    for (int e = tid; e < 64 * kMaxK; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      xs[r][c] = (i0 + r < N && c < k) ? X[(int64_t)(i0 + r) * k + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q, pp = e >> 6, qq = e & 63;
+      double s = 0.0;
+      for (int r = 0; r < 64; ++r) s += xs[r][pp] * xs[r][qq];
+      acc[q] += s;
+    }
   }
-  __syncthreads();
   double* out = part + (int64_t)blockIdx.x * k * k;
-  for (int e = tid; e < k * k; e += 256) {
-    const int p = e / k, q = e % k;
-    double s = 0.0;
-    for (int r = 0; r < 64; ++r) s += xs[r][p] * xs[r][q];
-    out[e] = s;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, pp = e >> 6, qq = e & 63;
+    if (pp < k && qq < k) out[pp * k + qq] = acc[q];
   }
 }
 
-// G = sum of the partials = R^T R; writes R^-1 (upper).  A pivot below
-// 1/4 means the vectors were not independent: info = -2.
+// G = sum of the partials (padded to 64 x 64 with the identity) = L L^T;
+// writes R^-1 = L^-T (upper, k x k), R = L^T.  A pivot not above 1/4 means
+// the vectors were not independent: info = -2.
 __global__ __launch_bounds__(256) void chol_small_kernel(const double* __restrict__ part,
                                                          int nparts, int k,
                                                          double* __restrict__ Rinv, int* info) {
-  __shared__ double g[kMaxK][kMaxK + 1];
-  __shared__ double x[kMaxK][kMaxK + 1];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < k * k; e += 256) {
-    double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * k * k + e];
-    g[e / k][e % k] = s;
+  __shared__ CholLds sh;
+  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
+  double ar[16], xr[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = g + 4 * q;
+    double v = c == r ? 1.0 : 0.0;
+    if (r < k && c < k && c <= r) {
+      v = 0.0;
+      for (int b = 0; b < nparts; ++b) v += part[(int64_t)b * k * k + r * k + c];
+    }
+    ar[q] = c <= r ? v : 0.0;
   }
-  __syncthreads();
-  // upper Cholesky G = R^T R, R stored in g's upper triangle
-  for (int c = 0; c < k; ++c) {
-    double piv = g[c][c];
-    if (!(piv > 0.25)) {
-      if (tid == 0) bad = 1;
-      piv = 1.0;
-    }
-    const double rcc = sqrt(piv), rinv = 1.0 / rcc;
-    __syncthreads();
-    if (tid < k) {
-      if (tid > c) g[c][tid] *= rinv;
-      if (tid == c) g[c][c] = rcc;
-    }
-    __syncthreads();
-    const int n2 = k - 1 - c;
-    for (int e = tid; e < n2 * n2; e += 256) {
-      const int r = c + 1 + e / n2, cc = c + 1 + e % n2;
-      if (cc >= r) g[r][cc] -= g[c][r] * g[c][cc];
-    }
-    __syncthreads();
+  const int fail = chol_inv_64(ar, xr, 0.25, sh);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = g + 4 * q;
+    if (r < k && c < k) Rinv[c * k + r] = c <= r ? xr[q] : 0.0;
   }
-  // R^-1 (upper), one column per thread: R x = e_j
-  if (tid < k) {
-    const int j = tid;
-    for (int i = j + 1; i < k; ++i) x[i][j] = 0.0;
-    x[j][j] = 1.0 / g[j][j];
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int q = i + 1; q <= j; ++q) s += g[i][q] * x[q][j];
-      x[i][j] = -s / g[i][i];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < k * k; e += 256) Rinv[e] = x[e / k][e % k];
-  if (tid == 0 && bad) {
+  if (tid == 0 && fail != 0) {
     if (*info == 0) *info = -2;
   }
 }
@@ -730,64 +1093,72 @@ __global__ __launch_bounds__(256) void larft_kernel(const double* __restrict__ V
     const int e = tid + 256 * q;
     gv[e / kWY][e % kWY] = acc[q];
   }
+  for (int e = tid; e < kWY * kWY; e += 256) T[e / kWY][e % kWY] = 0.0;
   __syncthreads();
-  if (tid == 0) {
-    for (int c = 0; c < kWY; ++c)
-      for (int r = 0; r < kWY; ++r) T[r][c] = 0.0;
-    for (int c = 0; c < nb; ++c) {
-      const double tc = tau[j0 + c];
-      T[c][c] = tc;
-      for (int r = 0; r < c; ++r) {
-        double s = 0.0;
-        for (int q = r; q < c; ++q) s += T[r][q] * gv[q][c];
-        T[r][c] = -tc * s;
-      }
+  // column c needs columns < c: one column per step, its rows in parallel
+  for (int c = 0; c < nb; ++c) {
+    const double tc = tau[j0 + c];
+    if (tid < c) {
+      double s = 0.0;
+      for (int q = tid; q < c; ++q) s += T[tid][q] * gv[q][c];
+      T[tid][c] = -tc * s;
     }
+    if (tid == c) T[c][c] = tc;
+    __syncthreads();
   }
-  __syncthreads();
   for (int e = tid; e < kWY * kWY; e += 256) Tout[(int64_t)b * kWY * kWY + e] = T[e / kWY][e % kWY];
 }
 
-// One workgroup per eigenvector: z = Q x with Q = H_0 H_1 ... (blocks applied
-// last first), z in LDS; output row m of Z [k][N].
-__global__ __launch_bounds__(256) void backtransform_kernel(const double* __restrict__ X, int k,
+// One 1024-thread workgroup per eigenvector: z = Q x with Q = H_0 H_1 ...
+// (blocks applied last first), z in LDS; output row m of Z [k][N].  In the
+// first pass of a block, wave w forms the dot products of reflectors w and
+// w + 16 with z (two wave reductions per wave); the second pass updates z
+// elementwise.
+constexpr int kBT = 1024;
+static_assert(kWY == 2 * (kBT / 64), "two reflectors per wave in the dot-product pass");
+
+__global__ __launch_bounds__(kBT) void backtransform_kernel(const double* __restrict__ X, int k,
                                                             const double* __restrict__ Vt,
                                                             int64_t ld,
                                                             const double* __restrict__ Tf,
                                                             int N, int nrefl, int nblocks,
                                                             double* __restrict__ Z) {
   extern __shared__ double z[];
-  __shared__ double red[4][kWY];
+  __shared__ double vz[kWY];
   __shared__ double pp[kWY];
   const int m = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < N; i += 256) z[i] = X[(int64_t)i * k + m];
+  for (int i = tid; i < N; i += kBT) z[i] = X[(int64_t)i * k + m];
   __syncthreads();
   for (int b = nblocks - 1; b >= 0; --b) {
     const int j0 = b * kWY, nb = min(kWY, nrefl - j0);
     const double* V = Vt + (int64_t)j0 * ld;
-    double acc[kWY];
-#pragma unroll
-    for (int c = 0; c < kWY; ++c) acc[c] = 0.0;
-    for (int i = j0 + 1 + tid; i < N; i += 256) {
-      const double zi = z[i];
-#pragma unroll
-      for (int c = 0; c < kWY; ++c)
-        if (c < nb) acc[c] += V[(int64_t)c * ld + i] * zi;
-    }
-#pragma unroll
-    for (int c = 0; c < kWY; ++c) {
-      const double s = wave_sum(acc[c]);
-      if (lane == 0) red[wave][c] = s;
+    {
+      const int c0 = wave, c1 = wave + kBT / 64;
+      const double* v0 = V + (int64_t)c0 * ld;
+      const double* v1 = V + (int64_t)c1 * ld;
+      double a0 = 0.0, a1 = 0.0;
+      // reflector j0 + c is zero up to index j0 + c
+      for (int i = j0 + 1 + lane; i < N; i += 64) {
+        const double zi = z[i];
+        if (c0 < nb) a0 += v0[i] * zi;
+        if (c1 < nb) a1 += v1[i] * zi;
+      }
+      a0 = wave_sum(a0);
+      a1 = wave_sum(a1);
+      if (lane == 0) {
+        vz[c0] = a0;
+        vz[c1] = a1;
+      }
     }
     __syncthreads();
     if (tid < kWY) {
       const double* T = Tf + (int64_t)b * kWY * kWY + tid * kWY;
       double s = 0.0;
-      for (int c = tid; c < kWY; ++c) s += T[c] * (red[0][c] + red[1][c] + red[2][c] + red[3][c]);
+      for (int c = tid; c < kWY; ++c) s += T[c] * vz[c];
       pp[tid] = s;
     }
     __syncthreads();
-    for (int i = j0 + 1 + tid; i < N; i += 256) {
+    for (int i = j0 + 1 + tid; i < N; i += kBT) {
       double s = 0.0;
 #pragma unroll
       for (int c = 0; c < kWY; ++c)
@@ -796,7 +1167,7 @@ __global__ __launch_bounds__(256) void backtransform_kernel(const double* __rest
     }
     __syncthreads();
   }
-  for (int i = tid; i < N; i += 256) Z[(int64_t)m * N + i] = z[i];
+  for (int i = tid; i < N; i += kBT) Z[(int64_t)m * N + i] = z[i];
 }
 
 // ------------------------------------------------------------------ plan
@@ -813,7 +1184,7 @@ DensePlan plan_dense(int N, int k) {
   p.Np = (int)ceil_div(N, kNB) * kNB;
   p.nrefl = std::max(N - 2, 0);
   p.nwy = (int)ceil_div(p.nrefl, kWY);
-  p.nchunks = (int)ceil_div(N, 64);
+  p.nchunks = (int)ceil_div(N, kGramRows);
   const size_t np2 = sizeof(double) * (size_t)p.Np * p.Np;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -825,7 +1196,7 @@ DensePlan plan_dense(int N, int k) {
   p.off_Linv = take(np2);
   p.off_C = take(np2);
   p.off_W = take(np2);
-  p.off_vec = take(sizeof(double) * 5 * (size_t)p.Np);
+  p.off_vec = take(sizeof(double) * 7 * (size_t)p.Np);
   p.off_f = take(sizeof(double) * 5 * (size_t)N * k);
   p.off_X = take(sizeof(double) * (size_t)N * k);
   p.off_part = take(sizeof(double) * (size_t)p.nchunks * k * k);
@@ -920,21 +1291,24 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
   TridArgs t;
   t.C = C;
   t.Vt = W;
-  t.y = vec;
-  t.w = vec + Np;
-  t.d = vec + 2 * Np;
-  t.e = vec + 3 * Np;
-  t.tau = vec + 4 * Np;
+  t.y[0] = vec;
+  t.y[1] = vec + Np;
+  t.part[0] = vec + 2 * Np;
+  t.part[1] = vec + 3 * Np;
+  t.d = vec + 4 * Np;
+  t.e = vec + 5 * Np;
+  t.tau = vec + 6 * Np;
   t.ld = ld;
   t.N = N;
-  for (int j = 0; j < N; ++j) {
-    hipLaunchKernelGGL(tridiag_house_kernel, dim3(1), dim3(256), 0, stream, t, j);
-    TL_CHECK_LAUNCH();
-    if (j <= N - 2) {
-      const int rows = N - j - 1;
-      hipLaunchKernelGGL(tridiag_update_kernel, dim3((unsigned)ceil_div(rows, 8)), dim3(256), 0,
-                         stream, t, j);
+  {
+    int nparts = 0;
+    const size_t lds = sizeof(double) * ((size_t)N + 1);
+    for (int j = 0; j < N; ++j) {
+      const int grid = std::max(1, (int)ceil_div(N - j - 1, kTR));
+      hipLaunchKernelGGL(tridiag_step_kernel, dim3((unsigned)grid), dim3(kTT), lds, stream, t, j,
+                         nparts);
       TL_CHECK_LAUNCH();
+      nparts = grid;
     }
   }
   // 5. eigenvalues
@@ -946,9 +1320,26 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
   double* F = (double*)(base + p.off_f);
   double* X = (double*)(base + p.off_X);
   InvArgs ia{T, evals, F, X, k};
-  hipLaunchKernelGGL(inverse_iter_kernel, dim3((unsigned)ceil_div(k, 64)), dim3(64), 0, stream,
-                     ia);
-  TL_CHECK_LAUNCH();
+  {
+    // per-eigenvalue LDS variant when 6 N doubles + N bytes fit in one
+    // workgroup's LDS, else the global-memory variant
+    const size_t lds = sizeof(double) * 6 * (size_t)N + (size_t)N;
+    int dev = 0, max_lds = 0;
+    TL_HIP(hipGetDevice(&dev));
+    TL_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    bool use_lds = lds + 64 <= (size_t)max_lds;
+    if (use_lds && lds > 65536)
+      use_lds = hipFuncSetAttribute((const void*)inverse_iter_lds_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds) == hipSuccess;
+    (void)hipGetLastError();
+    if (use_lds)
+      hipLaunchKernelGGL(inverse_iter_lds_kernel, dim3((unsigned)k), dim3(64), lds, stream, ia);
+    else
+      hipLaunchKernelGGL(inverse_iter_kernel, dim3((unsigned)ceil_div(k, 64)), dim3(64), 0,
+                         stream, ia);
+    TL_CHECK_LAUNCH();
+  }
   double* part = (double*)(base + p.off_part);
   double* R = (double*)(base + p.off_R);
   for (int pass = 0; pass < 2; ++pass) {
@@ -970,7 +1361,7 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
                        N, p.nrefl, Tf);
     TL_CHECK_LAUNCH();
   }
-  hipLaunchKernelGGL(backtransform_kernel, dim3((unsigned)k), dim3(256), sizeof(double) * N,
+  hipLaunchKernelGGL(backtransform_kernel, dim3((unsigned)k), dim3(kBT), sizeof(double) * N,
                      stream, X, k, W, ld, Tf, N, p.nrefl, p.nwy, Z);
   TL_CHECK_LAUNCH();
   // u^T = z^T L^-1 (rows of Z times the lower-triangular inverse)
