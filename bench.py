@@ -141,6 +141,116 @@ def measure(sys_, precision, n_slices, steps, warmup):
     }
 
 
+def box_chain_section(steps: int, warmup: int):
+    """256-site open chain (N_b = 2048): GPU assembly of the full H, S and the
+    dense lowest-64 generalized eigensolve, timed with HIP events (stage
+    events inside the eigensolver); eigenvalues checked against the oracle's,
+    stored by tests/golden/make_box_chain_eigs.py."""
+    import torch
+    from paper_1408_3839_amd import tl, workloads
+    from paper_1408_3839_amd.pipeline import BoxPipeline
+
+    s = workloads.config(3)
+    bp = BoxPipeline(s, k=64)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(1, warmup)):
+        bp.run()
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    asm, eig, stages = [], [], []
+    for _ in range(steps):
+        a0, a1 = ev(), ev()
+        st = [ev() for _ in range(6)]
+        for e in st:  # torch only times events it has recorded once itself
+            e.record(stream)
+        a0.record(stream)
+        bp.assemble()
+        a1.record(stream)
+        tl.tl_set_dense_eigh_events([e.cuda_event for e in st])
+        bp.eig.run(bp.H, bp.S)
+        tl.tl_set_dense_eigh_events(None)
+        torch.cuda.synchronize()
+        asm.append(a0.elapsed_time(a1))
+        eig.append(st[0].elapsed_time(st[5]))
+        stages.append([st[i].elapsed_time(st[i + 1]) for i in range(5)])
+    st_ms = np.median(np.array(stages), axis=0)
+    N = bp.Nb
+    # tridiagonalisation: one read + one write of the trailing (N-j-1)^2 block per column
+    tri_bytes = 16.0 * sum((N - j - 1) ** 2 for j in range(N))
+    golden = os.path.join(ROOT, "tests", "golden", "box_chain_256_lowest64.txt")
+    w_ref = np.array([float(l.split()[1]) for l in open(golden) if not l.startswith("#")])
+    ev_gpu = bp.eig.evals.cpu().numpy()
+    t0 = time.perf_counter()
+    import oracle
+    oracle.lowest_generalized_eigs(bp.H.cpu().numpy(), bp.S.cpu().numpy(), 64)
+    cpu_eigh_s = time.perf_counter() - t0
+    asm_ms, eig_ms = float(np.median(asm)), float(np.median(eig))
+    return {
+        "workload": "open (256,1,1) chain, 1.8 bohr, Z alternating 1/3, m0=8, grid 8500x256x256, "
+                    "h=0.0625, R=32; N_b=2048; lowest 64 generalized eigenpairs",
+        "assembly_ms": asm_ms,
+        "eigensolve_ms": eig_ms,
+        "ms_per_step": asm_ms + eig_ms,
+        "entries_per_s": N * N / (asm_ms * 1e-3),
+        "eigensolve_stage_ms": {"cholesky_and_inverse": st_ms[0], "reduce_to_standard": st_ms[1],
+                                "tridiagonalisation": st_ms[2], "eigenvalues": st_ms[3],
+                                "eigenvectors": st_ms[4]},
+        "tridiagonalisation_roofline": {
+            "bound": "hbm", "achieved": tri_bytes / (st_ms[2] * 1e-3) / 1e9, "peak": 8000.0,
+            "unit": "GB/s", "frac": tri_bytes / (st_ms[2] * 1e-3) / 8e12,
+            "algorithmic_bytes": tri_bytes},
+        "max_abs_dlambda_vs_oracle_Ha": float(np.abs(ev_gpu - w_ref).max()),
+        "info": int(bp.eig.info.item()),
+        "oracle_eigh_on_host_s": cpu_eigh_s,
+    }
+
+
+def batch_section(steps: int, warmup: int):
+    """64 ragged periodic (L,1,1) instances, whole chain, one launch per
+    stage, replayed as one HIP graph; FP64 and split-BF16 x6."""
+    import torch
+    from paper_1408_3839_amd import tl, workloads
+    from paper_1408_3839_amd.pipeline import BatchPipeline
+
+    systems = workloads.batch(64)
+    out = {"workload": "64 periodic (L,1,1) chains, L~U{16..512}, m0 in {4,8,13}, a~U[1.6,2.4], "
+                       "h=0.0625, R=24", "instances": len(systems)}
+    entries = sum(int(s.L[0]) * s.m0 * s.m0 for s in systems)
+    flops = sum(contraction_flops(s, tl.tl_query_sizes(s)) for s in systems)
+    for prec, nsl in (("fp64", 0), ("split_bf16", 6)):
+        bp = BatchPipeline(systems, precision=prec, n_slices=nsl)
+        for _ in range(max(1, warmup)):
+            bp.run()
+        bp.capture()
+        bp.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bp.replay()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        stream = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        b.record(stream)
+        tl.tl_set_contraction_events(a.cuda_event, b.cuda_event)
+        bp.run()
+        tl.tl_set_contraction_events(None, None)
+        torch.cuda.synchronize()
+        cms = a.elapsed_time(b)
+        mult = nsl * (nsl + 1) // 2 if nsl else 1
+        out[prec + (f"x{nsl}" if nsl else "")] = {
+            "ms_per_step": ms, "entries_per_s": entries / (ms * 1e-3),
+            "k_blocks_per_s": sum(int(s.L[0]) for s in systems) / (ms * 1e-3),
+            "contraction_ms": cms,
+            "contraction_tflops": flops * mult / (cms * 1e-3) / 1e12,
+        }
+        del bp
+        torch.cuda.synchronize()
+    out["entries_per_step"] = entries
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +262,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true", help="time the headline mode only")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-box", action="store_true", help="skip the open-chain section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch section")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -255,6 +367,10 @@ def main():
                 k: fp64["ms_per_step"] / v["ms_per_step"] for k, v in table.items()}
             out["split_vs_plain_contraction_speedup"] = {
                 k: fp64["contraction_ms"] / v["contraction_ms"] for k, v in table.items()}
+    if not args.no_box:
+        out["box_chain"] = box_chain_section(min(args.steps, 5), 1)
+    if not args.no_batch:
+        out["batch"] = batch_section(min(args.steps, 10), 2)
     print(json.dumps(out))
 
 

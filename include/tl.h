@@ -244,6 +244,16 @@ tl_status tl_batched_heigh(const double* H_dev, const double* S_dev, int count, 
  * back-transformation.  Asynchronous on `stream`; allocates nothing.
  */
 tl_status tl_dense_gen_eigh_workspace_bytes(int N, int k, size_t* bytes);
+
+/*
+ * tl_set_dense_eigh_events - profiling hook: with count = 6, the
+ * tl_dense_gen_eigh_lowest calls made afterwards by the calling thread
+ * record events[i] (hipEvent_t) on their stream at the stage boundaries:
+ * 0 before the Cholesky factorisation, 1 after L and L^-1, 2 after
+ * C = L^-1 H L^-T, 3 after the tridiagonalisation, 4 after the eigenvalues,
+ * 5 at the end.  count = 0 switches the hook off.  Events stay caller-owned.
+ */
+tl_status tl_set_dense_eigh_events(void* const* events, int count);
 tl_status tl_dense_gen_eigh_lowest(const double* H_dev, const double* S_dev, int N, int k,
                                    double* evals_dev, double* evecs_dev, int* info_dev,
                                    void* ws_dev, size_t ws_bytes, void* stream);

@@ -1207,6 +1207,18 @@ DensePlan plan_dense(int N, int k) {
   return p;
 }
 
+// Optional HIP events recorded at the stage boundaries of the next calls of
+// this thread (profiling hook): 0 before the Cholesky factorisation, 1 after
+// L and L^-1, 2 after C = L^-1 H L^-T, 3 after the tridiagonalisation, 4
+// after the eigenvalues, 5 after the eigenvectors.
+constexpr int kStages = 6;
+thread_local hipEvent_t g_stage[kStages] = {};
+
+tl_status stage_mark(int i, hipStream_t stream) {
+  if (g_stage[i] != nullptr) TL_HIP(hipEventRecord(g_stage[i], stream));
+  return TL_OK;
+}
+
 tl_status check_dense(int N, int k) {
   TL_REQUIRE(N >= 1 && N <= kMaxN, "dense eigensolver: N = %d outside [1, %d]", N, kMaxN);
   TL_REQUIRE(k >= 1 && k <= N && k <= kMaxK, "dense eigensolver: k = %d outside [1, min(N, %d)]",
@@ -1236,6 +1248,7 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
   const int64_t ld = Np;
 
   // 1. Cholesky
+  TL_TRY(stage_mark(0, stream));
   hipLaunchKernelGGL(setup_kernel, dim3((unsigned)ceil_div((int64_t)Np * Np, 256)), dim3(256), 0,
                      stream, S, N, Np, L, Linv, info);
   TL_CHECK_LAUNCH();
@@ -1279,6 +1292,7 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
     const int o_last = nfull * 2 * s;
     if (o_last + s < Np) TL_TRY(level(o_last, Np - o_last - s, 1));
   }
+  TL_TRY(stage_mark(1, stream));
   // 3. C = Linv H Linv^T (N x N, row stride ld)
   TL_TRY(gemm(gemm_args(Linv, ld, H, N, W, ld, N, N, N, 1.0, 0.0, 1), false, 1, stream));
   {
@@ -1287,6 +1301,7 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
     g.mirror = 1;
     TL_TRY(gemm(g, true, 1, stream));
   }
+  TL_TRY(stage_mark(2, stream));
   // 4. tridiagonalisation; reflectors reuse W
   TridArgs t;
   t.C = C;
@@ -1311,11 +1326,13 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
       nparts = grid;
     }
   }
+  TL_TRY(stage_mark(3, stream));
   // 5. eigenvalues
   TriSpec T{t.d, t.e, N};
   hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)k), dim3(256), 0, stream, T, evals);
   TL_CHECK_LAUNCH();
-  if (evecs == nullptr) return TL_OK;
+  TL_TRY(stage_mark(4, stream));
+  if (evecs == nullptr) return stage_mark(5, stream);
   // 6. eigenvectors of T
   double* F = (double*)(base + p.off_f);
   double* X = (double*)(base + p.off_X);
@@ -1366,12 +1383,21 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
   TL_CHECK_LAUNCH();
   // u^T = z^T L^-1 (rows of Z times the lower-triangular inverse)
   TL_TRY(gemm(gemm_args(Z, N, Linv, ld, evecs, N, k, N, N, 1.0, 0.0, 2), false, 1, stream));
-  return TL_OK;
+  return stage_mark(5, stream);
 }
 
 size_t dense_eigh_workspace_bytes(int N, int k) { return plan_dense(N, k).bytes; }
 
 }  // namespace tl
+
+extern "C" tl_status tl_set_dense_eigh_events(void* const* events, int count) {
+  tl::clear_error();
+  TL_REQUIRE(count == 0 || (events != nullptr && count == tl::kStages),
+             "give %d events or none", tl::kStages);
+  for (int i = 0; i < tl::kStages; ++i)
+    tl::g_stage[i] = count ? (hipEvent_t)events[i] : nullptr;
+  return TL_OK;
+}
 
 extern "C" tl_status tl_dense_gen_eigh_workspace_bytes(int N, int k, size_t* bytes) {
   tl::clear_error();

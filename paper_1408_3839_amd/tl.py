@@ -109,6 +109,7 @@ SIGNATURES = {
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "tl_dense_gen_eigh_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int,
                                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "tl_set_dense_eigh_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "tl_dense_gen_eigh_lowest": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                                 ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
@@ -302,6 +303,15 @@ def tl_dense_gen_eigh_workspace_bytes(N, k) -> int:
     _check(load().tl_dense_gen_eigh_workspace_bytes(int(N), int(k), ctypes.byref(v)),
            "tl_dense_gen_eigh_workspace_bytes")
     return v.value
+
+
+def tl_set_dense_eigh_events(events=None):
+    """events: six raw hipEvent_t handles (ints), or None to switch off."""
+    if events is None:
+        _check(load().tl_set_dense_eigh_events(None, 0), "tl_set_dense_eigh_events")
+        return
+    arr = (ctypes.c_void_p * len(events))(*events)
+    _check(load().tl_set_dense_eigh_events(arr, len(events)), "tl_set_dense_eigh_events")
 
 
 def tl_dense_gen_eigh_lowest(H, S, N, k, evals, evecs, info, ws, ws_bytes, stream=None):
