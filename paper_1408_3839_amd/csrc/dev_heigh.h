@@ -20,7 +20,7 @@ constexpr int kMaxSweeps = 60;
 
 // Partner of index x in round r of the round-robin ordering of `me` (even)
 // indices: me-1 meets r, every other pair {r+k, r-k} (mod me-1).
-__device__ inline int rr_partner(int x, int r, int me) {
+__device__ __forceinline__ int rr_partner(int x, int r, int me) {
   const int n1 = me - 1;
   if (x == n1) return r;
   if (x == r) return n1;
@@ -38,7 +38,7 @@ struct Rot {
   double c, s, tb, ph_re, ph_im;
 };
 
-__device__ inline Rot make_rot(double a, double d, cx b, bool valid) {
+__device__ __forceinline__ Rot make_rot(double a, double d, cx b, bool valid) {
   Rot r = {1.0, 0.0, 0.0, 1.0, 0.0};
   double b2 = cabs2(b);
   if (!valid || !(b2 > 0.0)) return r;
@@ -54,12 +54,200 @@ __device__ inline Rot make_rot(double a, double d, cx b, bool valid) {
   return r;
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates
+// (v_rcp_f64, v_rsq_f64) refined by two Newton steps each; the quadratic
+// convergence of Newton's iteration takes the estimate to full FP64 accuracy
+// (not necessarily correctly rounded).  Arguments must be normal and finite.
+__device__ __forceinline__ double nrcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double nrsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
+// The rotation of make_rot with the long-latency operations replaced by the
+// refined estimates: sqrt(u) = u rsq(u).  |b|^2 below 1e-290 counts as 0.
+__device__ __forceinline__ Rot make_rot_fast(double a, double d, cx b, bool valid) {
+  Rot r = {1.0, 0.0, 0.0, 1.0, 0.0};
+  const double b2 = cabs2(b);
+  if (!valid || !(b2 > 1e-290)) return r;
+  const double inv_ab = nrsq(b2);
+  const double tau = 0.5 * (d - a) * inv_ab;
+  const double at = fabs(tau);
+  double t;
+  if (at > 1e150) {
+    t = 0.5 / tau;
+  } else {
+    const double u = fma(tau, tau, 1.0);
+    t = copysign(nrcp(at + u * nrsq(u)), tau);
+  }
+  r.c = nrsq(fma(t, t, 1.0));
+  r.s = t * r.c;
+  r.tb = t * (b2 * inv_ab);
+  r.ph_re = b.re * inv_ab;
+  r.ph_im = -b.im * inv_ab;
+  return r;
+}
+
+// ---------------------------------------------------------------- m0 <= 8
+// One wave per k-block, lane 8 i + j holding entry (i, j) of every 8 x 8
+// (padded) matrix in registers: S, its Cholesky factor L, X = L^-1, C, V.
+// All exchanges are cross-lane reads, so no step needs a barrier.  Padded
+// indices carry S = I, H = 0 and never rotate.  Same stages and the same
+// rotation formulas as the LDS version below.
+__device__ inline cx shfl_cx(cx v, int src) { return {__shfl(v.re, src), __shfl(v.im, src)}; }
+
+__device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
+                                        const double* __restrict__ S, int m,
+                                        double* __restrict__ evals, double* __restrict__ evecs,
+                                        int* __restrict__ info, int64_t blk) {
+  const int lane = threadIdx.x & 63, i = lane >> 3, j = lane & 7;
+  const bool in = i < m && j < m;
+  const int mm = m * m;
+  const cx* Hb = (const cx*)H + blk * mm;
+  const cx* Sb = S ? (const cx*)S + blk * mm : nullptr;
+  const cx h = in ? Hb[i * m + j] : cx{0.0, 0.0};
+  cx s = (in && Sb) ? Sb[i * m + j] : cx{i == j ? 1.0 : 0.0, 0.0};
+  // 1. Cholesky S = L L^H, lane (i, j <= i) ends with L[i][j]
+  int fail = 0;
+  if (Sb) {
+    for (int k = 0; k < m; ++k) {
+      const double d = __shfl(s.re, 9 * k);
+      // pivots at or below 1e-300 (and non-finite ones) count as not positive
+      if (!(d > 1e-300) || !isfinite(d)) {
+        fail = k + 1;
+        break;
+      }
+      const double inv = nrsq(d), lkk = d * inv;
+      if (j == k) s = i == k ? cx{lkk, 0.0} : (i > k ? cscale(s, inv) : s);
+      const cx lik = shfl_cx(s, 8 * i + k), ljk = shfl_cx(s, 8 * j + k);
+      if (j > k && i >= j) s = csub(s, cmul(lik, cconj(ljk)));
+    }
+    if (j > i) s = {0.0, 0.0};
+  }
+  if (fail) {
+    if (j == 0 && i < m) evals[blk * m + i] = NAN;
+    if (evecs && in) ((cx*)evecs)[blk * mm + i * m + j] = {0.0, 0.0};
+    if (lane == 0) info[blk] = fail;
+    return;
+  }
+  // 2. X = L^-1 by forward elimination on the identity, C = X H X^H
+  cx x = {i == j ? 1.0 : 0.0, 0.0};
+  cx c = h;
+  if (Sb) {
+    for (int r = 0; r < m; ++r) {
+      const double lrr = __shfl(s.re, 9 * r);
+      if (i == r) x = cscale(x, nrcp(lrr));
+      const cx xrj = shfl_cx(x, 8 * r + j), lir = shfl_cx(s, 8 * i + r);
+      if (i > r) x = csub(x, cmul(lir, xrj));
+    }
+    cx w = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w = cadd(w, cmul(shfl_cx(x, 8 * i + k), shfl_cx(h, 8 * k + j)));
+    c = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      c = cadd(c, cmul(shfl_cx(w, 8 * i + k), cconj(shfl_cx(x, 8 * j + k))));
+  }
+  {
+    const cx ct = shfl_cx(c, 8 * j + i);  // Hermitian average
+    c = i == j ? cx{c.re, 0.0} : cscale(cadd(c, cconj(ct)), 0.5);
+  }
+  // 3. cyclic Jacobi, round-robin pairs of the even-padded index set; C and
+  // V are published once per round through LDS (one wave: the barriers only
+  // order the LDS accesses)
+  __shared__ cx sc[64], sv[64];
+  cx v = {i == j ? 1.0 : 0.0, 0.0};
+  const int me = m + (m & 1);
+  int converged = (m == 1);
+  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+    double off = 0.0, all = 0.0;
+    if (in) {
+      all = cabs2(c);
+      off = i != j ? all : 0.0;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      all += __shfl_xor(all, o);
+    }
+    if (off <= 1e-32 * all) {
+      converged = 1;
+      break;
+    }
+    for (int r = 0; r < me - 1; ++r) {
+      const int ip = i < me ? rr_partner(i, r, me) : i;
+      const int jp = j < me ? rr_partner(j, r, me) : j;
+      const int pi = min(i, ip), qi = max(i, ip), pj = min(j, jp), qj = max(j, jp);
+      __syncthreads();  // the previous round's reads are done
+      sc[lane] = c;
+      sv[lane] = v;
+      __syncthreads();
+      const Rot ri = make_rot_fast(sc[9 * pi].re, sc[9 * qi].re, sc[8 * pi + qi],
+                                   qi < m && qi != pi);
+      const Rot rj = make_rot_fast(sc[9 * pj].re, sc[9 * qj].re, sc[8 * pj + qj],
+                                   qj < m && qj != pj);
+      const cx c_ijp = sc[8 * i + jp], c_ipj = sc[8 * ip + j];
+      const cx c_ipjp = sc[8 * ip + jp], v_ijp = sv[8 * i + jp];
+      // column i of J: J[i][i] and J[ip][i]; column j likewise
+      const bool fi = i < ip, fj = j < jp;
+      const cx Jii = fi ? cx{ri.c, 0.0} : cx{ri.ph_re * ri.c, ri.ph_im * ri.c};
+      const cx Jpi = fi ? cx{-ri.ph_re * ri.s, -ri.ph_im * ri.s} : cx{ri.s, 0.0};
+      const cx Jjj = fj ? cx{rj.c, 0.0} : cx{rj.ph_re * rj.c, rj.ph_im * rj.c};
+      const cx Jpj = fj ? cx{-rj.ph_re * rj.s, -rj.ph_im * rj.s} : cx{rj.s, 0.0};
+      cx na;
+      if (j == i) {
+        na = {c.re + (fi ? -ri.tb : ri.tb), 0.0};
+      } else if (j == ip) {
+        na = {0.0, 0.0};
+      } else {
+        const cx t0 = cadd(cmul(c, Jjj), cmul(c_ijp, Jpj));
+        const cx t1 = cadd(cmul(c_ipj, Jjj), cmul(c_ipjp, Jpj));
+        na = cadd(cmul(cconj(Jii), t0), cmul(cconj(Jpi), t1));
+      }
+      v = cadd(cmul(v, Jjj), cmul(v_ijp, Jpj));
+      c = na;
+    }
+  }
+  // 4. eigenvalues ascending (ties by index), u = L^-H v = X^H v
+  const double li = __shfl(c.re, 9 * i), lj = __shfl(c.re, 9 * j);
+  const bool before = j < m && (lj < li || (lj == li && j < i));
+  const uint64_t mask = __ballot(before);
+  const int rank_i = __popcll((mask >> (8 * i)) & 0xFFull);
+  if (i == j && i < m) evals[blk * m + rank_i] = c.re;
+  if (lane == 0) info[blk] = converged ? 0 : -1;
+  if (evecs) {
+    cx u = v;
+    if (Sb) {
+      u = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        u = cadd(u, cmul(cconj(shfl_cx(x, 8 * k + i)), shfl_cx(v, 8 * k + j)));
+    }
+    const int rank_j = __shfl(rank_i, 8 * j);
+    if (in) ((cx*)evecs)[blk * mm + i * m + rank_j] = u;
+  }
+}
+
 // One k-block per workgroup; blk is the block index (H, S, evals, evecs and
 // info are indexed by it).
 template <int MAXM>
 __device__ inline void heigh_body(const double* __restrict__ H, const double* __restrict__ S,
                                   int m, double* __restrict__ evals, double* __restrict__ evecs,
                                   int* __restrict__ info, int64_t blk_) {
+  // m <= 8 takes the one-wave register version whatever the launch width, so
+  // a block gets the same bits in the single and the batched launches
+  if (MAXM == 8 || m <= 8) {
+    if (threadIdx.x < 64) heigh_wave8_body(H, S, m, evals, evecs, info, blk_);
+    return;
+  }
   constexpr int LD = MAXM + 1;
   // two copies of C and of V so that a Jacobi round needs one barrier
   // (read one copy, write the other); L is the Cholesky factor.

@@ -16,7 +16,7 @@ static __constant__ double kGLw[4] = {0.36268378337836205, 0.3137066458778876, 0
 // is formed where it does not cancel (erfc of two positive or two negative
 // arguments); below, every erf difference cancels, and the integrand is so
 // smooth on the cell that Gauss-Legendre reaches full precision.
-__device__ double cell_int(double t, double x, double h, double A) {
+__device__ __forceinline__ double cell_int(double t, double x, double h, double A) {
   if (t * h < 0.5) {
     double acc = 0.0;
     double c = x - A;
