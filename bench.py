@@ -28,6 +28,32 @@ METRIC = "core-Hamiltonian entries/s + k-block eigs/s at ≤1e-6 Ha vs FP64, spl
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split_fp16": 2500.0}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_f64_periodic64_traffic.json")
+
+
+def source_digest(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per contraction launch from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (scaled by the copy-kernel calibration), or None
+    when the kernel's sources changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        if source_digest(t["sources"]) != t["sources_sha256"]:
+            return None
+        return float(t["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def contraction_flops(sys, sizes) -> float:
     """Algorithmic flops of the 1D contractions of one assembly:
     2 * sum_l ((T+2) m0) * (m0 S_l) * n_l, S_l = L_l/2+1 shifts on a torus."""
@@ -123,17 +149,18 @@ def measure(sys_, precision, n_slices, steps, warmup):
         a.record(stream)
         b.record(stream)
     torch.cuda.synchronize()
-    te0 = time.perf_counter()
+    # a bounded spin at the head of the queue keeps the device busy while the
+    # host enqueues all K steps, so each event pair brackets the kernel and
+    # not a host-side gap
+    torch.cuda._sleep(int(1e6) * (steps + 10))
     for k in range(steps):
         tl.tl_set_contraction_events(evs[k][0].cuda_event, evs[k][1].cuda_event)
         pl.run()
     torch.cuda.synchronize()
-    te1 = time.perf_counter()
     tl.tl_set_contraction_events(None, None)
     contr_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     return {
         "ms_per_step": 1e3 * (t1 - t0) / steps,
-        "eager_ms_per_step": 1e3 * (te1 - te0) / steps,
         "contraction_ms": contr_ms,
         "H": pl.H.cpu().numpy(), "S": pl.S.cpu().numpy(),
         "evals": pl.evals.cpu().numpy(), "info": pl.info.cpu().numpy(),
@@ -262,6 +289,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true", help="time the headline mode only")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device once (reference kernel for the "
+                         "HBM byte counters) and exit")
     ap.add_argument("--no-box", action="store_true", help="skip the open-chain section")
     ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch section")
     args = ap.parse_args()
@@ -270,6 +300,17 @@ def main():
               "(the lattice instances would be sharded across GPUs without exchange).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes_read": 8 * n, "calibration_copy_bytes_written": 8 * n}))
+        return
 
     from paper_1408_3839_amd import workloads
 
@@ -296,7 +337,8 @@ def main():
         achieved = flops * mult / (r["contraction_ms"] * 1e-3) / 1e12
         peak = PEAK_TFLOPS[prec]
         return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak,
+                "traffic": measured_traffic() if prec == "fp64" else None,
                 "kernel": ("contract_split_kernel" if prec.startswith("split") else
                            f"contract_{'f32' if prec == 'fp32' else 'f64'}_kernel")
                 + " (1D contractions of the three dims, one launch)",
@@ -325,7 +367,6 @@ def main():
             "precision": args.precision,
             "slices": head_slices,
             "step": "one HIP-graph replay of the whole path",
-            "eager_ms_per_step": head["eager_ms_per_step"],
             "entries_per_step": entries,
             "k_blocks_per_step": sys_.ncells,
         },
