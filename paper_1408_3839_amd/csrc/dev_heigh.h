@@ -1,6 +1,8 @@
 // Device code of step a7 (batched generalized Hermitian eigensolver of the
 // k-block pencils), shared by the single-system and the batched launches.
 #pragma once
+#include <cfloat>
+
 #include "common.h"
 
 namespace tl {
@@ -159,6 +161,117 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
   {
     const cx ct = shfl_cx(c, 8 * j + i);  // Hermitian average
     c = i == j ? cx{c.re, 0.0} : cscale(cadd(c, cconj(ct)), 0.5);
+  }
+  if (evecs == nullptr) {
+    // eigenvalues only: Householder reduction of C to a real tridiagonal
+    // (LAPACK zhetd2 convention: x = C[k+1:, k], beta = -sign(Re alpha)
+    // sqrt(|alpha|^2 + |x'|^2), tau = ((beta - Re alpha) - i Im alpha) / beta,
+    // v = (1, x' / (alpha - beta)); w = tau C v, w -= 1/2 tau (w^H v) v,
+    // C -= v w^H + w v^H), then Sturm bisection on (d, e^2).
+    double e2[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      if (k > m - 3) break;  // uniform
+      const cx xi = shfl_cx(c, 8 * i + k), xj = shfl_cx(c, 8 * j + k);
+      const cx alpha = shfl_cx(c, 8 * (k + 1) + k);
+      double sq = (j == k && i >= k + 2) ? cabs2(c) : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+      if (sq == 0.0 && alpha.im == 0.0) {
+        e2[k] = alpha.re * alpha.re;  // already reduced: H = I
+        continue;
+      }
+      const double beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + sq), alpha.re);
+      const cx tau = {(beta - alpha.re) / beta, -alpha.im / beta};
+      const cx den = {alpha.re - beta, alpha.im};
+      const double dd = 1.0 / cabs2(den);
+      const cx rden = {den.re * dd, -den.im * dd};  // 1 / (alpha - beta)
+      const cx vi = i == k + 1 ? cx{1.0, 0.0} : (i > k + 1 ? cmul(xi, rden) : cx{0.0, 0.0});
+      const cx vj = j == k + 1 ? cx{1.0, 0.0} : (j > k + 1 ? cmul(xj, rden) : cx{0.0, 0.0});
+      // w_i = tau sum_j C[i][j] v_j over the trailing block (row groups of 8 lanes)
+      cx t = (i > k && j > k) ? cmul(c, vj) : cx{0.0, 0.0};
+#pragma unroll
+      for (int o = 4; o > 0; o >>= 1) {
+        t.re += __shfl_xor(t.re, o);
+        t.im += __shfl_xor(t.im, o);
+      }
+      cx wi = cmul(tau, t);
+      // K = -1/2 tau (w^H v): one lane per row contributes conj(w_i) v_i
+      cx kk = (j == 0 && i > k) ? cmul(cconj(wi), vi) : cx{0.0, 0.0};
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        kk.re += __shfl_xor(kk.re, o);
+        kk.im += __shfl_xor(kk.im, o);
+      }
+      const cx K = cscale(cmul(tau, kk), -0.5);
+      wi = cadd(wi, cmul(K, vi));
+      const cx wj = shfl_cx(wi, 8 * j);
+      if (i > k && j > k) c = csub(c, cadd(cmul(vi, cconj(wj)), cmul(wi, cconj(vj))));
+      e2[k] = beta * beta;
+    }
+    // the last off-diagonal element needs no reflector
+    double d8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) d8[q] = __shfl(c.re, 9 * q);
+    if (m >= 2) {
+      const cx last = shfl_cx(c, 8 * (m - 1) + (m - 2));
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q == m - 2) e2[q] = cabs2(last);
+    }
+    // Gershgorin interval and pivot floor (dstebz conventions)
+    double lo = 1e308, hi = -1e308, emax = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q >= m) break;
+      const double el = q > 0 ? sqrt(e2[q - 1]) : 0.0, er = q < m - 1 ? sqrt(e2[q]) : 0.0;
+      lo = fmin(lo, d8[q] - el - er);
+      hi = fmax(hi, d8[q] + el + er);
+      if (q < m - 1) emax = fmax(emax, e2[q]);
+    }
+    const double pivmin = DBL_MIN * fmax(1.0, emax);
+    const double tn = fmax(fabs(lo), fabs(hi));
+    const double fudge = 2.1 * DBL_EPSILON * tn * m + 4.2 * pivmin;
+    lo -= fudge;
+    hi += fudge;
+    // eigenvalue idx = lane / 8; each lane runs two interleaved Sturm
+    // sequences, so a round counts at sixteen interior points per eigenvalue
+    const int idx = lane >> 3, pt = lane & 7;
+    for (int round = 0; round < 40; ++round) {
+      const bool done = hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin;
+      if (__all(done || idx >= m)) break;
+      const double x0 = lo + (hi - lo) * ((double)(2 * pt + 1) / 17.0);
+      const double x1 = lo + (hi - lo) * ((double)(2 * pt + 2) / 17.0);
+      double q0 = d8[0] - x0, q1 = d8[0] - x1;
+      if (fabs(q0) < pivmin) q0 = -pivmin;
+      if (fabs(q1) < pivmin) q1 = -pivmin;
+      int c0 = q0 < 0.0, c1 = q1 < 0.0;
+#pragma unroll
+      for (int u = 1; u < 8; ++u) {
+        if (u >= m) break;
+        q0 = (d8[u] - x0) - e2[u - 1] * nrcp(q0);
+        q1 = (d8[u] - x1) - e2[u - 1] * nrcp(q1);
+        if (fabs(q0) < pivmin) q0 = -pivmin;
+        if (fabs(q1) < pivmin) q1 = -pivmin;
+        c0 += q0 < 0.0;
+        c1 += q1 < 0.0;
+      }
+      // x0 < x1 and counts are monotone: the pair brackets idx locally
+      double nlo = c1 <= idx ? x1 : (c0 <= idx ? x0 : lo);
+      double nhi = c0 > idx ? x0 : (c1 > idx ? x1 : hi);
+#pragma unroll
+      for (int o = 4; o > 0; o >>= 1) {
+        nlo = fmax(nlo, __shfl_xor(nlo, o));
+        nhi = fmin(nhi, __shfl_xor(nhi, o));
+      }
+      if (!done) {
+        lo = nlo;
+        hi = fmax(nhi, nlo);
+      }
+    }
+    if (pt == 0 && idx < m) evals[blk * m + idx] = 0.5 * (lo + hi);
+    if (lane == 0) info[blk] = 0;
+    return;
   }
   // 3. cyclic Jacobi, round-robin pairs of the even-padded index set; C and
   // V are published once per round through LDS (one wave: the barriers only

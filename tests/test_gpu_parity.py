@@ -272,3 +272,40 @@ def test_graph_replay_matches_eager():
         pl.run()            # eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(pl.evals, ev0), rep
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 7, 8])
+@pytest.mark.parametrize("standard", [False, True])
+def test_heigh_eigenvalues_only(m, standard):
+    """Without eigenvectors, m0 <= 8 blocks take the Householder-tridiagonal +
+    Sturm-bisection route; eigenvalues against LAPACK within the first-order
+    bound, ascending, info = 0."""
+    rng = np.random.default_rng(300 + m + 50 * standard)
+    H, S = _random_pencils(rng, 41, m)
+    if standard:
+        S = None
+    ev, _, info = _run_heigh(H, S, evecs=False)
+    assert np.all(info == 0)
+    for j in range(H.shape[0]):
+        Sj = np.eye(m) if standard else S[j]
+        lam, U = sla.eigh(H[j], Sj)
+        assert np.all(np.abs(ev[j] - lam) <= _eig_tol(H[j], Sj, lam, U)), (m, j, ev[j] - lam)
+        assert np.all(np.diff(ev[j]) >= 0)
+
+
+def test_heigh_eigenvalues_only_degenerate_and_reduced():
+    """Exactly repeated eigenvalues and an already diagonal block (every
+    reflector is the identity) on the eigenvalue-only route."""
+    m = 8
+    H = np.zeros((3, m, m), complex)
+    H[0] = np.diag([1.0, 1.0, 1.0, 2.0, 2.0, -3.0, 0.5, 0.5])
+    Q, _ = np.linalg.qr(np.random.default_rng(4).standard_normal((m, m))
+                        + 1j * np.random.default_rng(5).standard_normal((m, m)))
+    H[1] = Q @ H[0] @ Q.conj().T
+    H[1] = (H[1] + H[1].conj().T) / 2
+    H[2] = np.diag(np.arange(m, dtype=float)) + np.diag(np.full(m - 1, 0.25), 1) + np.diag(np.full(m - 1, 0.25), -1)
+    ev, _, info = _run_heigh(H, None, evecs=False)
+    assert np.all(info == 0)
+    for j in range(3):
+        lam = np.linalg.eigvalsh(H[j])
+        assert np.abs(ev[j] - lam).max() <= 64 * 2.0 ** -52 * np.abs(lam).max(), (j, ev[j] - lam)
