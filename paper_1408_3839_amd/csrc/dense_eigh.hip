@@ -15,8 +15,8 @@
 //      then applies the previous step's rank-2 update to its trailing rows
 //      and multiplies them by the reflector in the same pass (one read and
 //      one write of the trailing matrix per column).
-//   5. The k lowest eigenvalues of T by Sturm-count multisection (256 points
-//      per workgroup and round).
+//   5. The k lowest eigenvalues of T by Sturm-count multisection, one launch
+//      per round, 4096 points per eigenvalue and round over 8 workgroups.
 //   6. Eigenvectors of T by inverse iteration (partial-pivoting tridiagonal
 //      LU, three solves), orthonormalised by two Cholesky-QR passes.
 //   7. Back-transformation by the reflectors (compact WY blocks of 32) and
@@ -26,6 +26,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "dev_wave.h"
 
 namespace tl {
 namespace {
@@ -36,14 +37,27 @@ constexpr int kNB = 64;         // Cholesky / inverse block
 constexpr int kWY = 32;         // reflectors per back-transformation block
 constexpr int kMaxK = 64;       // eigenpairs per call
 constexpr int kMaxN = 7680;     // order (z in LDS during the back-transformation)
-constexpr int kMSect = 256;     // multisection points per round
 
 // ------------------------------------------------------------------ helpers
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+__device__ __forceinline__ double wave_sum(double v) { return dev::wave_sum_dpp(v); }
+
+// Reciprocal and reciprocal square root from the hardware estimates refined
+// by two Newton steps each (full FP64 accuracy, not necessarily correctly
+// rounded); arguments normal and finite.  They shorten the dependent chains
+// of the sequential steps against the correctly rounded sequences.
+__device__ __forceinline__ double nrcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double nrsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
 }
 
 // Sum over a 256-thread workgroup; every thread gets the result.
@@ -221,7 +235,7 @@ struct CholLds {
   double line[2][kNB];
   double xrow[2][kNB];
   double lcol[2][kNB];
-  double diag[kNB];
+  double rdiag[kNB];  // 1 / L[c][c]
 };
 
 __device__ int chol_inv_64(double (&ar)[16], double (&xr)[16], double pmin, CholLds& sh) {
@@ -229,6 +243,8 @@ __device__ int chol_inv_64(double (&ar)[16], double (&xr)[16], double pmin, Chol
 #pragma unroll
   for (int q = 0; q < 16; ++q) xr[q] = (g + 4 * q) == r ? 1.0 : 0.0;
   int fail = 0;
+  // fully unrolled: the register index of column c is a compile-time constant
+#pragma unroll
   for (int c = 0; c < kNB; ++c) {
     const int go = c & 3, qo = c >> 2;
     double* col = sh.line[c & 1];
@@ -241,11 +257,12 @@ __device__ int chol_inv_64(double (&ar)[16], double (&xr)[16], double pmin, Chol
     }
     __syncthreads();
     double piv = col[c];
-    if (!(piv > pmin)) {
+    if (!(piv > fmax(pmin, 1e-300))) {  // pivots at or below 1e-300 count as failed
       if (fail == 0) fail = c + 1;
       piv = 1.0;
     }
-    const double lcc = sqrt(piv), rinv = 1.0 / lcc;
+    const double rinv = nrsq(piv), lcc = piv * rinv;
+    if (tid == 0) sh.rdiag[c] = rinv;
     const double lrc = r > c ? col[r] * rinv : (r == c ? lcc : 0.0);
     double cv[16];
 #pragma unroll
@@ -257,21 +274,15 @@ __device__ int chol_inv_64(double (&ar)[16], double (&xr)[16], double pmin, Chol
       ar[q] = (q == qo && g == go && r >= c) ? lrc : ((r > c && cc > c && cc <= r) ? upd : ar[q]);
     }
   }
-  if (g == (r & 3)) {
-    double v = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (q == (r >> 2)) v = ar[q];
-    sh.diag[r] = v;
-  }
-  __syncthreads();
+  __syncthreads();  // rdiag complete
   // X = L^-1 by forward elimination on the identity: step i finalises row i
   // (scaled by 1 / L[i][i]) and removes L[r][i] * row i from rows r > i
+#pragma unroll
   for (int i = 0; i < kNB; ++i) {
     double* rowi = sh.xrow[i & 1];
     double* coli = sh.lcol[i & 1];
     if (r == i) {
-      const double sc = 1.0 / sh.diag[i];
+      const double sc = sh.rdiag[i];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         xr[q] *= sc;
@@ -454,9 +465,11 @@ __global__ __launch_bounds__(kTT) void tridiag_step_kernel(TridArgs t, int j, in
   const double alpha = s_alpha;
   double tau = 0.0, beta = alpha, scale = 0.0;
   if (sig > 0.0) {
-    beta = -copysign(sqrt(alpha * alpha + sig), alpha);
-    tau = (beta - alpha) / beta;
-    scale = 1.0 / (alpha - beta);
+    // |beta| = sqrt(u) = u rsq(u), 1 / beta = -sign(alpha) rsq(u)
+    const double u = fma(alpha, alpha, sig), ru = nrsq(u);
+    beta = -copysign(u * ru, alpha);
+    tau = (beta - alpha) * -copysign(ru, alpha);
+    scale = nrcp(alpha - beta);
   }
   for (int i = j + tid; i < N; i += kTT) vs[i] = i == j ? 0.0 : (i == j + 1 ? 1.0 : vs[i] * scale);
   __syncthreads();  // v_j complete in LDS
@@ -540,48 +553,36 @@ struct TriSpec {
   int N;
 };
 
-__device__ inline int sturm_count(const TriSpec& T, double x, double pivmin) {
-  int cnt = 0;
-  double q = T.d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  if (q < 0.0) ++cnt;
-  for (int i = 1; i < T.N; ++i) {
-    const double ei = T.e[i - 1];
-    q = (T.d[i] - x) - ei * ei / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    if (q < 0.0) ++cnt;
-  }
-  return cnt;
-}
-
 // Gershgorin interval, largest |entry| and the pivot floor of the Sturm
-// recurrence (LAPACK dstebz conventions).
+// recurrence (LAPACK dstebz conventions); every thread gets the results.
 __device__ inline void tri_bounds(const TriSpec& T, double* red, double& glo, double& ghi,
                                   double& pivmin) {
   double lo = 1e308, hi = -1e308, emax = 0.0;
-  for (int i = threadIdx.x; i < T.N; i += 256) {
+  for (int i = threadIdx.x; i < T.N; i += blockDim.x) {
     const double el = i > 0 ? fabs(T.e[i - 1]) : 0.0, er = i < T.N - 1 ? fabs(T.e[i]) : 0.0;
     lo = fmin(lo, T.d[i] - el - er);
     hi = fmax(hi, T.d[i] + el + er);
     emax = fmax(emax, er * er);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o));
-    hi = fmax(hi, __shfl_xor(hi, o));
-    emax = fmax(emax, __shfl_xor(emax, o));
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  lo = dev::wave_min_dpp(lo);
+  hi = dev::wave_max_dpp(hi);
+  emax = dev::wave_max_dpp(emax);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   __syncthreads();
   if (lane == 0) {
     red[wave] = lo;
-    red[4 + wave] = hi;
-    red[8 + wave] = emax;
+    red[16 + wave] = hi;
+    red[32 + wave] = emax;
   }
   __syncthreads();
-  glo = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
-  ghi = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
-  emax = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
+  glo = red[0];
+  ghi = red[16];
+  emax = red[32];
+  for (int w = 1; w < nw; ++w) {
+    glo = fmin(glo, red[w]);
+    ghi = fmax(ghi, red[16 + w]);
+    emax = fmax(emax, red[32 + w]);
+  }
   pivmin = DBL_MIN * fmax(1.0, emax);
   const double tnorm = fmax(fabs(glo), fabs(ghi));
   const double fudge = 2.1 * DBL_EPSILON * tnorm * T.N + 4.2 * pivmin;
@@ -589,77 +590,123 @@ __device__ inline void tri_bounds(const TriSpec& T, double* red, double& glo, do
   ghi += fudge;
 }
 
-// Eigenvalue m (0-based, ascending) of T per workgroup: each round counts
-// at 512 interior points (two interleaved Sturm sequences per thread, d and
-// e^2 staged through LDS) and keeps the sub-interval that holds index m.
+// Multisection for the k lowest eigenvalues, one launch per round: kBisWG
+// workgroups per eigenvalue, each counting at 512 interior points of the
+// current bracket (two interleaved Sturm sequences per thread, d and e^2
+// staged through LDS, the recurrence's reciprocal from nrcp), so a round
+// narrows the bracket 4097-fold.  Workgroup (m, w) reads the candidates that
+// the previous round's workgroups of eigenvalue m left in cand_in (their
+// largest point with count <= m and smallest above), and writes its own.
+constexpr int kBisWG = 8;
+constexpr int kBisRounds = 6;   // 6 x 12 bits cover the 53-bit mantissa
 constexpr int kBisChunk = 1024;
 
-__global__ __launch_bounds__(256) void bisect_kernel(TriSpec T, double* __restrict__ evals) {
-  __shared__ double red[12];
-  __shared__ double s_lo, s_hi;
-  __shared__ double sd[kBisChunk], se2[kBisChunk];
-  __shared__ double s_x[2 * kMSect];
-  __shared__ int s_c[2 * kMSect];
-  const int m = blockIdx.x, tid = threadIdx.x, N = T.N;
+struct BisArgs {
+  TriSpec T;
+  const double* bounds;  // glo, ghi, pivmin
+  const double* cand_in;   // [k][kBisWG][2]
+  double* cand_out;
+  int first;             // 1: start from the Gershgorin interval
+};
+
+__global__ __launch_bounds__(256) void bisect_bounds_kernel(TriSpec T, double* __restrict__ bounds) {
+  __shared__ double red[48];
   double glo, ghi, pivmin;
   tri_bounds(T, red, glo, ghi, pivmin);
-  double lo = glo, hi = ghi;
-  constexpr double kPts = 2.0 * kMSect + 1.0;
-  for (int round = 0; round < 24; ++round) {
-    const double tol = 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin;
-    if (hi - lo <= tol) break;  // uniform: lo, hi come from shared memory
-    const double x0 = lo + (hi - lo) * ((double)(2 * tid + 1) / kPts);
-    const double x1 = lo + (hi - lo) * ((double)(2 * tid + 2) / kPts);
-    int c0 = 0, c1 = 0;
-    double q0 = T.d[0] - x0, q1 = T.d[0] - x1;
-    if (fabs(q0) < pivmin) q0 = -pivmin;
-    if (fabs(q1) < pivmin) q1 = -pivmin;
-    c0 += q0 < 0.0;
-    c1 += q1 < 0.0;
-    for (int base = 1; base < N; base += kBisChunk) {
-      const int len = min(kBisChunk, N - base);
-      __syncthreads();
-      for (int u = tid; u < len; u += 256) {
-        sd[u] = T.d[base + u];
-        const double e = T.e[base + u - 1];
-        se2[u] = e * e;
-      }
-      __syncthreads();
-      for (int u = 0; u < len; ++u) {
-        const double du = sd[u], eu = se2[u];
-        q0 = (du - x0) - eu / q0;
-        q1 = (du - x1) - eu / q1;
-        if (fabs(q0) < pivmin) q0 = -pivmin;
-        if (fabs(q1) < pivmin) q1 = -pivmin;
-        c0 += q0 < 0.0;
-        c1 += q1 < 0.0;
-      }
-    }
-    s_x[2 * tid] = x0;
-    s_x[2 * tid + 1] = x1;
-    s_c[2 * tid] = c0;
-    s_c[2 * tid + 1] = c1;
-    __syncthreads();
-    if (tid == 0) {
-      double nlo = lo, nhi = hi;
-      for (int q = 0; q < 2 * kMSect; ++q) {
-        if (s_c[q] <= m)
-          nlo = fmax(nlo, s_x[q]);
-        else
-          nhi = fmin(nhi, s_x[q]);
-      }
-      if (nhi < nlo) nhi = nlo;
-      s_lo = nlo;
-      s_hi = nhi;
-    }
-    __syncthreads();
-    const double olo = lo, ohi = hi;
-    lo = s_lo;
-    hi = s_hi;
-    __syncthreads();
-    if (lo == olo && hi == ohi) break;  // no representable progress
+  if (threadIdx.x == 0) {
+    bounds[0] = glo;
+    bounds[1] = ghi;
+    bounds[2] = pivmin;
   }
-  if (tid == 0) evals[m] = 0.5 * (lo + hi);
+}
+
+__global__ __launch_bounds__(256) void bisect_round_kernel(BisArgs a) {
+  __shared__ double rlo[4], rhi[4];
+  __shared__ double sd[kBisChunk], se2[kBisChunk];
+  const int m = blockIdx.x / kBisWG, w = blockIdx.x % kBisWG, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, N = a.T.N;
+  const double pivmin = a.bounds[2];
+  double lo, hi;
+  if (a.first) {
+    lo = a.bounds[0];
+    hi = a.bounds[1];
+  } else {
+    const double* c = a.cand_in + (int64_t)m * kBisWG * 2;
+    lo = c[0];
+    hi = c[1];
+    for (int q = 1; q < kBisWG; ++q) {
+      lo = fmax(lo, c[2 * q]);
+      hi = fmin(hi, c[2 * q + 1]);
+    }
+    if (hi < lo) hi = lo;
+  }
+  double* out = a.cand_out + ((int64_t)m * kBisWG + w) * 2;
+  const double tol = 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin;
+  if (hi - lo <= tol) {  // converged: pass the bracket on (uniform per workgroup)
+    if (tid == 0) {
+      out[0] = lo;
+      out[1] = hi;
+    }
+    return;
+  }
+  constexpr double kPts = 2.0 * 256 * kBisWG + 1.0;
+  const int p0 = 2 * (w * 256 + tid);
+  const double x0 = lo + (hi - lo) * ((double)(p0 + 1) / kPts);
+  const double x1 = lo + (hi - lo) * ((double)(p0 + 2) / kPts);
+  int c0 = 0, c1 = 0;
+  double q0 = a.T.d[0] - x0, q1 = a.T.d[0] - x1;
+  if (fabs(q0) < pivmin) q0 = -pivmin;
+  if (fabs(q1) < pivmin) q1 = -pivmin;
+  c0 += q0 < 0.0;
+  c1 += q1 < 0.0;
+  for (int base = 1; base < N; base += kBisChunk) {
+    const int len = min(kBisChunk, N - base);
+    __syncthreads();
+    for (int u = tid; u < len; u += 256) {
+      sd[u] = a.T.d[base + u];
+      const double e = a.T.e[base + u - 1];
+      se2[u] = e * e;
+    }
+    __syncthreads();
+    for (int u = 0; u < len; ++u) {
+      const double du = sd[u], eu = se2[u];
+      q0 = (du - x0) - eu * nrcp(q0);
+      q1 = (du - x1) - eu * nrcp(q1);
+      if (fabs(q0) < pivmin) q0 = -pivmin;
+      if (fabs(q1) < pivmin) q1 = -pivmin;
+      c0 += q0 < 0.0;
+      c1 += q1 < 0.0;
+    }
+  }
+  double nlo = c1 <= m ? x1 : (c0 <= m ? x0 : lo);
+  double nhi = c0 > m ? x0 : (c1 > m ? x1 : hi);
+  nlo = dev::wave_max_dpp(nlo);
+  nhi = dev::wave_min_dpp(nhi);
+  if (lane == 0) {
+    rlo[wave] = nlo;
+    rhi[wave] = nhi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double blo = fmax(fmax(rlo[0], rlo[1]), fmax(rlo[2], rlo[3]));
+    double bhi = fmin(fmin(rhi[0], rhi[1]), fmin(rhi[2], rhi[3]));
+    out[0] = blo;
+    out[1] = bhi;
+  }
+}
+
+__global__ __launch_bounds__(64) void bisect_final_kernel(const double* __restrict__ cand, int k,
+                                                          double* __restrict__ evals) {
+  const int m = blockIdx.x * 64 + threadIdx.x;
+  if (m >= k) return;
+  const double* c = cand + (int64_t)m * kBisWG * 2;
+  double lo = c[0], hi = c[1];
+  for (int q = 1; q < kBisWG; ++q) {
+    lo = fmax(lo, c[2 * q]);
+    hi = fmin(hi, c[2 * q + 1]);
+  }
+  if (hi < lo) hi = lo;
+  evals[m] = 0.5 * (lo + hi);
 }
 
 // ------------------------------------------------------------------ inverse iteration
@@ -696,11 +743,8 @@ __global__ __launch_bounds__(64) void inverse_iter_kernel(InvArgs a) {
     lo = fmin(lo, a.T.d[i] - el - er);
     hi = fmax(hi, a.T.d[i] + el + er);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o));
-    hi = fmax(hi, __shfl_xor(hi, o));
-  }
+  lo = dev::wave_min_dpp(lo);
+  hi = dev::wave_max_dpp(hi);
   const double tnorm = fmax(fabs(lo), fabs(hi));
   const double pert = fmax(DBL_EPSILON * tnorm, DBL_MIN);
   const int m = blockIdx.x * 64 + threadIdx.x;
@@ -865,11 +909,8 @@ __global__ __launch_bounds__(64) void inverse_iter_lds_kernel(InvArgs a) {
     const uint64_t r = splitmix64(((uint64_t)m << 32) ^ (uint64_t)i);
     X[i] = (double)(r >> 11) * (2.0 / 9007199254740992.0) - 1.0;
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o));
-    hi = fmax(hi, __shfl_xor(hi, o));
-  }
+  lo = dev::wave_min_dpp(lo);
+  hi = dev::wave_max_dpp(hi);
   const double tnorm = fmax(fabs(lo), fabs(hi));
   const double pert = fmax(DBL_EPSILON * tnorm, DBL_MIN);
   __syncthreads();
@@ -1173,8 +1214,8 @@ __global__ __launch_bounds__(kBT) void backtransform_kernel(const double* __rest
 // ------------------------------------------------------------------ plan
 struct DensePlan {
   int N, Np, k, nrefl, nwy, nchunks;
-  size_t off_L, off_Linv, off_C, off_W, off_vec, off_f, off_X, off_part, off_R, off_T, off_Z,
-      bytes;
+  size_t off_L, off_Linv, off_C, off_W, off_vec, off_bis, off_f, off_X, off_part, off_R, off_T,
+      off_Z, bytes;
 };
 
 DensePlan plan_dense(int N, int k) {
@@ -1197,6 +1238,7 @@ DensePlan plan_dense(int N, int k) {
   p.off_C = take(np2);
   p.off_W = take(np2);
   p.off_vec = take(sizeof(double) * 7 * (size_t)p.Np);
+  p.off_bis = take(sizeof(double) * (4 + 4 * kBisWG * (size_t)k));
   p.off_f = take(sizeof(double) * 5 * (size_t)N * k);
   p.off_X = take(sizeof(double) * (size_t)N * k);
   p.off_part = take(sizeof(double) * (size_t)p.nchunks * k * k);
@@ -1329,8 +1371,21 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
   TL_TRY(stage_mark(3, stream));
   // 5. eigenvalues
   TriSpec T{t.d, t.e, N};
-  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)k), dim3(256), 0, stream, T, evals);
-  TL_CHECK_LAUNCH();
+  {
+    double* bounds = (double*)(base + p.off_bis);
+    double* cand[2] = {bounds + 4, bounds + 4 + 2 * kBisWG * (size_t)k};
+    hipLaunchKernelGGL(bisect_bounds_kernel, dim3(1), dim3(256), 0, stream, T, bounds);
+    TL_CHECK_LAUNCH();
+    for (int r = 0; r < kBisRounds; ++r) {
+      BisArgs ba{T, bounds, cand[r & 1], cand[(r + 1) & 1], r == 0};
+      hipLaunchKernelGGL(bisect_round_kernel, dim3((unsigned)(k * kBisWG)), dim3(256), 0, stream,
+                         ba);
+      TL_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(bisect_final_kernel, dim3((unsigned)ceil_div(k, 64)), dim3(64), 0, stream,
+                       cand[kBisRounds & 1], k, evals);
+    TL_CHECK_LAUNCH();
+  }
   TL_TRY(stage_mark(4, stream));
   if (evecs == nullptr) return stage_mark(5, stream);
   // 6. eigenvectors of T

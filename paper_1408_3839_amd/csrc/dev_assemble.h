@@ -3,6 +3,7 @@
 // single-system and the batched launches.
 #pragma once
 #include "common.h"
+#include "dev_wave.h"
 
 namespace tl {
 namespace dev {
@@ -546,10 +547,10 @@ __device__ inline void combine_periodic_body(const CombineArgs& a, int64_t total
            lookup(a, 2, a.T + 1, mu, nu, k3);
     }
   }
-  for (int o = 32; o > 0; o >>= 1) V += __shfl_xor(V, o);
-  const int tl = a.T % 64, sl = (a.T + 1) % 64;
-  Tk = __shfl(Tk, tl);
-  Sk = __shfl(Sk, sl);
+  // the wave is whole here (the early return above is per wave)
+  V = wave_sum_dpp(V);
+  Tk = readlane_d(Tk, a.T % 64);
+  Sk = readlane_d(Sk, (a.T + 1) % 64);
   if (lane == 0) {
     a.H[idx] = Tk - V;
     a.Sm[idx] = Sk;

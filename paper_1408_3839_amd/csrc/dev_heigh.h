@@ -4,6 +4,7 @@
 #include <cfloat>
 
 #include "common.h"
+#include "dev_wave.h"
 
 namespace tl {
 namespace dev {
@@ -174,9 +175,7 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
       if (k > m - 3) break;  // uniform
       const cx xi = shfl_cx(c, 8 * i + k), xj = shfl_cx(c, 8 * j + k);
       const cx alpha = shfl_cx(c, 8 * (k + 1) + k);
-      double sq = (j == k && i >= k + 2) ? cabs2(c) : 0.0;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+      const double sq = wave_sum_dpp((j == k && i >= k + 2) ? cabs2(c) : 0.0);
       if (sq == 0.0 && alpha.im == 0.0) {
         e2[k] = alpha.re * alpha.re;  // already reduced: H = I
         continue;
@@ -190,19 +189,13 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
       const cx vj = j == k + 1 ? cx{1.0, 0.0} : (j > k + 1 ? cmul(xj, rden) : cx{0.0, 0.0});
       // w_i = tau sum_j C[i][j] v_j over the trailing block (row groups of 8 lanes)
       cx t = (i > k && j > k) ? cmul(c, vj) : cx{0.0, 0.0};
-#pragma unroll
-      for (int o = 4; o > 0; o >>= 1) {
-        t.re += __shfl_xor(t.re, o);
-        t.im += __shfl_xor(t.im, o);
-      }
+      t.re = group8_sum(t.re);
+      t.im = group8_sum(t.im);
       cx wi = cmul(tau, t);
       // K = -1/2 tau (w^H v): one lane per row contributes conj(w_i) v_i
       cx kk = (j == 0 && i > k) ? cmul(cconj(wi), vi) : cx{0.0, 0.0};
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        kk.re += __shfl_xor(kk.re, o);
-        kk.im += __shfl_xor(kk.im, o);
-      }
+      kk.re = wave_sum_dpp(kk.re);
+      kk.im = wave_sum_dpp(kk.im);
       const cx K = cscale(cmul(tau, kk), -0.5);
       wi = cadd(wi, cmul(K, vi));
       const cx wj = shfl_cx(wi, 8 * j);
@@ -259,11 +252,8 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
       // x0 < x1 and counts are monotone: the pair brackets idx locally
       double nlo = c1 <= idx ? x1 : (c0 <= idx ? x0 : lo);
       double nhi = c0 > idx ? x0 : (c1 > idx ? x1 : hi);
-#pragma unroll
-      for (int o = 4; o > 0; o >>= 1) {
-        nlo = fmax(nlo, __shfl_xor(nlo, o));
-        nhi = fmin(nhi, __shfl_xor(nhi, o));
-      }
+      nlo = group8_max(nlo);
+      nhi = group8_min(nhi);
       if (!done) {
         lo = nlo;
         hi = fmax(nhi, nlo);
@@ -286,11 +276,8 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
       all = cabs2(c);
       off = i != j ? all : 0.0;
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      off += __shfl_xor(off, o);
-      all += __shfl_xor(all, o);
-    }
+    off = wave_sum_dpp(off);
+    all = wave_sum_dpp(all);
     if (off <= 1e-32 * all) {
       converged = 1;
       break;
