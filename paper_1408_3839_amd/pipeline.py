@@ -224,3 +224,18 @@ class BoxPipeline:
         self.assemble(stream)
         if self.eig is not None:
             self.eig.run(self.H, self.S, stream)
+
+    def capture(self):
+        """Capture one whole run() (assembly and eigensolve) into a HIP graph."""
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            self.run()
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
