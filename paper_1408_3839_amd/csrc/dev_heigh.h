@@ -99,6 +99,39 @@ __device__ __forceinline__ Rot make_rot_fast(double a, double d, cx b, bool vali
   return r;
 }
 
+// Sturm counts at two points x0, x1 of the symmetric tridiagonal with
+// diagonal d[0..m-1] and squared off-diagonal e2[0..m-2], entries scaled into
+// (-1, 1): the number of eigenvalues below x is the number of sign changes in
+// the leading principal minors p_0 = 1, p_k = det(T_k - x I), which obey
+// p_k = (d_{k-1} - x) p_{k-1} - e2_{k-2} p_{k-2}.  Rounding in this recurrence
+// amounts to relative perturbations of d - x and e2 of a few ulps, as in the
+// ratio form q_k = p_k / p_{k-1}, but the dependent chain is one FMA per step.
+// An exact zero p_k takes the sign opposite to p_{k-1} (a tiny negative pivot
+// in the ratio form).
+__device__ __forceinline__ void sturm_count2(const double (&d)[8], const double (&e2)[8], int m,
+                                             double x0, double x1, int& c0, int& c1) {
+  constexpr double kTiny = 0x1p-500;
+  double p0 = d[0] - x0, p1 = d[0] - x1, r0 = 1.0, r1 = 1.0;
+  if (p0 == 0.0) p0 = -kTiny;
+  if (p1 == 0.0) p1 = -kTiny;
+  c0 = p0 < 0.0;
+  c1 = p1 < 0.0;
+#pragma unroll
+  for (int u = 1; u < 8; ++u) {
+    if (u >= m) break;
+    double n0 = fma(d[u] - x0, p0, -e2[u - 1] * r0);
+    double n1 = fma(d[u] - x1, p1, -e2[u - 1] * r1);
+    if (n0 == 0.0) n0 = -copysign(kTiny, p0);
+    if (n1 == 0.0) n1 = -copysign(kTiny, p1);
+    c0 += (n0 < 0.0) != (p0 < 0.0);
+    c1 += (n1 < 0.0) != (p1 < 0.0);
+    r0 = p0;
+    r1 = p1;
+    p0 = n0;
+    p1 = n1;
+  }
+}
+
 // ---------------------------------------------------------------- m0 <= 8
 // One wave per k-block, lane 8 i + j holding entry (i, j) of every 8 x 8
 // (padded) matrix in registers: S, its Cholesky factor L, X = L^-1, C, V.
@@ -107,10 +140,18 @@ __device__ __forceinline__ Rot make_rot_fast(double a, double d, cx b, bool vali
 // rotation formulas as the LDS version below.
 __device__ inline cx shfl_cx(cx v, int src) { return {__shfl(v.re, src), __shfl(v.im, src)}; }
 
+//
+// Eigenvalues only (evecs == nullptr): with wave < 0 the wave bisects all m
+// eigenvalues together (8 lanes and 16 points per eigenvalue and round); with
+// wave >= 0 it bisects eigenvalues wave, wave + nwave, ... one after the other
+// with all 64 lanes (128 points per round, about 7 bits), for launches that
+// give every block several waves.  The two schedules agree to the bisection
+// tolerance, not bit for bit.
 __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
                                         const double* __restrict__ S, int m,
                                         double* __restrict__ evals, double* __restrict__ evecs,
-                                        int* __restrict__ info, int64_t blk) {
+                                        int* __restrict__ info, int64_t blk, int wave = -1,
+                                        int nwave = 1) {
   const int lane = threadIdx.x & 63, i = lane >> 3, j = lane & 7;
   const bool in = i < m && j < m;
   const int mm = m * m;
@@ -136,6 +177,7 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
     if (j > i) s = {0.0, 0.0};
   }
   if (fail) {
+    if (wave > 0) return;
     if (j == 0 && i < m) evals[blk * m + i] = NAN;
     if (evecs && in) ((cx*)evecs)[blk * mm + i * m + j] = {0.0, 0.0};
     if (lane == 0) info[blk] = fail;
@@ -212,43 +254,65 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
       for (int q = 0; q < 8; ++q)
         if (q == m - 2) e2[q] = cabs2(last);
     }
-    // Gershgorin interval and pivot floor (dstebz conventions)
-    double lo = 1e308, hi = -1e308, emax = 0.0;
+    // Gershgorin interval, then an exact power-of-two scaling that puts the
+    // spectrum inside (-1, 1) (the leading minors below then stay far from
+    // overflow and underflow for m <= 8)
+    double lo = 1e308, hi = -1e308;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       if (q >= m) break;
       const double el = q > 0 ? sqrt(e2[q - 1]) : 0.0, er = q < m - 1 ? sqrt(e2[q]) : 0.0;
       lo = fmin(lo, d8[q] - el - er);
       hi = fmax(hi, d8[q] + el + er);
-      if (q < m - 1) emax = fmax(emax, e2[q]);
     }
-    const double pivmin = DBL_MIN * fmax(1.0, emax);
     const double tn = fmax(fabs(lo), fabs(hi));
-    const double fudge = 2.1 * DBL_EPSILON * tn * m + 4.2 * pivmin;
-    lo -= fudge;
-    hi += fudge;
-    // eigenvalue idx = lane / 8; each lane runs two interleaved Sturm
-    // sequences, so a round counts at sixteen interior points per eigenvalue
-    const int idx = lane >> 3, pt = lane & 7;
-    for (int round = 0; round < 40; ++round) {
-      const bool done = hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin;
-      if (__all(done || idx >= m)) break;
-      const double x0 = lo + (hi - lo) * ((double)(2 * pt + 1) / 17.0);
-      const double x1 = lo + (hi - lo) * ((double)(2 * pt + 2) / 17.0);
-      double q0 = d8[0] - x0, q1 = d8[0] - x1;
-      if (fabs(q0) < pivmin) q0 = -pivmin;
-      if (fabs(q1) < pivmin) q1 = -pivmin;
-      int c0 = q0 < 0.0, c1 = q1 < 0.0;
+    int ex = 0;
+    if (tn > 0.0 && isfinite(tn)) frexp(tn, &ex);
+    ex += 1;
 #pragma unroll
-      for (int u = 1; u < 8; ++u) {
-        if (u >= m) break;
-        q0 = (d8[u] - x0) - e2[u - 1] * nrcp(q0);
-        q1 = (d8[u] - x1) - e2[u - 1] * nrcp(q1);
-        if (fabs(q0) < pivmin) q0 = -pivmin;
-        if (fabs(q1) < pivmin) q1 = -pivmin;
-        c0 += q0 < 0.0;
-        c1 += q1 < 0.0;
+    for (int q = 0; q < 8; ++q) {
+      d8[q] = ldexp(d8[q], -ex);
+      e2[q] = ldexp(e2[q], -2 * ex);
+    }
+    const double fudge = 2.1 * DBL_EPSILON * m * ldexp(tn, -ex);
+    lo = ldexp(lo, -ex) - fudge;
+    hi = ldexp(hi, -ex) + fudge;
+    // stop at an interval of 2 ulp of the scaled norm (absolute) or of the
+    // eigenvalue (relative), whichever is larger
+    const double atol = 2.0 * DBL_EPSILON * ldexp(tn, -ex);
+    if (wave >= 0) {
+      // one eigenvalue at a time; lane l counts at the interior points
+      // 2l + 1 and 2l + 2 of 129 equal parts, and the new bracket is read
+      // from the lanes that hold its ends (the counts rise with x)
+      const double f0 = (double)(2 * lane + 1) / 129.0, f1 = (double)(2 * lane + 2) / 129.0;
+      for (int idx = wave; idx < m; idx += nwave) {
+        double a = lo, b = hi;
+        for (int round = 0; round < 24; ++round) {
+          if (b - a <= fmax(atol, 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)))) break;  // uniform
+          const double x0 = a + (b - a) * f0, x1 = a + (b - a) * f1;
+          int c0, c1;
+          sturm_count2(d8, e2, m, x0, x1, c0, c1);
+          const int K = __popcll(__ballot(c0 <= idx)) + __popcll(__ballot(c1 <= idx));
+          const double na = K > 0 ? readlane_d(((K - 1) & 1) ? x1 : x0, (K - 1) >> 1) : a;
+          const double nb = K < 128 ? readlane_d((K & 1) ? x1 : x0, K >> 1) : b;
+          a = na;
+          b = fmax(nb, na);
+        }
+        if (lane == 0) evals[blk * m + idx] = ldexp(0.5 * (a + b), ex);
       }
+      if (wave == 0 && lane == 0) info[blk] = 0;
+      return;
+    }
+    // eigenvalue idx = lane / 8; each lane counts at two points, so a round
+    // splits the bracket at sixteen interior points per eigenvalue
+    const int idx = lane >> 3, pt = lane & 7;
+    const double f0 = (double)(2 * pt + 1) / 17.0, f1 = (double)(2 * pt + 2) / 17.0;
+    for (int round = 0; round < 40; ++round) {
+      const bool done = hi - lo <= fmax(atol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)));
+      if (__all(done || idx >= m)) break;
+      const double x0 = lo + (hi - lo) * f0, x1 = lo + (hi - lo) * f1;
+      int c0, c1;
+      sturm_count2(d8, e2, m, x0, x1, c0, c1);
       // x0 < x1 and counts are monotone: the pair brackets idx locally
       double nlo = c1 <= idx ? x1 : (c0 <= idx ? x0 : lo);
       double nhi = c0 > idx ? x0 : (c1 > idx ? x1 : hi);
@@ -259,7 +323,7 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
         hi = fmax(nhi, nlo);
       }
     }
-    if (pt == 0 && idx < m) evals[blk * m + idx] = 0.5 * (lo + hi);
+    if (pt == 0 && idx < m) evals[blk * m + idx] = ldexp(0.5 * (lo + hi), ex);
     if (lane == 0) info[blk] = 0;
     return;
   }

@@ -2,13 +2,12 @@
 // of the Fourier-space problem (Sec. 4.2, eq. (HF-FSpace-Block); Proposition
 // on block-circulant diagonalisation, eq. (lambdAbc)).
 //
-// One workgroup per block, one thread per matrix entry, everything in LDS:
-//   1. Cholesky Sbar = L L^H (lower),
-//   2. C = L^-1 Hbar L^-H by two forward substitutions, Hermitian average,
-//   3. complex Jacobi iteration with the parallel round-robin ordering
-//      (m/2 disjoint rotations per round, every thread updates its own
-//      entry from the four entries of its 2x2 coupling),
-//   4. eigenvalues sorted ascending; eigenvectors u = L^-H v.
+// Per block: Cholesky Sbar = L L^H, C = L^-1 Hbar L^-H (Hermitian average),
+// then either eigenvalues only (m <= 8: Householder reduction of C to a real
+// tridiagonal and Sturm bisection) or complex Jacobi with the parallel
+// round-robin ordering and eigenvectors u = L^-H v.  m <= 8 runs in one wave
+// with the matrices in registers; larger m uses one workgroup per block and
+// LDS.  Eigenvalues ascending.
 #include <cmath>
 
 #include "common.h"
@@ -26,12 +25,27 @@ __global__ __launch_bounds__(1024) void heigh_kernel(const double* __restrict__ 
   dev::heigh_body<MAXM>(H, S, m, evals, evecs, info, blockIdx.x);
 }
 
+// Eigenvalues only, m <= 8: m one-wave workgroups per block, each repeating
+// the reduction to tridiagonal form and bisecting one eigenvalue with the
+// whole wave, which shortens the dependent chain of the bisection.
+__global__ __launch_bounds__(64) void heigh_evals_kernel(const double* __restrict__ H,
+                                                         const double* __restrict__ S, int m,
+                                                         double* __restrict__ evals,
+                                                         int* __restrict__ info) {
+  const int64_t blk = blockIdx.x / m;
+  const int w = (int)(blockIdx.x - blk * m);
+  dev::heigh_wave8_body(H, S, m, evals, nullptr, info, blk, w, m);
+}
+
 }  // namespace
 
 tl_status batched_heigh(const double* H, const double* S, int count, int m, double* evals,
                         double* evecs, int* info, hipStream_t stream) {
   int threads = (int)std::max<int64_t>(64, ceil_div((int64_t)m * m, 64) * 64);
-  if (m <= 8) {
+  if (m <= 8 && evecs == nullptr && (int64_t)count * m <= INT32_MAX) {
+    hipLaunchKernelGGL(heigh_evals_kernel, dim3((unsigned)(count * m)), dim3(64), 0, stream, H, S,
+                       m, evals, info);
+  } else if (m <= 8) {
     hipLaunchKernelGGL(heigh_kernel<8>, dim3(count), dim3(threads), 0, stream, H, S, m, evals,
                        evecs, info);
   } else if (m <= 16) {

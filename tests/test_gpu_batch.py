@@ -11,6 +11,17 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+def _same_evals(a, b):
+    """Batch and single launches bisect with different point schedules: the
+    eigenvalues agree to the bisection tolerance (a few ulps of the spectrum's
+    scale), not bit for bit."""
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    ok = ~np.isnan(a)
+    scale = np.max(np.abs(a[ok]), initial=1.0)
+    return bool(np.all(np.abs(a[ok] - b[ok]) <= 64 * 2.0 ** -52 * max(1.0, scale)))
+
+
 def _ragged():
     out = []
     specs = [(6, 3, 8), (9, 5, 7), (4, 1, 6), (13, 8, 10), (7, 13, 9), (16, 4, 12)]
@@ -33,7 +44,7 @@ def test_batch_equals_single(precision, slices):
         torch.cuda.synchronize()
         assert torch.equal(v["H"], sp.H), s.name
         assert torch.equal(v["S"], sp.S), s.name
-        assert torch.equal(v["evals"], sp.evals), s.name
+        assert _same_evals(v["evals"], sp.evals), s.name
         assert torch.equal(v["info"], sp.info), s.name
 
 
@@ -94,7 +105,7 @@ def test_ragged_64_chain_batch():
         sp = PeriodicPipeline(s)
         sp.run()
         torch.cuda.synchronize()
-        assert torch.equal(v["H"], sp.H) and torch.equal(v["evals"], sp.evals), s.name
+        assert torch.equal(v["H"], sp.H) and _same_evals(v["evals"], sp.evals), s.name
     for i in order[:2]:
         s, v = systems[i], bp.views[i]
         Hr, Sr, scale = oracle.core_hamiltonian_blocks(s)
