@@ -153,9 +153,11 @@ tl_status tl_build_basis(const tl_system* sys, double* G_dev, double* AG_dev, do
  *   exp-sum image of the cell-averaged kernel; w_q and Z_nu sit in dim 0.
  *   Periodic dims: image sum k = -K..K of cell integrals
  *   int_cell exp(-t_q^2 (y - o - k a)^2) dy evaluated on the central cell and
- *   replicated with period a ("master" vectors on the accompanying grid,
- *   shifted and windowed); box dims: one factor per nucleus.
- * P_dev holds pot_elems doubles; ws_dev holds tl_potential_workspace_bytes.
+ *   replicated with period a (entries of the "master" vector on the
+ *   accompanying grid, formed where they are summed); box dims: one factor
+ *   per nucleus.
+ * P_dev holds pot_elems doubles.  tl_potential_workspace_bytes reports 0
+ * (no scratch memory is used); ws_dev may then be NULL.
  */
 tl_status tl_lattice_sum_potential(const tl_system* sys, double* P_dev, void* ws_dev,
                                    size_t ws_bytes, void* stream);

@@ -18,8 +18,7 @@ namespace {
 
 enum Stage {
   kBasis = 0,
-  kDirect,
-  kFold,
+  kPotential,
   kSlice,
   kContract,
   kReduce,
@@ -75,16 +74,9 @@ __global__ __launch_bounds__(256) void batch_basis_kernel(const BatchDesc* __res
   dev::basis_body(J.basis, J.G, J.AG, J.SG, lb);
 }
 
-__global__ __launch_bounds__(256) void batch_direct_kernel(const BatchDesc* __restrict__ d) {
-  TL_BATCH_LOCATE(kDirect)
-  dev::direct_body(J.pot.direct, J.pot.quad, J.pot.master, J.pot.P, (int)lb);
-}
-
-__global__ __launch_bounds__(256) void batch_fold_kernel(const BatchDesc* __restrict__ d) {
-  extern __shared__ double sh[];
-  TL_BATCH_LOCATE(kFold)
-  dev::fold_body(J.pot.fold, J.pot.quad, J.pot.master, J.pot.P, (int)(lb % J.T), (int)(lb / J.T),
-                 sh);
+__global__ __launch_bounds__(256) void batch_potential_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kPotential)
+  dev::potential_body(J.pot.direct, J.pot.fold, J.pot.quad, J.T, J.pot.fold_blocks, J.pot.P, lb);
 }
 
 template <typename LowT>
@@ -231,7 +223,6 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
   d->count = count;
   int64_t ob = 0, op = 0, ohs = 0, oev = 0, okb = 0;
   size_t ows = 0;
-  size_t fold_shmem = 0;
   for (int i = 0; i < count; ++i) {
     const tl_system* s = &systems[i];
     InstanceSizes is;
@@ -266,8 +257,7 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
     // stage block counts of this instance
     int64_t blocks[kStages];
     blocks[kBasis] = ceil_div(g.basis_elems, 256);
-    blocks[kDirect] = J.pot.direct_blocks;
-    blocks[kFold] = (int64_t)J.T * J.pot.fold_slots;
+    blocks[kPotential] = (int64_t)J.pot.fold_blocks + J.pot.direct_blocks;
     blocks[kSlice] = J.asmb.slice_blocks;
     blocks[kContract] = J.asmb.contract_blocks;
     blocks[kReduce] = ceil_div(J.asmb.reduce_total, 256);
@@ -275,7 +265,6 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
     blocks[kDft] = 2LL * g.L[0] * J.dft_rchunks;
     blocks[kHeigh] = g.L[0];
     for (int st = 0; st < kStages; ++st) d->prefix[st][i + 1] = d->prefix[st][i] + blocks[st];
-    fold_shmem = std::max(fold_shmem, J.pot.fold_shmem);
     ob += g.basis_elems;
     op += g.pot_elems;
     ohs += 2 * g.block_elems;
@@ -313,20 +302,14 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
   const BatchDesc* d = (const BatchDesc*)desc_dev;
   TL_REQUIRE(hd->count == plan->count, "descriptor does not match the plan");
   auto blocks = [&](int st) { return (unsigned)hd->prefix[st][hd->count]; };
-  size_t fold_shmem = 0;
-  for (int i = 0; i < hd->count; ++i) fold_shmem = std::max(fold_shmem, hd->job[i].pot.fold_shmem);
   const tl_precision prec = (tl_precision)plan->precision;
   hipEvent_t ev0, ev1;
   contraction_events(&ev0, &ev1);
 
   hipLaunchKernelGGL(batch_basis_kernel, dim3(blocks(kBasis)), dim3(256), 0, stream, d);
   TL_CHECK_LAUNCH();
-  if (blocks(kDirect)) {
-    hipLaunchKernelGGL(batch_direct_kernel, dim3(blocks(kDirect)), dim3(256), 0, stream, d);
-    TL_CHECK_LAUNCH();
-  }
-  if (blocks(kFold)) {
-    hipLaunchKernelGGL(batch_fold_kernel, dim3(blocks(kFold)), dim3(256), fold_shmem, stream, d);
+  if (blocks(kPotential)) {
+    hipLaunchKernelGGL(batch_potential_kernel, dim3(blocks(kPotential)), dim3(256), 0, stream, d);
     TL_CHECK_LAUNCH();
   }
   if (prec == TL_SPLIT_BF16) {

@@ -2,6 +2,7 @@
 // vectors), shared by the single-system and the batched launches.
 #pragma once
 #include "common.h"
+#include "dev_wave.h"
 
 namespace tl {
 namespace dev {
@@ -46,14 +47,11 @@ struct QuadArgs {  // the exponential-sum table, passed by value
   double w[TL_MAX_R];
 };
 
-// ---- a2 + open transverse dims in one launch.
-// Blocks [0, master_blocks): master vectors b~_q[j], j = -J..J.
-// Blocks after that: the y / z factors of open dims (one per group and
-// term), b_q(x_i; y_g), which need no lattice sum.
+// ---- open transverse dims: the y / z factors (one per group and term),
+// b_q(x_i; y_g), which need no lattice sum.
 struct DirectArgs {
-  int R, J, master_blocks;
+  int R;
   double h;
-  // open transverse dims (y = 1, z = 2)
   int n_open;                 // number of open transverse dims handled here (0..2)
   int open_dim[2];
   int n[2];
@@ -65,17 +63,7 @@ struct DirectArgs {
 };
 
 __device__ inline void direct_body(const DirectArgs& a, const QuadArgs& quad,
-                                   double* __restrict__ master, double* __restrict__ P, int b) {
-  if (b < a.master_blocks) {
-    int64_t idx = (int64_t)b * blockDim.x + threadIdx.x;
-    int64_t width = 2 * (int64_t)a.J + 1;
-    if (idx >= (int64_t)a.R * width) return;
-    int q = (int)(idx / width);
-    int j = (int)(idx - (int64_t)q * width) - a.J;
-    master[idx] = cell_int(quad.t[q], (double)j * a.h, a.h, 0.0);
-    return;
-  }
-  b -= a.master_blocks;
+                                   double* __restrict__ P, int b) {
   int od = 0;
   int span0 = a.T * a.blocks_per_term[0];
   if (a.n_open == 2 && b >= span0) {
@@ -99,55 +87,67 @@ struct FoldArgs {
   int group_off[3][TL_MAX_SITES];  // representative offset of each group per dim
   int dims[3];                     // periodic dims handled by this launch
   int c[3], K[3], n[3];
+  int chunks[3];                   // workgroups per term: ceil(c / kFoldNodes)
   int64_t out_off[3];
-  int R, J;
+  int n_slots, R;
+  double h;
 };
+constexpr int kFoldNodes = 4;  // window nodes per workgroup, one wave each
 
-// ---- a3 (torus dims): workgroup per (term, periodic dim).  Threads split the
-// image sum of every window node, partial sums meet in LDS, the window is
-// then replicated over the torus.
-__device__ inline void fold_body(const FoldArgs& p, const QuadArgs& quad,
-                                 const double* __restrict__ master, double* __restrict__ P,
-                                 int term, int slot, double* sh) {
-  // sh: win[c] then part[256] (dynamic LDS of the launch)
+// ---- a2 + a3 (torus dims).  Site and lattice offsets are whole numbers of
+// nodes, so every image factor is the cell integral b~_q[j] = b_q(j h; 0) of
+// the "master" vector at an integer node j.  With one site per group each
+// (window node, image) pair meets a different j, so the cell integrals are
+// formed right where they are summed instead of being stored and read back.
+// One wave per window node of the central cell: lanes take the images
+// k = -K + lane, -K + lane + 64, ..., the wave sums them, and the node's value
+// is replicated over the torus with the lattice period.
+__device__ inline void fold_body(const FoldArgs& p, const QuadArgs& quad, double* __restrict__ P,
+                                 int term, int slot, int chunk) {
   const int dim = p.dims[slot];
   const int c = p.c[slot], K = p.K[slot], n = p.n[slot];
-  double* win = sh;
-  double* part = sh + c;
+  const int lane = threadIdx.x & 63;
+  const int r = chunk * kFoldNodes + (int)(threadIdx.x >> 6);  // window node
+  if (r >= c) return;  // whole wave
   const int t = term;
   const int g = t / p.R;
   const int q = t - g * p.R;
-  const double* mq = master + (int64_t)q * (2 * p.J + 1) + p.J;  // mq[j], j in [-J, J]
-  const int half = c / 2;
-  const int tid = threadIdx.x;
-  auto image_sum = [&](int rr, int k_first, int k_step) {
-    double acc = 0.0;
-    for (int k = -K + k_first; k <= K; k += k_step) {
-      if (dim == 0) {
-        for (int s = 0; s < p.n_sites; ++s)
-          if (p.site_group[s] == g) acc += p.site_Z[s] * mq[rr - p.site_off[0][s] - k * c];
-      } else {
-        acc += mq[rr - p.group_off[dim][g] - k * c];
-      }
+  const double tq = quad.t[q], h = p.h;
+  const int rr = r - c / 2;  // offset of the node from the cell centre
+  double acc = 0.0;
+  for (int k = -K + lane; k <= K; k += 64) {
+    if (dim == 0) {
+      for (int s = 0; s < p.n_sites; ++s)
+        if (p.site_group[s] == g)
+          acc += p.site_Z[s] * cell_int(tq, (double)(rr - p.site_off[0][s] - k * c) * h, h, 0.0);
+    } else {
+      acc += cell_int(tq, (double)(rr - p.group_off[dim][g] - k * c) * h, h, 0.0);
     }
-    return acc;
-  };
-  const double wscale = dim == 0 ? quad.w[q] : 1.0;
-  if (c <= 256) {
-    const int np = 256 / c;
-    if (tid < np * c) part[tid] = image_sum(tid % c - half, tid / c, np);
-    __syncthreads();
-    if (tid < c) {
-      double v = 0.0;
-      for (int s2 = 0; s2 < np; ++s2) v += part[tid + s2 * c];
-      win[tid] = v * wscale;
-    }
-  } else {
-    for (int r = tid; r < c; r += blockDim.x) win[r] = image_sum(r - half, 0, 1) * wscale;
   }
-  __syncthreads();
+  const double v = wave_sum_dpp(acc) * (dim == 0 ? quad.w[q] : 1.0);
+  // node r of the window lands on every i = rr (mod c) of the torus
   double* out = P + p.out_off[slot] + (int64_t)t * n;
-  for (int i = tid; i < n; i += blockDim.x) out[i] = win[(i + half) % c];
+  for (int i = (rr % c + c) % c + lane * c; i < n; i += 64 * c) out[i] = v;
+}
+
+// The whole of a2/a3 for one system in one launch: blocks [0, fold_blocks)
+// run the torus dims (slot by slot, term-major within a slot), the rest the
+// open transverse dims.  The branch is uniform per workgroup.
+__device__ inline void potential_body(const DirectArgs& a, const FoldArgs& f,
+                                      const QuadArgs& quad, int T, int fold_blocks,
+                                      double* __restrict__ P, int64_t b) {
+  if (b < fold_blocks) {
+    int slot = 0;
+    int64_t span = (int64_t)T * f.chunks[0];
+    while (slot + 1 < f.n_slots && b >= span) {
+      b -= span;
+      ++slot;
+      span = (int64_t)T * f.chunks[slot];
+    }
+    fold_body(f, quad, P, (int)(b / f.chunks[slot]), slot, (int)(b % f.chunks[slot]));
+  } else {
+    direct_body(a, quad, P, (int)(b - fold_blocks));
+  }
 }
 
 constexpr int kNucChunk = 80;

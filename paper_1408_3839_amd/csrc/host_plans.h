@@ -40,8 +40,7 @@ struct PotentialPlan {
   int direct_blocks;
   dev::FoldArgs fold;
   int fold_slots;
-  size_t fold_shmem;
-  double* master;
+  int fold_blocks;  // torus-dim workgroups, ahead of the direct blocks in the launch
   double* P;
   int box_dim0;   // open dim 0: nuclei summed directly (single-system path only)
 };

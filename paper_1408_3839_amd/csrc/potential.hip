@@ -9,11 +9,12 @@
 // Torus dims (Sec. 4.1, eq. (EwaldSumP)): the lattice sum over images
 // k = -K..K is evaluated on the central cell only and replicated with the
 // lattice period.  Because site offsets and a are multiples of h, every image
-// factor is a shifted window of one "master" vector b~_q[j] = b_q(j h; 0) on
-// the accompanying grid (Sec. 3.2, master tensor and eq. (core_tens)), so the
-// master vectors are computed once (ALU-bound, erfc) and the windows are sums
-// of shifted reads (a few adds per node).
-// Open dims: one factor per nucleus, evaluated directly.
+// factor is an entry b~_q[j] = b_q(j h; 0) of one "master" vector on the
+// accompanying grid (Sec. 3.2, master tensor and eq. (core_tens)).  Each
+// entry enters one window node once (per site), so the entries are evaluated
+// (ALU-bound, erfc) inside the workgroup that sums them, not stored.
+// Open dims: one factor per nucleus, evaluated directly.  Torus and open
+// transverse dims share one launch.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -32,17 +33,10 @@ using dev::FoldArgs;
 using dev::QuadArgs;
 constexpr int kNucChunk = dev::kNucChunk;
 
-__global__ __launch_bounds__(256) void direct_kernel(DirectArgs a, QuadArgs quad,
-                                                     double* __restrict__ master,
-                                                     double* __restrict__ P) {
-  dev::direct_body(a, quad, master, P, blockIdx.x);
-}
-
-__global__ __launch_bounds__(256) void fold_kernel(FoldArgs p, QuadArgs quad,
-                                                   const double* __restrict__ master,
-                                                   double* __restrict__ P) {
-  extern __shared__ double sh[];
-  dev::fold_body(p, quad, master, P, blockIdx.x, blockIdx.y, sh);
+__global__ __launch_bounds__(256) void potential_kernel(DirectArgs a, FoldArgs f, QuadArgs quad,
+                                                        int T, int fold_blocks,
+                                                        double* __restrict__ P) {
+  dev::potential_body(a, f, quad, T, fold_blocks, P, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void box_potential_kernel(BoxArgs p, QuadArgs quad,
@@ -75,25 +69,11 @@ GroupInfo make_groups(const tl_system* s) {
   return gi;
 }
 
-int master_half_width(const Geometry& g, const tl_system* s) {
-  int J = 0;
-  for (int d = 0; d < 3; ++d) {
-    if (!g.periodic[d]) continue;
-    int maxoff = 0;
-    for (int nu = 0; nu < s->n_nuc; ++nu)
-      maxoff = std::max(maxoff, (int)std::lround(std::fabs(s->nuc_pos[3 * nu + d]) / g.h));
-    J = std::max(J, g.K[d] * g.cell_nodes[d] + g.cell_nodes[d] / 2 + maxoff + 2);
-  }
-  return J;
-}
-
 }  // namespace
 
-size_t potential_workspace_bytes(const Geometry& g, const tl_system* s) {
-  int J = master_half_width(g, s);
-  if (J == 0) return 0;
-  return align_up(sizeof(double) * (size_t)g.R * (2 * (size_t)J + 1), 256);
-}
+// The lattice sums form their cell integrals in place, so no workspace is
+// needed; the query stays part of the interface.
+size_t potential_workspace_bytes(const Geometry&, const tl_system*) { return 0; }
 
 tl_status plan_potential(const Geometry& g, const tl_system* s, double* P, void* ws,
                          size_t ws_bytes, PotentialPlan* out) {
@@ -104,23 +84,19 @@ tl_status plan_potential(const Geometry& g, const tl_system* s, double* P, void*
   }
   PotentialPlan& pp = *out;
   std::memset(&pp, 0, sizeof(pp));
-  pp.master = (double*)ws;
   pp.P = P;
   for (int q = 0; q < g.R; ++q) {
     pp.quad.t[q] = s->t_q[q];
     pp.quad.w[q] = s->w_q[q];
   }
   GroupInfo gi = make_groups(s);
-  int J = master_half_width(g, s);
   const int T = (int)g.pot_terms;
-  // launch 1: master vectors + open transverse dims
+  // open transverse dims
   DirectArgs& da = pp.direct;
   da.R = g.R;
-  da.J = J;
   da.h = g.h;
   da.T = T;
-  da.master_blocks = J > 0 ? (int)ceil_div((int64_t)g.R * (2 * J + 1), 256) : 0;
-  int total_blocks = da.master_blocks;
+  int total_blocks = 0;
   for (int d = 1; d < 3; ++d) {
     if (g.periodic[d]) continue;
     int od = da.n_open++;
@@ -133,11 +109,11 @@ tl_status plan_potential(const Geometry& g, const tl_system* s, double* P, void*
     total_blocks += T * da.blocks_per_term[od];
   }
   pp.direct_blocks = total_blocks;
-  // launch 2: lattice sums of every torus dim
+  // lattice sums of every torus dim
   FoldArgs& fa = pp.fold;
   fa.n_sites = s->n_nuc;
   fa.R = g.R;
-  fa.J = J;
+  fa.h = g.h;
   for (int nu = 0; nu < s->n_nuc && nu < TL_MAX_SITES; ++nu) {
     fa.site_group[nu] = gi.of_nucleus[nu];
     fa.site_Z[nu] = s->nuc_Z[nu];
@@ -149,23 +125,21 @@ tl_status plan_potential(const Geometry& g, const tl_system* s, double* P, void*
     fa.group_off[2][gr] = (int)std::lround(gi.z[gr] / g.h);
   }
   int slots = 0;
-  int cmax = 0;
+  int fold_blocks = 0;
   for (int d = 0; d < 3; ++d) {
     if (!g.periodic[d]) continue;
     fa.dims[slots] = d;
     fa.c[slots] = g.cell_nodes[d];
     fa.K[slots] = g.K[d];
     fa.n[slots] = g.n[d];
+    fa.chunks[slots] = (int)ceil_div(g.cell_nodes[d], dev::kFoldNodes);
     fa.out_off[slots] = g.pot_off[d];
-    cmax = std::max(cmax, g.cell_nodes[d]);
+    fold_blocks += T * fa.chunks[slots];
     ++slots;
   }
+  fa.n_slots = slots;
   pp.fold_slots = slots;
-  pp.fold_shmem = sizeof(double) * ((size_t)cmax + 256);
-  if (slots > 0 && pp.fold_shmem > 64 * 1024) {
-    set_error("cell of %d nodes exceeds the LDS window", cmax);
-    return TL_EUNSUPPORTED;
-  }
+  pp.fold_blocks = fold_blocks;
   pp.box_dim0 = !g.periodic[0];
   return TL_OK;
 }
@@ -175,14 +149,10 @@ tl_status lattice_sum_potential(const Geometry& g, const tl_system* s, double* P
   PotentialPlan pp;
   TL_TRY(plan_potential(g, s, P, ws, ws_bytes, &pp));
   const int T = (int)g.pot_terms;
-  if (pp.direct_blocks > 0) {
-    hipLaunchKernelGGL(direct_kernel, dim3((unsigned)pp.direct_blocks), dim3(256), 0, stream,
-                       pp.direct, pp.quad, pp.master, P);
-    TL_CHECK_LAUNCH();
-  }
-  if (pp.fold_slots > 0) {
-    hipLaunchKernelGGL(fold_kernel, dim3((unsigned)T, (unsigned)pp.fold_slots), dim3(256),
-                       pp.fold_shmem, stream, pp.fold, pp.quad, pp.master, P);
+  const int blocks = pp.fold_blocks + pp.direct_blocks;
+  if (blocks > 0) {
+    hipLaunchKernelGGL(potential_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                       pp.direct, pp.fold, pp.quad, T, pp.fold_blocks, P);
     TL_CHECK_LAUNCH();
   }
   // open dim 0 (box mode): every nucleus summed directly, in chunks

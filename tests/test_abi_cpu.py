@@ -78,7 +78,7 @@ def test_invalid_systems_rejected():
 def test_null_outputs_and_small_workspaces_rejected():
     s = wl.config(1)
     _expect(tl.tl_build_basis, tl.TL_EINVAL, s, 0, 0, 0, 0)
-    _expect(tl.tl_lattice_sum_potential, tl.TL_EWORKSPACE, s, 16, 0, 0, 0)
+    _expect(tl.tl_lattice_sum_potential, tl.TL_EINVAL, s, 0, 0, 0, 0)
     _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EWORKSPACE, s, 8, 8, 8, 8,
             tl.TL_FP64, 0, 8, 8, 0, 0, 0)
     _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EINVAL, s, 8, 8, 8, 8, 7, 0, 8, 8,
@@ -93,7 +93,7 @@ def test_null_outputs_and_small_workspaces_rejected():
 def test_workspace_queries():
     for cid in (1, 2, 5):
         s = wl.config(cid)
-        assert tl.tl_potential_workspace_bytes(s) > 0
+        assert tl.tl_potential_workspace_bytes(s) == 0
         assert tl.tl_assemble_workspace_bytes(s) % 256 == 0
     assert tl.tl_block_fft_workspace_bytes(64, 1, 1, 8, 2) == 0
     assert tl.tl_block_fft_workspace_bytes(8, 8, 8, 10, 2) == 8 * 2 * 512 * 100 * 2
