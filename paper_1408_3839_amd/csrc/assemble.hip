@@ -34,6 +34,9 @@ using namespace dev;
 __global__ __launch_bounds__(256) void contract_f64_kernel(ContractArgs a) {
   contract_f64_body(a, blockIdx.x);
 }
+__global__ __launch_bounds__(256) void contract_f64_src_kernel(ContractArgs a) {
+  contract_f64_src_body(a, blockIdx.x);
+}
 __global__ __launch_bounds__(256) void contract_f32_kernel(ContractArgs a) {
   contract_f32_body(a, blockIdx.x);
 }
@@ -128,6 +131,68 @@ SplitPlan make_split_plan(const Geometry& g, const Plan& plan, int s, size_t bas
 
 bool is_split(tl_precision prec) { return prec == TL_SPLIT_BF16 || prec == TL_SPLIT_FP16; }
 
+// Dynamic LDS budget of the source-row FP64 kernel: three workgroups per CU.
+constexpr size_t kSrcLdsMax = 53 * 1024;
+
+// Largest node sub-chunk (256, 128 or 64, at most the chunk unless 64) whose
+// worst tile fits the budget, 0 if none does.  The X part of a tile depends
+// only on its rows and the Y part only on its columns, so the worst tile is
+// the worst row block plus the worst column block.
+// Bank multiplicity of one 32-lane B-operand read of the source-row kernel:
+// lanes (g, n), g = 0, 1 consecutive nodes, n = 16 consecutive shifts cn
+// nodes apart, with ypad pad doubles after every 32 window nodes; 64 banks
+// of 4 bytes, lanes at one address share it.
+int window_conflicts(int cn, int ypad) {
+  int worst = 1;
+  for (int h = 15; h < 15 + 32; ++h)
+    for (int k = 0; k < 64; k += 2) {
+      int addr[32], cnt[64] = {0}, na = 0;
+      for (int g = 0; g < 2; ++g)
+        for (int n = 0; n < 16; ++n) {
+          const int w = (h - n) * cn + k + g;
+          const int a2 = 2 * (w + ypad * (w >> 5));
+          bool dup = false;
+          for (int q = 0; q < na; ++q) dup = dup || addr[q] == a2;
+          if (dup) continue;
+          addr[na++] = a2;
+          ++cnt[a2 & 63];
+          ++cnt[(a2 + 1) & 63];
+        }
+      for (int b = 0; b < 64; ++b) worst = std::max(worst, cnt[b]);
+    }
+  return worst;
+}
+
+int choose_ypad(int cn) {
+  if (cn <= 0) return 1;
+  return window_conflicts(cn, 2) < window_conflicts(cn, 1) ? 2 : 1;
+}
+
+int choose_kc(const Plan& plan, const Geometry& g, int d, int ypad, size_t* bytes) {
+  const int M = plan.M[d], N = plan.N[d], S = g.shifts[d];
+  const int cn = g.periodic[d] ? g.cell_nodes[d] : 0;
+  const int T = (int)g.pot_terms;
+  for (int kc : {256, 128, 64}) {
+    if (kc > plan.kchunk[d] && kc > 64) continue;
+    int xmax = 0, ymax = 0;
+    dev::TileLayout L;
+    for (int row0 = 0; row0 < M; row0 += kBM) {
+      dev::tile_layout(M, N, S, cn, g.m0, T, row0, 0, kc, ypad, &L);
+      xmax = std::max(xmax, L.xtotal);
+    }
+    for (int col0 = 0; col0 < N; col0 += kBN) {
+      dev::tile_layout(M, N, S, cn, g.m0, T, 0, col0, kc, ypad, &L);
+      ymax = std::max(ymax, L.total - L.xtotal);
+    }
+    const size_t b = sizeof(double) * (size_t)(xmax + ymax);
+    if (b <= kSrcLdsMax) {
+      *bytes = b;
+      return kc;
+    }
+  }
+  return 0;
+}
+
 int default_slices(tl_precision prec) { return prec == TL_SPLIT_FP16 ? 5 : 6; }
 
 }  // namespace
@@ -182,7 +247,24 @@ tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, co
     p.ks = plan.ks[d];
     p.tiles_n = plan.tiles_n[d];
     p.block_begin = begin;
+    p.kc = 0;
+    p.ypad = 1;
     begin += plan.blocks[d];
+  }
+  // FP64: the source-row kernel when every dimension's tiles fit its budget
+  ap.src_lds = 0;
+  if (prec == TL_FP64) {
+    size_t need = 0;
+    bool ok = true;
+    for (int d = 0; d < 3 && ok; ++d) {
+      size_t b = 0;
+      a.d[d].ypad = choose_ypad(a.d[d].cn);
+      const int kc = choose_kc(plan, g, d, a.d[d].ypad, &b);
+      ok = kc > 0;
+      a.d[d].kc = kc;
+      need = std::max(need, b);
+    }
+    ap.src_lds = ok ? need : 0;
   }
   // split modes: slicing pass and sliced contraction
   if (is_split(prec)) {
@@ -301,6 +383,9 @@ tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream) {
   else if (ap.prec == TL_FP32)
     hipLaunchKernelGGL(contract_f32_kernel, dim3((unsigned)ap.contract_blocks), dim3(256), 0,
                        stream, ap.contract);
+  else if (ap.src_lds > 0)
+    hipLaunchKernelGGL(contract_f64_src_kernel, dim3((unsigned)ap.contract_blocks), dim3(256),
+                       ap.src_lds, stream, ap.contract);
   else
     hipLaunchKernelGGL(contract_f64_kernel, dim3((unsigned)ap.contract_blocks), dim3(256), 0,
                        stream, ap.contract);

@@ -24,7 +24,72 @@ struct DimArgs {
   const double* P;
   double* part;    // [ks][M][N] partial sums over node chunks
   int n, S, cn, M, N, kchunk, ks, tiles_n, block_begin;
+  int kc;          // nodes per LDS sub-chunk of the source-row kernel (64, 128 or 256)
+  int ypad;        // source-row kernel: pad doubles after every 32 window nodes (1 or 2)
 };
+
+// LDS layout (offsets in doubles) of the source-row FP64 kernel for one
+// 32 x 32 tile and a sub-chunk of kc nodes.  A zero row and a ones row come
+// first: lanes outside the matrix read zeros, and the kinetic and mass rows
+// (no potential factor) multiply by one, so the MFMA loop has no branch or
+// select.  X rows (term t, nu) are formed from the P row of t and the G, AG
+// or SG row of nu; Y columns (mu, shift) from one window of mu's G row that
+// covers all of the tile's shifts of mu.  Rows sit at the stride kc + 2
+// (2 mod 32), so the 32 lanes of an operand read (16 rows, 2 nodes) fall in
+// distinct banks; window node x sits at x + ypad (x / 32), with ypad chosen
+// per dimension so that windows read cn nodes apart do too.  Shared by the
+// host (sizing) and the kernel.
+struct TileLayout {
+  int t0, nP;               // P rows t0 .. t0+nP-1 (terms below T)
+  int offP, offG, offA, offS;  // row blocks; offG/A/S = -1 when the tile has no such row
+  int mu0, nmu;             // mu0 .. mu0+nmu-1
+  int ysh_hi[kBN];          // per local mu: largest shift of the tile
+  int yoff[kBN];            // per local mu: offset of its window
+  int ylen[kBN];            // per local mu: window length in nodes
+  int xtotal, total;        // doubles up to the end of the X sources, of everything
+};
+
+__host__ __device__ inline int src_zero_len(int kc) { return kc + (kc >> 4) + 4; }
+__host__ __device__ inline int src_ones_off(int kc) { return src_zero_len(kc); }
+
+__host__ __device__ inline void tile_layout(int M, int N, int S, int cn, int m0, int T, int row0,
+                                            int col0, int kc, int ypad, TileLayout* L) {
+  const int ld = kc + 2;
+  const int r1 = min(M, row0 + kBM) - 1;
+  const int t0 = row0 / m0, t1 = r1 / m0;
+  L->t0 = t0;
+  L->nP = t0 < T ? min(t1, T - 1) - t0 + 1 : 0;
+  int off = src_ones_off(kc) + kc;
+  L->offP = off;
+  off += L->nP * ld;
+  L->offG = L->offA = L->offS = -1;
+  if (t0 < T) {
+    L->offG = off;
+    off += m0 * ld;
+  }
+  if (t0 <= T && T <= t1) {
+    L->offA = off;
+    off += m0 * ld;
+  }
+  if (t0 <= T + 1 && T + 1 <= t1) {
+    L->offS = off;
+    off += m0 * ld;
+  }
+  L->xtotal = off;
+  const int c1 = min(N, col0 + kBN) - 1;
+  L->mu0 = col0 / S;
+  L->nmu = c1 / S - L->mu0 + 1;
+  for (int u = 0; u < L->nmu; ++u) {
+    const int mu = L->mu0 + u;
+    const int sh_lo = max(0, col0 - mu * S), sh_hi = min(S - 1, c1 - mu * S);
+    const int len = kc + (sh_hi - sh_lo) * cn;
+    L->ysh_hi[u] = sh_hi;
+    L->yoff[u] = off;
+    L->ylen[u] = len;
+    off += len + ypad * (len >> 5) + ypad;
+  }
+  L->total = off;
+}
 
 struct ContractArgs {
   DimArgs d[3];
@@ -123,6 +188,111 @@ __device__ inline void contract_f64_body(const ContractArgs& a, int b) {
   for (int r = 0; r < 4; ++r) {
     int row = row0 + wm * 16 + (lane >> 4) + 4 * r;
     if (row < p.M && col < p.N) p.part[((int64_t)z * p.M + row) * p.N + col] = acc[r];
+  }
+}
+
+// Source-row variant of the FP64 contraction, same tile, chunking, MFMA
+// sequence and output as contract_f64_body: per sub-chunk of kc nodes the
+// workgroup stages only the distinct source rows of its tile (TileLayout)
+// in one burst of coalesced loads, then forms X = p_t g_nu and the shifted
+// Y from LDS inside the MFMA loop.  The products and the order of the MFMA
+// accumulation are those of contract_f64_body, so the partial sums agree
+// bit for bit.
+__device__ inline void contract_f64_src_body(const ContractArgs& a, int b) {
+  extern __shared__ double sm[];
+  __shared__ TileLayout L;
+  const int dd = b >= a.d[2].block_begin ? 2 : (b >= a.d[1].block_begin ? 1 : 0);
+  const DimArgs& p = a.d[dd];
+  const int local = b - p.block_begin;
+  const int z = local % p.ks;
+  const int rest = local / p.ks;
+  const int col0 = (rest % p.tiles_n) * kBN;
+  const int row0 = (rest / p.tiles_n) * kBM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int kbeg = z * p.kchunk, kend = min(p.n, kbeg + p.kchunk);
+  const int kc = p.kc, ks2 = __ffs(kc) - 1, ld = kc + 2, ypad = p.ypad, ysh = ypad - 1;
+  if (tid == 0) tile_layout(p.M, p.N, p.S, p.cn, a.m0, a.T, row0, col0, kc, ypad, &L);
+  {  // the zero and ones rows
+    const int zl = src_zero_len(kc);
+    for (int e = tid; e < zl + kc; e += 256) sm[e] = e < zl ? 0.0 : 1.0;
+  }
+  __syncthreads();
+  // this lane's A row and B column as LDS offsets (the node is added);
+  // lanes outside the matrix read the zero row
+  const int row = row0 + wm * 16 + (lane & 15), col = col0 + wn * 16 + (lane & 15);
+  const bool yin = col < p.N;
+  int xp = 0, xb = 0, yo = 0, yw = 0;
+  if (row < p.M) {
+    const int t = row / a.m0, nu = row - t * a.m0;
+    xp = t < a.T ? L.offP + (t - L.t0) * ld : src_ones_off(kc);
+    xb = (t < a.T ? L.offG : (t == a.T ? L.offA : L.offS)) + nu * ld;
+  }
+  if (yin) {
+    const int mu = col / p.S, sh = col - mu * p.S, u = mu - L.mu0;
+    yo = L.yoff[u];
+    yw = (L.ysh_hi[u] - sh) * p.cn;
+  }
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kbeg; k0 < kend; k0 += kc) {
+    const int len = min(kc, kend - k0);
+    __syncthreads();  // the previous sub-chunk's reads are done
+    // every thread keeps one node of the sub-chunk and walks the rows
+    const int kn = tid & (kc - 1), r0 = tid >> ks2, rstep = 256 >> ks2;
+    const bool kin = kn < len;  // zero past the chunk end (zeroes X there)
+    {  // P rows of the tile's terms
+      const double* src = p.P + (int64_t)(L.t0 + r0) * p.n + k0 + kn;
+#pragma unroll 4
+      for (int r = r0; r < L.nP; r += rstep, src += (int64_t)rstep * p.n)
+        sm[L.offP + r * ld + kn] = kin ? *src : 0.0;
+    }
+    for (int q = 0; q < 3; ++q) {  // G / AG / SG rows
+      const int off = q == 0 ? L.offG : (q == 1 ? L.offA : L.offS);
+      if (off < 0) continue;
+      const double* src = (q == 0 ? p.G : (q == 1 ? p.AG : p.SG)) + (int64_t)r0 * p.n + k0 + kn;
+#pragma unroll 4
+      for (int r = r0; r < a.m0; r += rstep, src += (int64_t)rstep * p.n)
+        sm[off + r * ld + kn] = kin ? *src : 0.0;
+    }
+    for (int u = 0; u < L.nmu; ++u) {  // window x holds node (k0 - sh_hi cn + x) mod n
+      const double* g = p.G + (int64_t)(L.mu0 + u) * p.n;
+      const int base = k0 - L.ysh_hi[u] * p.cn;
+      double* dst = sm + L.yoff[u];
+      const int wl = L.ylen[u];
+#pragma unroll 4
+      for (int x = tid; x < wl; x += 256) {
+        int node = base + x;
+        while (node < 0) node += p.n;
+        while (node >= p.n) node -= p.n;
+        dst[x + ((x >> 5) << ysh)] = g[node];
+      }
+    }
+    __syncthreads();
+    const int kmax = (len + 3) & ~3;
+    int kk = 0;
+    for (; kk + 32 <= kmax; kk += 32) {  // eight MFMA steps, operands read first
+      double av[8], bv[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int k = kk + 4 * s + (lane >> 4), w = yw + k;
+        av[s] = sm[xp + k] * sm[xb + k];
+        bv[s] = sm[yo + w + ((w >> 5) << ysh)];
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+    }
+    for (; kk < kmax; kk += 4) {
+      const int k = kk + (lane >> 4), w = yw + k;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sm[xp + k] * sm[xb + k],
+                                                 sm[yo + w + ((w >> 5) << ysh)], acc, 0, 0, 0);
+    }
+  }
+  // f64 16x16x4 result layout on gfx950: register r of lane l holds
+  // D[l / 16 + 4 r][l % 16].
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int orow = row0 + wm * 16 + (lane >> 4) + 4 * r;
+    if (orow < p.M && yin) p.part[((int64_t)z * p.M + orow) * p.N + col] = acc[r];
   }
 }
 

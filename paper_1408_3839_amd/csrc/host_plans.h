@@ -24,6 +24,7 @@ struct AssemblyPlan {
   int64_t reduce_total;
   dev::CombineArgs combine;
   int64_t combine_total;
+  size_t src_lds;  // FP64: dynamic LDS of the source-row kernel (0: the staging kernel)
 };
 
 size_t assemble_workspace_bytes(const Geometry& g, tl_precision prec, int n_slices,
