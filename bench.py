@@ -340,7 +340,7 @@ def main():
                 "frac": achieved / peak,
                 "traffic": measured_traffic() if prec == "fp64" else None,
                 "kernel": ("contract_split_kernel" if prec.startswith("split") else
-                           f"contract_{'f32' if prec == 'fp32' else 'f64'}_kernel")
+                           "contract_f32_kernel" if prec == "fp32" else "contract_f64_src_kernel")
                 + " (1D contractions of the three dims, one launch)",
                 "algorithmic_flops_per_step": flops, "executed_flops_per_step": flops * mult,
                 "avg_kernel_ms": r["contraction_ms"]}

@@ -163,7 +163,7 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
   int fail = 0;
   if (Sb) {
     for (int k = 0; k < m; ++k) {
-      const double d = __shfl(s.re, 9 * k);
+      const double d = readlane_d(s.re, 9 * k);
       // pivots at or below 1e-300 (and non-finite ones) count as not positive
       if (!(d > 1e-300) || !isfinite(d)) {
         fail = k + 1;
@@ -188,7 +188,7 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
   cx c = h;
   if (Sb) {
     for (int r = 0; r < m; ++r) {
-      const double lrr = __shfl(s.re, 9 * r);
+      const double lrr = readlane_d(s.re, 9 * r);
       if (i == r) x = cscale(x, nrcp(lrr));
       const cx xrj = shfl_cx(x, 8 * r + j), lir = shfl_cx(s, 8 * i + r);
       if (i > r) x = csub(x, cmul(lir, xrj));
@@ -217,15 +217,20 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
       if (k > m - 3) break;  // uniform
       const cx xi = shfl_cx(c, 8 * i + k), xj = shfl_cx(c, 8 * j + k);
       const cx alpha = shfl_cx(c, 8 * (k + 1) + k);
-      const double sq = wave_sum_dpp((j == k && i >= k + 2) ? cabs2(c) : 0.0);
+      // |x'|^2 = sum over rows j >= k + 2 of |C[j][k]|^2: every group of 8
+      // lanes holds column k in xj, so a group sum gives it to all lanes
+      const double sq = group8_sum(j >= k + 2 ? cabs2(xj) : 0.0);
       if (sq == 0.0 && alpha.im == 0.0) {
         e2[k] = alpha.re * alpha.re;  // already reduced: H = I
         continue;
       }
-      const double beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + sq), alpha.re);
-      const cx tau = {(beta - alpha.re) / beta, -alpha.im / beta};
+      // |beta| and 1 / |beta| from one refined reciprocal square root
+      const double s2 = alpha.re * alpha.re + alpha.im * alpha.im + sq;
+      const double rs = nrsq(s2);
+      const double beta = -copysign(s2 * rs, alpha.re), rbeta = -copysign(rs, alpha.re);
+      const cx tau = {(beta - alpha.re) * rbeta, -alpha.im * rbeta};
       const cx den = {alpha.re - beta, alpha.im};
-      const double dd = 1.0 / cabs2(den);
+      const double dd = nrcp(cabs2(den));
       const cx rden = {den.re * dd, -den.im * dd};  // 1 / (alpha - beta)
       const cx vi = i == k + 1 ? cx{1.0, 0.0} : (i > k + 1 ? cmul(xi, rden) : cx{0.0, 0.0});
       const cx vj = j == k + 1 ? cx{1.0, 0.0} : (j > k + 1 ? cmul(xj, rden) : cx{0.0, 0.0});
@@ -234,20 +239,21 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
       t.re = group8_sum(t.re);
       t.im = group8_sum(t.im);
       cx wi = cmul(tau, t);
-      // K = -1/2 tau (w^H v): one lane per row contributes conj(w_i) v_i
-      cx kk = (j == 0 && i > k) ? cmul(cconj(wi), vi) : cx{0.0, 0.0};
-      kk.re = wave_sum_dpp(kk.re);
-      kk.im = wave_sum_dpp(kk.im);
+      cx wj = shfl_cx(wi, 8 * j);
+      // K = -1/2 tau (w^H v), summed over j within every group of 8 lanes
+      cx kk = j > k ? cmul(cconj(wj), vj) : cx{0.0, 0.0};
+      kk.re = group8_sum(kk.re);
+      kk.im = group8_sum(kk.im);
       const cx K = cscale(cmul(tau, kk), -0.5);
       wi = cadd(wi, cmul(K, vi));
-      const cx wj = shfl_cx(wi, 8 * j);
+      wj = cadd(wj, cmul(K, vj));
       if (i > k && j > k) c = csub(c, cadd(cmul(vi, cconj(wj)), cmul(wi, cconj(vj))));
       e2[k] = beta * beta;
     }
     // the last off-diagonal element needs no reflector
     double d8[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) d8[q] = __shfl(c.re, 9 * q);
+    for (int q = 0; q < 8; ++q) d8[q] = readlane_d(c.re, 9 * q);
     if (m >= 2) {
       const cx last = shfl_cx(c, 8 * (m - 1) + (m - 2));
 #pragma unroll
