@@ -160,9 +160,14 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
   const cx h = in ? Hb[i * m + j] : cx{0.0, 0.0};
   cx s = (in && Sb) ? Sb[i * m + j] : cx{i == j ? 1.0 : 0.0, 0.0};
   // 1. Cholesky S = L L^H, lane (i, j <= i) ends with L[i][j]
+  // (1 / L[k][k] and L[i][k] stay in registers for the forward elimination)
   int fail = 0;
+  double linv[8];
+  cx lcol[8];
   if (Sb) {
-    for (int k = 0; k < m; ++k) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k >= m) break;
       const double d = readlane_d(s.re, 9 * k);
       // pivots at or below 1e-300 (and non-finite ones) count as not positive
       if (!(d > 1e-300) || !isfinite(d)) {
@@ -173,6 +178,8 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
       if (j == k) s = i == k ? cx{lkk, 0.0} : (i > k ? cscale(s, inv) : s);
       const cx lik = shfl_cx(s, 8 * i + k), ljk = shfl_cx(s, 8 * j + k);
       if (j > k && i >= j) s = csub(s, cmul(lik, cconj(ljk)));
+      linv[k] = inv;
+      lcol[k] = lik;
     }
     if (j > i) s = {0.0, 0.0};
   }
@@ -187,11 +194,12 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
   cx x = {i == j ? 1.0 : 0.0, 0.0};
   cx c = h;
   if (Sb) {
-    for (int r = 0; r < m; ++r) {
-      const double lrr = readlane_d(s.re, 9 * r);
-      if (i == r) x = cscale(x, nrcp(lrr));
-      const cx xrj = shfl_cx(x, 8 * r + j), lir = shfl_cx(s, 8 * i + r);
-      if (i > r) x = csub(x, cmul(lir, xrj));
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (r >= m) break;
+      if (i == r) x = cscale(x, linv[r]);
+      const cx xrj = shfl_cx(x, 8 * r + j);
+      if (i > r) x = csub(x, cmul(lcol[r], xrj));
     }
     cx w = {0.0, 0.0};
 #pragma unroll
