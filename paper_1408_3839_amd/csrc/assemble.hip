@@ -343,6 +343,10 @@ tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, co
   c.T = (int)g.pot_terms;
   c.H = H;
   c.Sm = S;
+  if (g.block_elems > INT32_MAX) {
+    set_error("block column of %lld entries exceeds 2^31 - 1", (long long)g.block_elems);
+    return TL_EUNSUPPORTED;
+  }
   ap.combine_total = g.block_elems;
   return TL_OK;
 }

@@ -336,7 +336,8 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
   hipLaunchKernelGGL(batch_combine_kernel, dim3(blocks(kCombine)), dim3(256), 0, stream, d);
   TL_CHECK_LAUNCH();
   hipLaunchKernelGGL(batch_dft_kernel, dim3(blocks(kDft)), dim3(256),
-                     sizeof(double) * 2 * (size_t)plan->max_len, stream, d);
+                     sizeof(double) * std::max<size_t>(2 * (size_t)plan->max_len, 2 * 256),
+                     stream, d);
   TL_CHECK_LAUNCH();
   if (plan->max_m0 <= 8)
     hipLaunchKernelGGL(batch_heigh_kernel<8>, dim3(blocks(kHeigh)), dim3(64), 0, stream, d);

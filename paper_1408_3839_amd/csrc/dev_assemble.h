@@ -664,8 +664,18 @@ __device__ inline void reduce_partials_body(const ReduceArgs& a, int64_t total, 
   int d = idx >= a.begin[2] ? 2 : (idx >= a.begin[1] ? 1 : 0);
   int64_t e = idx - a.begin[d];
   const double* p = a.part[d] + e;
+  const int64_t st = a.MN[d];
+  const int ks = a.ks[d];
   double v = 0.0;
-  for (int s = 0; s < a.ks[d]; ++s) v += p[(int64_t)s * a.MN[d]];
+  int s = 0;
+  for (; s + 8 <= ks; s += 8) {  // eight loads in flight, summed in chunk order
+    double r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r[u] = p[(int64_t)(s + u) * st];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += r[u];
+  }
+  for (; s < ks; ++s) v += p[(int64_t)s * st];
   a.C[d][e] = v;
 }
 
@@ -693,16 +703,18 @@ __device__ inline double lookup(const CombineArgs& a, int d, int t, int mu, int 
 // (t < T), lane T the kinetic combination, lane T+1 the mass product; a
 // wave-wide sum then gives V (FP64 throughout).
 __device__ inline void combine_periodic_body(const CombineArgs& a, int64_t total, int64_t bx) {
-  const int64_t idx = bx * 4 + (threadIdx.x >> 6);
+  // (32-bit index arithmetic: the host keeps block columns below 2^31 entries)
+  const int idx = (int)(bx * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (idx >= total) return;
   const int m2 = a.m0 * a.m0;
-  const int64_t kflat = idx / m2;
-  const int e = (int)(idx - kflat * m2);
+  const int kflat = idx / m2;
+  const int e = idx - kflat * m2;
   const int mu = e / a.m0, nu = e - mu * a.m0;
-  const int k3 = (int)(kflat % a.L[2]);
-  const int k2 = (int)((kflat / a.L[2]) % a.L[1]);
-  const int k1 = (int)(kflat / ((int64_t)a.L[2] * a.L[1]));
+  const int k12 = kflat / a.L[2];
+  const int k3 = kflat - k12 * a.L[2];
+  const int k1 = k12 / a.L[1];
+  const int k2 = k12 - k1 * a.L[1];
   double V = 0.0, Tk = 0.0, Sk = 0.0;
   for (int t = lane; t < a.T + 2; t += 64) {
     if (t < a.T) {

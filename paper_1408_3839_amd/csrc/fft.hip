@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void dft_axis_kernel(DftArgs a) {
 tl_status launch_axis(const DftArgs& a, int64_t outer, hipStream_t stream) {
   dim3 grid((unsigned)(outer * a.len), (unsigned)ceil_div(a.inner, 256));
   const bool table = a.len <= kMaxTwiddle;
-  size_t shmem = table ? sizeof(double) * 2 * (size_t)a.len : 0;
+  size_t shmem = sizeof(double) * std::max<size_t>(table ? 2 * (size_t)a.len : 0, 2 * 256);
   if (a.real_in && table)
     hipLaunchKernelGGL((dft_axis_kernel<true, true>), grid, dim3(256), shmem, stream, a);
   else if (a.real_in)
