@@ -90,6 +90,12 @@ __global__ __launch_bounds__(256) void batch_contract_f64_kernel(const BatchDesc
   dev::contract_f64_body(J.asmb.contract, (int)lb);
 }
 
+__global__ __launch_bounds__(256) void batch_contract_f64_src_kernel(
+    const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kContract)
+  dev::contract_f64_src_body(J.asmb.contract, (int)lb);
+}
+
 __global__ __launch_bounds__(256) void batch_contract_f32_kernel(const BatchDesc* __restrict__ d) {
   TL_BATCH_LOCATE(kContract)
   dev::contract_f32_body(J.asmb.contract, (int)lb);
@@ -327,8 +333,21 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
     launch_batch_split<_Float16>(plan->n_slices, blocks(kContract), d, stream);
   else if (prec == TL_FP32)
     hipLaunchKernelGGL(batch_contract_f32_kernel, dim3(blocks(kContract)), dim3(256), 0, stream, d);
-  else
-    hipLaunchKernelGGL(batch_contract_f64_kernel, dim3(blocks(kContract)), dim3(256), 0, stream, d);
+  else {
+    // the source-row kernel when every instance's tiles fit its LDS budget
+    size_t src_lds = 0;
+    bool all_src = true;
+    for (int i = 0; i < hd->count; ++i) {
+      all_src = all_src && hd->job[i].asmb.src_lds > 0;
+      src_lds = std::max(src_lds, hd->job[i].asmb.src_lds);
+    }
+    if (all_src)
+      hipLaunchKernelGGL(batch_contract_f64_src_kernel, dim3(blocks(kContract)), dim3(256),
+                         src_lds, stream, d);
+    else
+      hipLaunchKernelGGL(batch_contract_f64_kernel, dim3(blocks(kContract)), dim3(256), 0, stream,
+                         d);
+  }
   TL_CHECK_LAUNCH();
   if (ev1) TL_HIP(hipEventRecord(ev1, stream));
   hipLaunchKernelGGL(batch_reduce_kernel, dim3(blocks(kReduce)), dim3(256), 0, stream, d);
