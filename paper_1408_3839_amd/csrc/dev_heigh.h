@@ -132,6 +132,32 @@ __device__ __forceinline__ void sturm_count2(const double (&d)[8], const double 
   }
 }
 
+// The same counts without the zero fix-up on the dependent chain (one FMA per
+// step); `zero` reports whether some minor came out exactly zero, in which
+// case the counts may be wrong and the caller recounts with sturm_count2.
+__device__ __forceinline__ void sturm_count2_fast(const double (&d)[8], const double (&e2)[8], int m,
+                                                  double x0, double x1, int& c0, int& c1,
+                                                  bool& zero) {
+  double p0 = d[0] - x0, p1 = d[0] - x1, r0 = 1.0, r1 = 1.0;
+  bool z = p0 == 0.0 || p1 == 0.0;
+  c0 = signbit(p0);
+  c1 = signbit(p1);
+#pragma unroll
+  for (int u = 1; u < 8; ++u) {
+    if (u >= m) break;
+    const double n0 = fma(d[u] - x0, p0, -e2[u - 1] * r0);
+    const double n1 = fma(d[u] - x1, p1, -e2[u - 1] * r1);
+    z = z || n0 == 0.0 || n1 == 0.0;
+    c0 += signbit(n0) != signbit(p0);
+    c1 += signbit(n1) != signbit(p1);
+    r0 = p0;
+    r1 = p1;
+    p0 = n0;
+    p1 = n1;
+  }
+  zero = z;
+}
+
 // ---------------------------------------------------------------- m0 <= 8
 // One wave per k-block, lane 8 i + j holding entry (i, j) of every 8 x 8
 // (padded) matrix in registers: S, its Cholesky factor L, X = L^-1, C, V.
@@ -305,7 +331,9 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
           if (b - a <= fmax(atol, 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)))) break;  // uniform
           const double x0 = a + (b - a) * f0, x1 = a + (b - a) * f1;
           int c0, c1;
-          sturm_count2(d8, e2, m, x0, x1, c0, c1);
+          bool zero;
+          sturm_count2_fast(d8, e2, m, x0, x1, c0, c1, zero);
+          if (__any(zero)) sturm_count2(d8, e2, m, x0, x1, c0, c1);  // rare
           const int K = __popcll(__ballot(c0 <= idx)) + __popcll(__ballot(c1 <= idx));
           const double na = K > 0 ? readlane_d(((K - 1) & 1) ? x1 : x0, (K - 1) >> 1) : a;
           const double nb = K < 128 ? readlane_d((K & 1) ? x1 : x0, K >> 1) : b;
@@ -326,7 +354,9 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
       if (__all(done || idx >= m)) break;
       const double x0 = lo + (hi - lo) * f0, x1 = lo + (hi - lo) * f1;
       int c0, c1;
-      sturm_count2(d8, e2, m, x0, x1, c0, c1);
+      bool zero;
+      sturm_count2_fast(d8, e2, m, x0, x1, c0, c1, zero);
+      if (__any(zero)) sturm_count2(d8, e2, m, x0, x1, c0, c1);  // rare
       // x0 < x1 and counts are monotone: the pair brackets idx locally
       double nlo = c1 <= idx ? x1 : (c0 <= idx ? x0 : lo);
       double nhi = c0 > idx ? x0 : (c1 > idx ? x1 : hi);
