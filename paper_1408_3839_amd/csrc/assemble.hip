@@ -34,8 +34,9 @@ using namespace dev;
 __global__ __launch_bounds__(256) void contract_f64_kernel(ContractArgs a) {
   contract_f64_body(a, blockIdx.x);
 }
+template <int TILE>
 __global__ __launch_bounds__(256) void contract_f64_src_kernel(ContractArgs a) {
-  contract_f64_src_body(a, blockIdx.x);
+  contract_f64_src_body<TILE, TILE>(a, blockIdx.x);
 }
 __global__ __launch_bounds__(256) void contract_f32_kernel(ContractArgs a) {
   contract_f32_body(a, blockIdx.x);
@@ -131,8 +132,10 @@ SplitPlan make_split_plan(const Geometry& g, const Plan& plan, int s, size_t bas
 
 bool is_split(tl_precision prec) { return prec == TL_SPLIT_BF16 || prec == TL_SPLIT_FP16; }
 
-// Dynamic LDS budget of the source-row FP64 kernel: three workgroups per CU.
+// Dynamic LDS budget of the source-row FP64 kernel: three workgroups per CU
+// with 32 x 32 tiles, two with 64 x 64 tiles.
 constexpr size_t kSrcLdsMax = 53 * 1024;
+constexpr size_t kSrcLdsMax64 = 64 * 1024;
 
 // Largest node sub-chunk (256, 128 or 64, at most the chunk unless 64) whose
 // worst tile fits the budget, 0 if none does.  The X part of a tile depends
@@ -168,7 +171,7 @@ int choose_ypad(int cn) {
   return window_conflicts(cn, 2) < window_conflicts(cn, 1) ? 2 : 1;
 }
 
-int choose_kc(const Plan& plan, const Geometry& g, int d, int ypad, size_t* bytes) {
+int choose_kc(const Plan& plan, const Geometry& g, int d, int ypad, int tile, size_t* bytes) {
   const int M = plan.M[d], N = plan.N[d], S = g.shifts[d];
   const int cn = g.periodic[d] ? g.cell_nodes[d] : 0;
   const int T = (int)g.pot_terms;
@@ -176,16 +179,16 @@ int choose_kc(const Plan& plan, const Geometry& g, int d, int ypad, size_t* byte
     if (kc > plan.kchunk[d] && kc > 64) continue;
     int xmax = 0, ymax = 0;
     dev::TileLayout L;
-    for (int row0 = 0; row0 < M; row0 += kBM) {
-      dev::tile_layout(M, N, S, cn, g.m0, T, row0, 0, kc, ypad, &L);
+    for (int row0 = 0; row0 < M; row0 += tile) {
+      dev::tile_layout(M, N, S, cn, g.m0, T, row0, 0, tile, tile, kc, ypad, &L);
       xmax = std::max(xmax, L.xtotal);
     }
-    for (int col0 = 0; col0 < N; col0 += kBN) {
-      dev::tile_layout(M, N, S, cn, g.m0, T, 0, col0, kc, ypad, &L);
+    for (int col0 = 0; col0 < N; col0 += tile) {
+      dev::tile_layout(M, N, S, cn, g.m0, T, 0, col0, tile, tile, kc, ypad, &L);
       ymax = std::max(ymax, L.total - L.xtotal);
     }
     const size_t b = sizeof(double) * (size_t)(xmax + ymax);
-    if (b <= kSrcLdsMax) {
+    if (b <= (tile == 64 ? kSrcLdsMax64 : kSrcLdsMax)) {
       *bytes = b;
       return kc;
     }
@@ -207,7 +210,8 @@ size_t assemble_workspace_bytes(const Geometry& g, tl_precision prec, int n_slic
 
 tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, const double* SG,
                         const double* P, tl_precision prec, int n_slices, double* H, double* S,
-                        void* ws, size_t ws_bytes, int want_blocks, AssemblyPlan* out) {
+                        void* ws, size_t ws_bytes, int want_blocks, AssemblyPlan* out,
+                        int tile_hint) {
   Plan plan = make_plan(g, want_blocks);
   const int nsl = is_split(prec) ? (n_slices > 0 ? n_slices : default_slices(prec)) : 0;
   if (is_split(prec) && (nsl < 2 || nsl > kMaxSlices)) {
@@ -251,20 +255,41 @@ tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, co
     p.ypad = 1;
     begin += plan.blocks[d];
   }
-  // FP64: the source-row kernel when every dimension's tiles fit its budget
+  // FP64: the source-row kernel when every dimension's tiles fit its budget,
+  // with 64 x 64 tiles when asked for (same node chunks and partial sums;
+  // 4x fewer, larger workgroups) and they fit, else 32 x 32
   ap.src_lds = 0;
+  ap.src_tile = 0;
   if (prec == TL_FP64) {
-    size_t need = 0;
-    bool ok = true;
-    for (int d = 0; d < 3 && ok; ++d) {
-      size_t b = 0;
-      a.d[d].ypad = choose_ypad(a.d[d].cn);
-      const int kc = choose_kc(plan, g, d, a.d[d].ypad, &b);
-      ok = kc > 0;
-      a.d[d].kc = kc;
-      need = std::max(need, b);
+    for (int tile : {64, 32}) {
+      if (tile > tile_hint) continue;
+      size_t need = 0;
+      bool ok = true;
+      for (int d = 0; d < 3 && ok; ++d) {
+        size_t b = 0;
+        a.d[d].ypad = choose_ypad(a.d[d].cn);
+        const int kc = choose_kc(plan, g, d, a.d[d].ypad, tile, &b);
+        ok = kc > 0;
+        a.d[d].kc = kc;
+        need = std::max(need, b);
+      }
+      if (!ok) continue;
+      ap.src_lds = need;
+      ap.src_tile = tile;
+      if (tile != kBM) {  // the grid of the larger tiles
+        int nb = 0;
+        for (int d = 0; d < 3; ++d) {
+          DimArgs& p = a.d[d];
+          p.tiles_n = (int)ceil_div(p.N, tile);
+          p.block_begin = nb;
+          nb += (int)(ceil_div(p.M, tile) * p.tiles_n * p.ks);
+        }
+        ap.contract_blocks = nb;
+      }
+      break;
     }
-    ap.src_lds = ok ? need : 0;
+    if (ap.src_tile == 0)
+      for (int d = 0; d < 3; ++d) a.d[d].kc = 0;
   }
   // split modes: slicing pass and sliced contraction
   if (is_split(prec)) {
@@ -387,8 +412,11 @@ tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream) {
   else if (ap.prec == TL_FP32)
     hipLaunchKernelGGL(contract_f32_kernel, dim3((unsigned)ap.contract_blocks), dim3(256), 0,
                        stream, ap.contract);
-  else if (ap.src_lds > 0)
-    hipLaunchKernelGGL(contract_f64_src_kernel, dim3((unsigned)ap.contract_blocks), dim3(256),
+  else if (ap.src_tile == 64)
+    hipLaunchKernelGGL(contract_f64_src_kernel<64>, dim3((unsigned)ap.contract_blocks), dim3(256),
+                       ap.src_lds, stream, ap.contract);
+  else if (ap.src_tile == 32)
+    hipLaunchKernelGGL(contract_f64_src_kernel<32>, dim3((unsigned)ap.contract_blocks), dim3(256),
                        ap.src_lds, stream, ap.contract);
   else
     hipLaunchKernelGGL(contract_f64_kernel, dim3((unsigned)ap.contract_blocks), dim3(256), 0,

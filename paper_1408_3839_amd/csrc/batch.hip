@@ -93,7 +93,10 @@ __global__ __launch_bounds__(256) void batch_contract_f64_kernel(const BatchDesc
 __global__ __launch_bounds__(256) void batch_contract_f64_src_kernel(
     const BatchDesc* __restrict__ d) {
   TL_BATCH_LOCATE(kContract)
-  dev::contract_f64_src_body(J.asmb.contract, (int)lb);
+  if (J.asmb.src_tile == 64)  // uniform per workgroup
+    dev::contract_f64_src_body<64, 64>(J.asmb.contract, (int)lb);
+  else
+    dev::contract_f64_src_body<32, 32>(J.asmb.contract, (int)lb);
 }
 
 __global__ __launch_bounds__(256) void batch_contract_f32_kernel(const BatchDesc* __restrict__ d) {
@@ -246,7 +249,7 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
     double* H = buf->HS + ohs;
     double* S = H + g.block_elems;
     TL_TRY(plan_assembly(g, J.G, J.AG, J.SG, P, prec, plan->n_slices, H, S, ws + is.pot_ws,
-                         is.asm_ws, plan->want_blocks, &J.asmb));
+                         is.asm_ws, plan->want_blocks, &J.asmb, 64));
     // one lattice axis: transform H and S (outer = 2) along L
     double* Hbar = buf->HSbar + 2 * ohs;
     J.dft.in = H;
@@ -338,7 +341,7 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
     size_t src_lds = 0;
     bool all_src = true;
     for (int i = 0; i < hd->count; ++i) {
-      all_src = all_src && hd->job[i].asmb.src_lds > 0;
+      all_src = all_src && hd->job[i].asmb.src_tile > 0;
       src_lds = std::max(src_lds, hd->job[i].asmb.src_lds);
     }
     if (all_src)

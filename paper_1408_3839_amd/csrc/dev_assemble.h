@@ -39,13 +39,15 @@ struct DimArgs {
 // distinct banks; window node x sits at x + ypad (x / 32), with ypad chosen
 // per dimension so that windows read cn nodes apart do too.  Shared by the
 // host (sizing) and the kernel.
+constexpr int kMaxSrcTile = 64;  // largest tile edge of the source-row kernel
+
 struct TileLayout {
   int t0, nP;               // P rows t0 .. t0+nP-1 (terms below T)
   int offP, offG, offA, offS;  // row blocks; offG/A/S = -1 when the tile has no such row
   int mu0, nmu;             // mu0 .. mu0+nmu-1
-  int ysh_hi[kBN];          // per local mu: largest shift of the tile
-  int yoff[kBN];            // per local mu: offset of its window
-  int ylen[kBN];            // per local mu: window length in nodes
+  int ysh_hi[kMaxSrcTile];  // per local mu: largest shift of the tile
+  int yoff[kMaxSrcTile];    // per local mu: offset of its window
+  int ylen[kMaxSrcTile];    // per local mu: window length in nodes
   int xtotal, total;        // doubles up to the end of the X sources, of everything
 };
 
@@ -53,9 +55,10 @@ __host__ __device__ inline int src_zero_len(int kc) { return kc + (kc >> 4) + 4;
 __host__ __device__ inline int src_ones_off(int kc) { return src_zero_len(kc); }
 
 __host__ __device__ inline void tile_layout(int M, int N, int S, int cn, int m0, int T, int row0,
-                                            int col0, int kc, int ypad, TileLayout* L) {
+                                            int col0, int bm, int bn, int kc, int ypad,
+                                            TileLayout* L) {
   const int ld = kc + 2;
-  const int r1 = min(M, row0 + kBM) - 1;
+  const int r1 = min(M, row0 + bm) - 1;
   const int t0 = row0 / m0, t1 = r1 / m0;
   L->t0 = t0;
   L->nP = t0 < T ? min(t1, T - 1) - t0 + 1 : 0;
@@ -76,7 +79,7 @@ __host__ __device__ inline void tile_layout(int M, int N, int S, int cn, int m0,
     off += m0 * ld;
   }
   L->xtotal = off;
-  const int c1 = min(N, col0 + kBN) - 1;
+  const int c1 = min(N, col0 + bn) - 1;
   L->mu0 = col0 / S;
   L->nmu = c1 / S - L->mu0 + 1;
   for (int u = 0; u < L->nmu; ++u) {
@@ -191,14 +194,17 @@ __device__ inline void contract_f64_body(const ContractArgs& a, int b) {
   }
 }
 
-// Source-row variant of the FP64 contraction, same tile, chunking, MFMA
-// sequence and output as contract_f64_body: per sub-chunk of kc nodes the
-// workgroup stages only the distinct source rows of its tile (TileLayout)
-// in one burst of coalesced loads, then forms X = p_t g_nu and the shifted
-// Y from LDS inside the MFMA loop.  The products and the order of the MFMA
-// accumulation are those of contract_f64_body, so the partial sums agree
-// bit for bit.
+// Source-row variant of the FP64 contraction, same chunking, MFMA sequence
+// and output as contract_f64_body: per sub-chunk of kc nodes the workgroup
+// stages only the distinct source rows of its BM x BN tile (TileLayout) in
+// one burst of coalesced loads, then forms X = p_t g_nu and the shifted Y
+// from LDS inside the MFMA loop.  Each of the 4 waves owns a BM/2 x BN/2
+// quadrant of 16 x 16 MFMA blocks.  Every output block sees the products
+// and the order of accumulation of contract_f64_body, so the partial sums
+// agree bit for bit whatever the tile size.
+template <int BM, int BN>
 __device__ inline void contract_f64_src_body(const ContractArgs& a, int b) {
+  constexpr int RM = BM / 32, RN = BN / 32;  // 16 x 16 blocks per wave and direction
   extern __shared__ double sm[];
   __shared__ TileLayout L;
   const int dd = b >= a.d[2].block_begin ? 2 : (b >= a.d[1].block_begin ? 1 : 0);
@@ -206,34 +212,50 @@ __device__ inline void contract_f64_src_body(const ContractArgs& a, int b) {
   const int local = b - p.block_begin;
   const int z = local % p.ks;
   const int rest = local / p.ks;
-  const int col0 = (rest % p.tiles_n) * kBN;
-  const int row0 = (rest / p.tiles_n) * kBM;
+  const int col0 = (rest % p.tiles_n) * BN;
+  const int row0 = (rest / p.tiles_n) * BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int kbeg = z * p.kchunk, kend = min(p.n, kbeg + p.kchunk);
   const int kc = p.kc, ks2 = __ffs(kc) - 1, ld = kc + 2, ypad = p.ypad, ysh = ypad - 1;
-  if (tid == 0) tile_layout(p.M, p.N, p.S, p.cn, a.m0, a.T, row0, col0, kc, ypad, &L);
+  if (tid == 0) tile_layout(p.M, p.N, p.S, p.cn, a.m0, a.T, row0, col0, BM, BN, kc, ypad, &L);
   {  // the zero and ones rows
     const int zl = src_zero_len(kc);
     for (int e = tid; e < zl + kc; e += 256) sm[e] = e < zl ? 0.0 : 1.0;
   }
   __syncthreads();
-  // this lane's A row and B column as LDS offsets (the node is added);
+  // this lane's A rows and B columns as LDS offsets (the node is added);
   // lanes outside the matrix read the zero row
-  const int row = row0 + wm * 16 + (lane & 15), col = col0 + wn * 16 + (lane & 15);
-  const bool yin = col < p.N;
-  int xp = 0, xb = 0, yo = 0, yw = 0;
-  if (row < p.M) {
-    const int t = row / a.m0, nu = row - t * a.m0;
-    xp = t < a.T ? L.offP + (t - L.t0) * ld : src_ones_off(kc);
-    xb = (t < a.T ? L.offG : (t == a.T ? L.offA : L.offS)) + nu * ld;
+  int xp[RM], xb[RM], yo[RN], yw[RN];
+  bool yin[RN];
+#pragma unroll
+  for (int rb = 0; rb < RM; ++rb) {
+    const int row = row0 + wm * (BM / 2) + rb * 16 + (lane & 15);
+    xp[rb] = 0;
+    xb[rb] = 0;
+    if (row < p.M) {
+      const int t = row / a.m0, nu = row - t * a.m0;
+      xp[rb] = t < a.T ? L.offP + (t - L.t0) * ld : src_ones_off(kc);
+      xb[rb] = (t < a.T ? L.offG : (t == a.T ? L.offA : L.offS)) + nu * ld;
+    }
   }
-  if (yin) {
-    const int mu = col / p.S, sh = col - mu * p.S, u = mu - L.mu0;
-    yo = L.yoff[u];
-    yw = (L.ysh_hi[u] - sh) * p.cn;
+#pragma unroll
+  for (int cb = 0; cb < RN; ++cb) {
+    const int col = col0 + wn * (BN / 2) + cb * 16 + (lane & 15);
+    yin[cb] = col < p.N;
+    yo[cb] = 0;
+    yw[cb] = 0;
+    if (yin[cb]) {
+      const int mu = col / p.S, sh = col - mu * p.S, u = mu - L.mu0;
+      yo[cb] = L.yoff[u];
+      yw[cb] = (L.ysh_hi[u] - sh) * p.cn;
+    }
   }
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  f64x4 acc[RM][RN];
+#pragma unroll
+  for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < RN; ++cb) acc[rb][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = kbeg; k0 < kend; k0 += kc) {
     const int len = min(kc, kend - k0);
     __syncthreads();  // the previous sub-chunk's reads are done
@@ -269,31 +291,59 @@ __device__ inline void contract_f64_src_body(const ContractArgs& a, int b) {
     }
     __syncthreads();
     const int kmax = (len + 3) & ~3;
+    constexpr int US = 8 / (RM * RN) > 0 ? 8 / (RM * RN) : 1;  // k steps with operands read first
     int kk = 0;
-    for (; kk + 32 <= kmax; kk += 32) {  // eight MFMA steps, operands read first
-      double av[8], bv[8];
+    for (; kk + 4 * US <= kmax; kk += 4 * US) {
+      double av[US][RM], bv[US][RN];
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int k = kk + 4 * s + (lane >> 4), w = yw + k;
-        av[s] = sm[xp + k] * sm[xb + k];
-        bv[s] = sm[yo + w + ((w >> 5) << ysh)];
+      for (int s = 0; s < US; ++s) {
+        const int k = kk + 4 * s + (lane >> 4);
+#pragma unroll
+        for (int rb = 0; rb < RM; ++rb) av[s][rb] = sm[xp[rb] + k] * sm[xb[rb] + k];
+#pragma unroll
+        for (int cb = 0; cb < RN; ++cb) {
+          const int w = yw[cb] + k;
+          bv[s][cb] = sm[yo[cb] + w + ((w >> 5) << ysh)];
+        }
       }
 #pragma unroll
-      for (int s = 0; s < 8; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+      for (int s = 0; s < US; ++s)
+#pragma unroll
+        for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < RN; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][rb], bv[s][cb], acc[rb][cb], 0, 0, 0);
     }
     for (; kk < kmax; kk += 4) {
-      const int k = kk + (lane >> 4), w = yw + k;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sm[xp + k] * sm[xb + k],
-                                                 sm[yo + w + ((w >> 5) << ysh)], acc, 0, 0, 0);
+      const int k = kk + (lane >> 4);
+      double av[RM], bv[RN];
+#pragma unroll
+      for (int rb = 0; rb < RM; ++rb) av[rb] = sm[xp[rb] + k] * sm[xb[rb] + k];
+#pragma unroll
+      for (int cb = 0; cb < RN; ++cb) {
+        const int w = yw[cb] + k;
+        bv[cb] = sm[yo[cb] + w + ((w >> 5) << ysh)];
+      }
+#pragma unroll
+      for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < RN; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
     }
   }
   // f64 16x16x4 result layout on gfx950: register r of lane l holds
   // D[l / 16 + 4 r][l % 16].
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int orow = row0 + wm * 16 + (lane >> 4) + 4 * r;
-    if (orow < p.M && yin) p.part[((int64_t)z * p.M + orow) * p.N + col] = acc[r];
-  }
+  for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < RN; ++cb) {
+      const int col = col0 + wn * (BN / 2) + cb * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int orow = row0 + wm * (BM / 2) + rb * 16 + (lane >> 4) + 4 * r;
+        if (orow < p.M && yin[cb]) p.part[((int64_t)z * p.M + orow) * p.N + col] = acc[rb][cb][r];
+      }
+    }
 }
 
 // ---------------------------------------------------------------- FP32 mode

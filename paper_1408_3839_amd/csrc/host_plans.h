@@ -25,13 +25,17 @@ struct AssemblyPlan {
   dev::CombineArgs combine;
   int64_t combine_total;
   size_t src_lds;  // FP64: dynamic LDS of the source-row kernel (0: the staging kernel)
+  int src_tile;    // FP64: tile edge of the source-row kernel (32 or 64; 0: staging kernel)
 };
 
 size_t assemble_workspace_bytes(const Geometry& g, tl_precision prec, int n_slices,
                                 int want_blocks);
+// tile_hint: the largest tile edge of the FP64 source-row contraction that
+// may be used (32: latency-bound single systems; 64: large batches).
 tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, const double* SG,
                         const double* P, tl_precision prec, int n_slices, double* H, double* S,
-                        void* ws, size_t ws_bytes, int want_blocks, AssemblyPlan* out);
+                        void* ws, size_t ws_bytes, int want_blocks, AssemblyPlan* out,
+                        int tile_hint = 32);
 tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream);
 void contraction_events(hipEvent_t* start, hipEvent_t* stop);
 
