@@ -234,9 +234,11 @@ def box_chain_section(steps: int, warmup: int):
 
 def batch_section(steps: int, warmup: int):
     """64 ragged periodic (L,1,1) instances, whole chain, one launch per
-    stage, replayed as one HIP graph; FP64 and split-BF16 x6."""
+    stage, replayed as one HIP graph; FP64 and split-BF16 x6, each with the
+    contraction tiling target chosen by the autotuner (timed on the device
+    before the timed region)."""
     import torch
-    from paper_1408_3839_amd import tl, workloads
+    from paper_1408_3839_amd import autotune, tl, workloads
     from paper_1408_3839_amd.pipeline import BatchPipeline
 
     systems = workloads.batch(64)
@@ -245,7 +247,8 @@ def batch_section(steps: int, warmup: int):
     entries = sum(int(s.L[0]) * s.m0 * s.m0 for s in systems)
     flops = sum(contraction_flops(s, tl.tl_query_sizes(s)) for s in systems)
     for prec, nsl in (("fp64", 0), ("split_bf16", 6)):
-        bp = BatchPipeline(systems, precision=prec, n_slices=nsl)
+        want, tuning = autotune.tune_batch(systems, precision=prec, n_slices=nsl, cache_path=None)
+        bp = BatchPipeline(systems, precision=prec, n_slices=nsl, want_blocks=want)
         for _ in range(max(1, warmup)):
             bp.run()
         bp.capture()
@@ -271,6 +274,8 @@ def batch_section(steps: int, warmup: int):
             "k_blocks_per_s": sum(int(s.L[0]) for s in systems) / (ms * 1e-3),
             "contraction_ms": cms,
             "contraction_tflops": flops * mult / (cms * 1e-3) / 1e12,
+            "tuned_want_blocks": want,
+            "tuning_contraction_ms": {str(k): round(v, 4) for k, v in tuning.items()},
         }
         del bp
         torch.cuda.synchronize()

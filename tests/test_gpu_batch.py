@@ -110,3 +110,25 @@ def test_ragged_64_chain_batch():
         s, v = systems[i], bp.views[i]
         Hr, Sr, scale = oracle.core_hamiltonian_blocks(s)
         assert np.all(np.abs(v["H"].cpu().numpy() - Hr) <= 1e-10 * scale + 1e-290), s.name
+
+
+def test_autotune_picks_and_caches(tmp_path):
+    """The tiling autotuner times every candidate, keeps the fastest in its
+    cache, answers the next call from the cache, and the tuned batch still
+    matches the oracle."""
+    from paper_1408_3839_amd import autotune
+    from paper_1408_3839_amd.pipeline import BatchPipeline
+    systems = _ragged()
+    cache = str(tmp_path / "tuning.json")
+    cands = (128, 512, 2048)
+    best, times = autotune.tune_batch(systems, candidates=cands, reps=2, cache_path=cache)
+    assert set(times) == set(cands) and best == min(times, key=times.get)
+    assert all(t > 0 for t in times.values())
+    best2, times2 = autotune.tune_batch(systems, candidates=cands, reps=2, cache_path=cache)
+    assert best2 == best and times2 == times
+    bp = BatchPipeline(systems, want_blocks=best)
+    bp.run()
+    torch.cuda.synchronize()
+    s, v = systems[0], bp.views[0]
+    Hr, Sr, scale = oracle.core_hamiltonian_blocks(s)
+    assert np.all(np.abs(v["H"].cpu().numpy() - Hr) <= 1e-10 * scale + 1e-290)
