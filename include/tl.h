@@ -187,11 +187,11 @@ tl_status tl_assemble_core_hamiltonian_block(const tl_system* sys, const double*
 
 /*
  * tl_set_contraction_events - profiling hook: when both are non-NULL, the
- * assembly calls made afterwards by the calling thread record start_event
- * (a hipEvent_t) on their stream right before the 1D-contraction kernels
- * and stop_event right after them, so a caller can time that kernel
- * live with hipEventElapsedTime.  NULL, NULL switches the hook off.
- * The events stay owned by the caller.
+ * assembly and batch calls made afterwards by the calling thread attach
+ * start_event and stop_event (hipEvent_t, created with timing) to the launch
+ * of the 1D-contraction kernel itself (hipExtLaunchKernel), so
+ * hipEventElapsedTime gives that kernel's duration on its stream.  NULL,
+ * NULL switches the hook off.  The events stay owned by the caller.
  */
 tl_status tl_set_contraction_events(void* start_event, void* stop_event);
 

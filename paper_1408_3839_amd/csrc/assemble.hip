@@ -379,16 +379,17 @@ tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, co
 namespace {
 
 template <typename LowT>
-void launch_split_contraction(const AssemblyPlan& ap, hipStream_t stream) {
-  dim3 grid((unsigned)ap.contract_blocks), blk(256);
+void launch_split_contraction(const AssemblyPlan& ap, hipStream_t stream, hipEvent_t e0,
+                              hipEvent_t e1) {
+  const dim3 grid((unsigned)ap.contract_blocks), blk(256);
   switch (ap.n_slices) {
-    case 2: hipLaunchKernelGGL((contract_split_kernel<LowT, 2>), grid, blk, 0, stream, ap.split); break;
-    case 3: hipLaunchKernelGGL((contract_split_kernel<LowT, 3>), grid, blk, 0, stream, ap.split); break;
-    case 4: hipLaunchKernelGGL((contract_split_kernel<LowT, 4>), grid, blk, 0, stream, ap.split); break;
-    case 5: hipLaunchKernelGGL((contract_split_kernel<LowT, 5>), grid, blk, 0, stream, ap.split); break;
-    case 6: hipLaunchKernelGGL((contract_split_kernel<LowT, 6>), grid, blk, 0, stream, ap.split); break;
-    case 7: hipLaunchKernelGGL((contract_split_kernel<LowT, 7>), grid, blk, 0, stream, ap.split); break;
-    default: hipLaunchKernelGGL((contract_split_kernel<LowT, 8>), grid, blk, 0, stream, ap.split); break;
+    case 2: launch_with_events(contract_split_kernel<LowT, 2>, grid, blk, 0, stream, e0, e1, ap.split); break;
+    case 3: launch_with_events(contract_split_kernel<LowT, 3>, grid, blk, 0, stream, e0, e1, ap.split); break;
+    case 4: launch_with_events(contract_split_kernel<LowT, 4>, grid, blk, 0, stream, e0, e1, ap.split); break;
+    case 5: launch_with_events(contract_split_kernel<LowT, 5>, grid, blk, 0, stream, e0, e1, ap.split); break;
+    case 6: launch_with_events(contract_split_kernel<LowT, 6>, grid, blk, 0, stream, e0, e1, ap.split); break;
+    case 7: launch_with_events(contract_split_kernel<LowT, 7>, grid, blk, 0, stream, e0, e1, ap.split); break;
+    default: launch_with_events(contract_split_kernel<LowT, 8>, grid, blk, 0, stream, e0, e1, ap.split); break;
   }
 }
 
@@ -404,25 +405,25 @@ tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream) {
                        stream, ap.slice);
     TL_CHECK_LAUNCH();
   }
-  if (g_ev_start) TL_HIP(hipEventRecord(g_ev_start, stream));
+  // the profiling events (if set) are attached to the contraction launch
+  const hipEvent_t e0 = g_ev_start && g_ev_stop ? g_ev_start : nullptr;
+  const hipEvent_t e1 = e0 ? g_ev_stop : nullptr;
+  const dim3 cgrid((unsigned)ap.contract_blocks), cblk(256);
   if (ap.prec == TL_SPLIT_BF16)
-    launch_split_contraction<__bf16>(ap, stream);
+    launch_split_contraction<__bf16>(ap, stream, e0, e1);
   else if (ap.prec == TL_SPLIT_FP16)
-    launch_split_contraction<_Float16>(ap, stream);
+    launch_split_contraction<_Float16>(ap, stream, e0, e1);
   else if (ap.prec == TL_FP32)
-    hipLaunchKernelGGL(contract_f32_kernel, dim3((unsigned)ap.contract_blocks), dim3(256), 0,
-                       stream, ap.contract);
+    launch_with_events(contract_f32_kernel, cgrid, cblk, 0, stream, e0, e1, ap.contract);
   else if (ap.src_tile == 64)
-    hipLaunchKernelGGL(contract_f64_src_kernel<64>, dim3((unsigned)ap.contract_blocks), dim3(256),
-                       ap.src_lds, stream, ap.contract);
+    launch_with_events(contract_f64_src_kernel<64>, cgrid, cblk, ap.src_lds, stream, e0, e1,
+                       ap.contract);
   else if (ap.src_tile == 32)
-    hipLaunchKernelGGL(contract_f64_src_kernel<32>, dim3((unsigned)ap.contract_blocks), dim3(256),
-                       ap.src_lds, stream, ap.contract);
+    launch_with_events(contract_f64_src_kernel<32>, cgrid, cblk, ap.src_lds, stream, e0, e1,
+                       ap.contract);
   else
-    hipLaunchKernelGGL(contract_f64_kernel, dim3((unsigned)ap.contract_blocks), dim3(256), 0,
-                       stream, ap.contract);
+    launch_with_events(contract_f64_kernel, cgrid, cblk, 0, stream, e0, e1, ap.contract);
   TL_CHECK_LAUNCH();
-  if (g_ev_stop) TL_HIP(hipEventRecord(g_ev_stop, stream));
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)ceil_div(ap.reduce_total, 256)),
                      dim3(256), 0, stream, ap.reduce, ap.reduce_total);
   TL_CHECK_LAUNCH();

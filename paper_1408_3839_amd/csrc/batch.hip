@@ -288,15 +288,17 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
 namespace {
 
 template <typename LowT>
-void launch_batch_split(int S, unsigned grid, const BatchDesc* d, hipStream_t stream) {
+void launch_batch_split(int S, unsigned grid, const BatchDesc* d, hipStream_t stream, hipEvent_t e0,
+                        hipEvent_t e1) {
+  const dim3 g(grid), b(256);
   switch (S) {
-    case 2: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 2>), dim3(grid), dim3(256), 0, stream, d); break;
-    case 3: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 3>), dim3(grid), dim3(256), 0, stream, d); break;
-    case 4: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 4>), dim3(grid), dim3(256), 0, stream, d); break;
-    case 5: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 5>), dim3(grid), dim3(256), 0, stream, d); break;
-    case 6: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 6>), dim3(grid), dim3(256), 0, stream, d); break;
-    case 7: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 7>), dim3(grid), dim3(256), 0, stream, d); break;
-    default: hipLaunchKernelGGL((batch_contract_split_kernel<LowT, 8>), dim3(grid), dim3(256), 0, stream, d); break;
+    case 2: launch_with_events(batch_contract_split_kernel<LowT, 2>, g, b, 0, stream, e0, e1, d); break;
+    case 3: launch_with_events(batch_contract_split_kernel<LowT, 3>, g, b, 0, stream, e0, e1, d); break;
+    case 4: launch_with_events(batch_contract_split_kernel<LowT, 4>, g, b, 0, stream, e0, e1, d); break;
+    case 5: launch_with_events(batch_contract_split_kernel<LowT, 5>, g, b, 0, stream, e0, e1, d); break;
+    case 6: launch_with_events(batch_contract_split_kernel<LowT, 6>, g, b, 0, stream, e0, e1, d); break;
+    case 7: launch_with_events(batch_contract_split_kernel<LowT, 7>, g, b, 0, stream, e0, e1, d); break;
+    default: launch_with_events(batch_contract_split_kernel<LowT, 8>, g, b, 0, stream, e0, e1, d); break;
   }
 }
 
@@ -329,13 +331,15 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
                        d);
     TL_CHECK_LAUNCH();
   }
-  if (ev0) TL_HIP(hipEventRecord(ev0, stream));
+  // the profiling events (if set) are attached to the contraction launch
+  const hipEvent_t e0 = ev0 && ev1 ? ev0 : nullptr, e1 = e0 ? ev1 : nullptr;
+  const dim3 cgrid(blocks(kContract)), cblk(256);
   if (prec == TL_SPLIT_BF16)
-    launch_batch_split<__bf16>(plan->n_slices, blocks(kContract), d, stream);
+    launch_batch_split<__bf16>(plan->n_slices, blocks(kContract), d, stream, e0, e1);
   else if (prec == TL_SPLIT_FP16)
-    launch_batch_split<_Float16>(plan->n_slices, blocks(kContract), d, stream);
+    launch_batch_split<_Float16>(plan->n_slices, blocks(kContract), d, stream, e0, e1);
   else if (prec == TL_FP32)
-    hipLaunchKernelGGL(batch_contract_f32_kernel, dim3(blocks(kContract)), dim3(256), 0, stream, d);
+    launch_with_events(batch_contract_f32_kernel, cgrid, cblk, 0, stream, e0, e1, d);
   else {
     // the source-row kernel when every instance's tiles fit its LDS budget
     size_t src_lds = 0;
@@ -345,14 +349,11 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
       src_lds = std::max(src_lds, hd->job[i].asmb.src_lds);
     }
     if (all_src)
-      hipLaunchKernelGGL(batch_contract_f64_src_kernel, dim3(blocks(kContract)), dim3(256),
-                         src_lds, stream, d);
+      launch_with_events(batch_contract_f64_src_kernel, cgrid, cblk, src_lds, stream, e0, e1, d);
     else
-      hipLaunchKernelGGL(batch_contract_f64_kernel, dim3(blocks(kContract)), dim3(256), 0, stream,
-                         d);
+      launch_with_events(batch_contract_f64_kernel, cgrid, cblk, 0, stream, e0, e1, d);
   }
   TL_CHECK_LAUNCH();
-  if (ev1) TL_HIP(hipEventRecord(ev1, stream));
   hipLaunchKernelGGL(batch_reduce_kernel, dim3(blocks(kReduce)), dim3(256), 0, stream, d);
   TL_CHECK_LAUNCH();
   hipLaunchKernelGGL(batch_combine_kernel, dim3(blocks(kCombine)), dim3(256), 0, stream, d);

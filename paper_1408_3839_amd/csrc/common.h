@@ -1,6 +1,7 @@
 // Shared host/device helpers of the tl library (gfx950).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -83,5 +84,15 @@ struct Geometry {
 };
 
 tl_status digest(const tl_system* sys, Geometry* g);
+
+// Kernel launch with optional profiling events attached to the kernel itself
+// (hipExtLaunchKernel: the start / stop events time exactly this kernel on
+// its stream); null events give a plain launch.
+template <typename K, typename... A>
+inline void launch_with_events(K kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t stream,
+                               hipEvent_t start, hipEvent_t stop, A... args) {
+  hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)shmem, stream, start, stop, 0u,
+                        args...);
+}
 
 }  // namespace tl
