@@ -25,6 +25,8 @@
 #include <cfloat>
 #include <cmath>
 
+#include <utility>
+
 #include "common.h"
 #include "dev_wave.h"
 
@@ -311,28 +313,99 @@ __device__ int chol_inv_64(double (&ar)[16], double (&xr)[16], double pmin, Chol
   return fail;
 }
 
+constexpr int kLw = kNB + 2;
+struct __attribute__((aligned(16))) CholWaveLds {
+  double lt[kNB * kLw];  // L by columns: lt[c * kLw + r] = L[r][c], zero above the diagonal
+  double rd[kNB];        // 1 / L[i][i]
+};
+
+// Column C of the factorisation (a compile-time index, so that a[] stays in
+// registers: the whole 64-column nest is too large for the loop unroller).
+// No branch inside, so that the updates of a column are not deferred into
+// later columns.
+template <int C>
+__device__ __forceinline__ void chol_wave_col(double (&a)[kNB], int r, double pmin, int& fail,
+                                              double& rdr) {
+  double piv = dev::readlane_d(a[C], C);
+  const bool bad = !(piv > fmax(pmin, 1e-300));  // pivots at or below 1e-300 count as failed
+  fail = (bad && fail == 0) ? C + 1 : fail;
+  piv = bad ? 1.0 : piv;
+  const double rinv = nrsq(piv), lcc = piv * rinv;
+  a[C] = r > C ? a[C] * rinv : (r == C ? lcc : 0.0);
+  rdr = r == C ? rinv : rdr;
+#pragma unroll
+  for (int j = C + 1; j < kNB; ++j) a[j] = fma(-a[C], dev::readlane_d(a[C], j), a[j]);
+}
+
+template <int... C>
+__device__ __forceinline__ void chol_wave_cols(double (&a)[kNB], int r, double pmin, int& fail,
+                                               double& rdr, std::integer_sequence<int, C...>) {
+  (chol_wave_col<C>(a, r, pmin, fail, rdr), ...);
+}
+
+// Step K of X = L^-1 by columns (lane r holds column r of X): X[K][r] is
+// final once scaled, then goes into every later row with column K of L.
+template <int K>
+__device__ __forceinline__ void inv_wave_col(double (&x)[kNB], const CholWaveLds& sh) {
+  x[K] *= sh.rd[K];
+  const double xk = x[K];
+#pragma unroll
+  for (int i = (K + 1) & ~1; i < kNB; i += 2) {
+    const double2 l = *(const double2*)&sh.lt[K * kLw + i];
+    if (i >= K + 1) x[i] = fma(-l.x, xk, x[i]);
+    x[i + 1] = fma(-l.y, xk, x[i + 1]);
+  }
+}
+
+template <int... K>
+__device__ __forceinline__ void inv_wave_cols(double (&x)[kNB], const CholWaveLds& sh,
+                                              std::integer_sequence<int, K...>) {
+  (inv_wave_col<K>(x, sh), ...);
+}
+
+// The same factorisation and inverse in one wave, with no barrier: lane r
+// keeps row r of the block in a[] (entries c > r ignored), every pivot and
+// every column entry L[j][c] reaches the other lanes through readlane, and
+// the rank-1 updates are FMAs with a scalar operand.  L then goes to LDS by
+// columns and lane r solves column r of X = L^-1 in registers, reading the
+// columns of L as LDS broadcasts.  On return sh.lt holds L and x[i] =
+// X[i][r] (zero for i < r).  Pivot rule and return value as chol_inv_64.
+__device__ __forceinline__ int chol_inv_64_wave(double (&a)[kNB], double (&x)[kNB], double pmin,
+                                                CholWaveLds& sh) {
+  const int r = threadIdx.x & 63;
+  int fail = 0;
+  double rdr = 1.0;  // 1 / L[r][r] on lane r
+  chol_wave_cols(a, r, pmin, fail, rdr, std::make_integer_sequence<int, kNB>{});
+  sh.rd[r] = rdr;
+#pragma unroll
+  for (int c = 0; c < kNB; ++c) sh.lt[c * kLw + r] = c <= r ? a[c] : 0.0;
+  // one wave: its LDS accesses complete in program order, no barrier needed
+#pragma unroll
+  for (int i = 0; i < kNB; ++i) x[i] = i == r ? 1.0 : 0.0;
+  inv_wave_cols(x, sh, std::make_integer_sequence<int, kNB>{});
+  return fail;
+}
+
 // Factor the diagonal block at (p, p) in place (lower) and write its inverse
 // into the same block of Linv.  A non-positive pivot records the first
 // failing column (1-based) in *info and continues with pivot 1.
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ L,
-                                                         double* __restrict__ Linv, int64_t ld,
-                                                         int p, int* info) {
-  __shared__ CholLds sh;
-  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
-  double ar[16], xr[16];
+__global__ __launch_bounds__(64) void potrf_diag_kernel(double* __restrict__ L,
+                                                        double* __restrict__ Linv, int64_t ld,
+                                                        int p, int* info) {
+  __shared__ CholWaveLds sh;
+  const int r = threadIdx.x & 63;
+  double a[kNB], x[kNB];
+  const double* row = L + (int64_t)(p + r) * ld + p;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g + 4 * q;
-    ar[q] = c <= r ? L[(int64_t)(p + r) * ld + p + c] : 0.0;
-  }
-  const int fail = chol_inv_64(ar, xr, 0.0, sh);
+  for (int c = 0; c < kNB; ++c) a[c] = c <= r ? row[c] : 0.0;
+  const int fail = chol_inv_64_wave(a, x, 0.0, sh);
+  // column r of L from its LDS copy (a[] is dead after the factorisation)
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g + 4 * q;
-    L[(int64_t)(p + r) * ld + p + c] = c <= r ? ar[q] : 0.0;
-    Linv[(int64_t)(p + r) * ld + p + c] = c <= r ? xr[q] : 0.0;
-  }
-  if (tid == 0 && fail != 0) {
+  for (int i = 0; i < kNB; ++i) L[(int64_t)(p + i) * ld + p + r] = sh.lt[r * kLw + i];
+  // lane r holds column r of the inverse
+#pragma unroll
+  for (int i = 0; i < kNB; ++i) Linv[(int64_t)(p + i) * ld + p + r] = x[i];
+  if (r == 0 && fail != 0) {
     if (*info == 0) *info = p + fail;
   }
 }
@@ -1065,26 +1138,38 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const double* __restr
 __global__ __launch_bounds__(256) void chol_small_kernel(const double* __restrict__ part,
                                                          int nparts, int k,
                                                          double* __restrict__ Rinv, int* info) {
-  __shared__ CholLds sh;
-  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
-  double ar[16], xr[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g + 4 * q;
-    double v = c == r ? 1.0 : 0.0;
-    if (r < k && c < k && c <= r) {
-      v = 0.0;
-      for (int b = 0; b < nparts; ++b) v += part[(int64_t)b * k * k + r * k + c];
+  __shared__ CholWaveLds sh;
+  // the sum of the partials, by all four waves, goes through LDS (by
+  // columns); wave 0 alone then loads its register rows, outside any loop
+  const int kk = k * k;
+  for (int e = threadIdx.x; e < kk; e += 256) {
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int b = 0;
+    for (; b + 3 < nparts; b += 4) {
+      v0 += part[(int64_t)b * kk + e];
+      v1 += part[(int64_t)(b + 1) * kk + e];
+      v2 += part[(int64_t)(b + 2) * kk + e];
+      v3 += part[(int64_t)(b + 3) * kk + e];
     }
-    ar[q] = c <= r ? v : 0.0;
+    for (; b < nparts; ++b) v0 += part[(int64_t)b * kk + e];
+    sh.lt[(e % k) * kLw + e / k] = (v0 + v1) + (v2 + v3);
   }
-  const int fail = chol_inv_64(ar, xr, 0.25, sh);
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const int r = threadIdx.x;
+  double a[kNB], x[kNB];
+  // rows and columns beyond k are the identity's
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int c = g + 4 * q;
-    if (r < k && c < k) Rinv[c * k + r] = c <= r ? xr[q] : 0.0;
-  }
-  if (tid == 0 && fail != 0) {
+  for (int c = 0; c < kNB; ++c)
+    a[c] = (r < k && c < k) ? (c <= r ? sh.lt[c * kLw + r] : 0.0) : (c == r ? 1.0 : 0.0);
+  const int fail = chol_inv_64_wave(a, x, 0.25, sh);
+  // lane r holds column r of L^-1, i.e. row r of R^-1 = L^-T; it goes out
+  // through LDS so that the stores carry no per-element guard (guarded, the
+  // compiler sinks the whole solve into the guarded blocks)
+#pragma unroll
+  for (int i = 0; i < kNB; ++i) sh.lt[i * kLw + r] = x[i];
+  for (int e = r; e < kk; e += 64) Rinv[e] = sh.lt[(e % k) * kLw + e / k];
+  if (r == 0 && fail != 0) {
     if (*info == 0) *info = -2;
   }
 }
@@ -1295,7 +1380,7 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
                      stream, S, N, Np, L, Linv, info);
   TL_CHECK_LAUNCH();
   for (int q = 0; q < Np; q += kNB) {
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, stream, L, Linv, ld, q, info);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(64), 0, stream, L, Linv, ld, q, info);
     TL_CHECK_LAUNCH();
     const int rest = Np - q - kNB;
     if (rest <= 0) continue;
