@@ -226,93 +226,6 @@ __global__ __launch_bounds__(256) void setup_kernel(const double* __restrict__ S
   Linv[idx] = 0.0;
 }
 
-// Cholesky factor and inverse of a 64 x 64 symmetric block held in
-// registers: thread (r, g) = (tid % 64, tid / 64) of a 256-thread workgroup
-// keeps row r, columns g, g+4, ..., g+60 of the lower triangle in ar (on
-// return: of L) and of L^-1 in xr.  The current column or row is broadcast
-// through double-buffered LDS lines, one barrier per step, and every update
-// is branch-free.  A pivot not above pmin is replaced by 1; the return value
-// is the first such column + 1 (0 if none).
-struct CholLds {
-  double line[2][kNB];
-  double xrow[2][kNB];
-  double lcol[2][kNB];
-  double rdiag[kNB];  // 1 / L[c][c]
-};
-
-__device__ int chol_inv_64(double (&ar)[16], double (&xr)[16], double pmin, CholLds& sh) {
-  const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) xr[q] = (g + 4 * q) == r ? 1.0 : 0.0;
-  int fail = 0;
-  // fully unrolled: the register index of column c is a compile-time constant
-#pragma unroll
-  for (int c = 0; c < kNB; ++c) {
-    const int go = c & 3, qo = c >> 2;
-    double* col = sh.line[c & 1];
-    if (g == go) {
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (q == qo) v = ar[q];
-      col[r] = v;
-    }
-    __syncthreads();
-    double piv = col[c];
-    if (!(piv > fmax(pmin, 1e-300))) {  // pivots at or below 1e-300 count as failed
-      if (fail == 0) fail = c + 1;
-      piv = 1.0;
-    }
-    const double rinv = nrsq(piv), lcc = piv * rinv;
-    if (tid == 0) sh.rdiag[c] = rinv;
-    const double lrc = r > c ? col[r] * rinv : (r == c ? lcc : 0.0);
-    double cv[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) cv[q] = col[g + 4 * q];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int cc = g + 4 * q;
-      const double upd = ar[q] - lrc * (cv[q] * rinv);
-      ar[q] = (q == qo && g == go && r >= c) ? lrc : ((r > c && cc > c && cc <= r) ? upd : ar[q]);
-    }
-  }
-  __syncthreads();  // rdiag complete
-  // X = L^-1 by forward elimination on the identity: step i finalises row i
-  // (scaled by 1 / L[i][i]) and removes L[r][i] * row i from rows r > i
-#pragma unroll
-  for (int i = 0; i < kNB; ++i) {
-    double* rowi = sh.xrow[i & 1];
-    double* coli = sh.lcol[i & 1];
-    if (r == i) {
-      const double sc = sh.rdiag[i];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        xr[q] *= sc;
-        rowi[g + 4 * q] = xr[q];
-      }
-    }
-    if (g == (i & 3)) {
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (q == (i >> 2)) v = ar[q];
-      coli[r] = v;
-    }
-    __syncthreads();
-    const double l = coli[r];
-    double rv[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) rv[q] = rowi[g + 4 * q];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int jj = g + 4 * q;
-      const double upd = xr[q] - l * rv[q];
-      xr[q] = (r > i && jj <= i) ? upd : xr[q];
-    }
-  }
-  return fail;
-}
-
 constexpr int kLw = kNB + 2;
 struct __attribute__((aligned(16))) CholWaveLds {
   double lt[kNB * kLw];  // L by columns: lt[c * kLw + r] = L[r][c], zero above the diagonal
@@ -363,13 +276,15 @@ __device__ __forceinline__ void inv_wave_cols(double (&x)[kNB], const CholWaveLd
   (inv_wave_col<K>(x, sh), ...);
 }
 
-// The same factorisation and inverse in one wave, with no barrier: lane r
-// keeps row r of the block in a[] (entries c > r ignored), every pivot and
-// every column entry L[j][c] reaches the other lanes through readlane, and
-// the rank-1 updates are FMAs with a scalar operand.  L then goes to LDS by
-// columns and lane r solves column r of X = L^-1 in registers, reading the
-// columns of L as LDS broadcasts.  On return sh.lt holds L and x[i] =
-// X[i][r] (zero for i < r).  Pivot rule and return value as chol_inv_64.
+// Cholesky factor and inverse of a 64 x 64 symmetric block in one wave,
+// with no barrier: lane r keeps row r of the block in a[] (entries c > r
+// ignored), every pivot and every column entry L[j][c] reaches the other
+// lanes through readlane, and the rank-1 updates are FMAs with a scalar
+// operand.  L then goes to LDS by columns and lane r solves column r of
+// X = L^-1 in registers, reading the columns of L as LDS broadcasts.  On
+// return sh.lt holds L and x[i] = X[i][r] (zero for i < r).  A pivot not
+// above pmin is replaced by 1; the return value is the first such column + 1
+// (0 if none).
 __device__ __forceinline__ int chol_inv_64_wave(double (&a)[kNB], double (&x)[kNB], double pmin,
                                                 CholWaveLds& sh) {
   const int r = threadIdx.x & 63;
