@@ -163,6 +163,19 @@ tl_status tl_lattice_sum_potential(const tl_system* sys, double* P_dev, void* ws
                                    size_t ws_bytes, void* stream);
 
 /*
+ * tl_build_basis_and_potential - tl_build_basis and tl_lattice_sum_potential
+ * in one call, with the arguments and outputs of the two (G_dev, AG_dev,
+ * SG_dev: basis_elems doubles each; P_dev: pot_elems doubles; ws as for the
+ * potential).  The results are bit-identical to the two calls in sequence.
+ * For a system periodic in dim 0 with m0 <= 8 both steps share one kernel
+ * launch (they are independent); otherwise the two launches run in order.
+ * Errors: TL_EINVAL for an invalid system or a null output array.
+ */
+tl_status tl_build_basis_and_potential(const tl_system* sys, double* G_dev, double* AG_dev,
+                                       double* SG_dev, double* P_dev, void* ws_dev,
+                                       size_t ws_bytes, void* stream);
+
+/*
  * tl_assemble_core_hamiltonian_block - Galerkin matrices from 1D inner
  * products (proof of Lemma 3.1, eq. (nuc_potMatrTot); Sec. 3.4 A_3; Lemma 4.1
  * eqs. (BC-Core), (BC-mass), (BC-Laplace)):

@@ -8,8 +8,11 @@ namespace dev {
 
 constexpr double kGaussTailExponent = 46.0;  // images within exp(-46) of the peak
 
-struct BasisArgs {
-  FnParams fn[TL_MAX_M0];
+// Kernel arguments of the basis step; MaxFn bounds m0 (a launch that shares its
+// arguments with other steps carries a shorter table).
+template <int MaxFn>
+struct BasisArgsN {
+  FnParams fn[MaxFn];
   double x0[3], period[3];
   int64_t begin[3];   // flat start of each dimension (rows * n elements each)
   int64_t total;
@@ -17,6 +20,7 @@ struct BasisArgs {
   double h, box_origin0, box_a;
   int m0;
 };
+using BasisArgs = BasisArgsN<TL_MAX_M0>;
 
 __device__ inline double factor_value(double x, double A, int l, double alpha, double coef) {
   double r = x - A;
@@ -38,7 +42,8 @@ __device__ inline double sample(double x0, double h, double period, int periodic
 }
 
 // Thread per (row, node) of the three dimensions; bx is the block index.
-__device__ inline void basis_body(const BasisArgs& p, double* __restrict__ G,
+template <class Args>
+__device__ inline void basis_body(const Args& p, double* __restrict__ G,
                                   double* __restrict__ AG, double* __restrict__ SG, int64_t bx) {
   int64_t idx = bx * blockDim.x + threadIdx.x;
   if (idx >= p.total) return;

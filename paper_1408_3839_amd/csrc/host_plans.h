@@ -55,6 +55,8 @@ tl_status plan_potential(const Geometry& g, const tl_system* s, double* P, void*
                          size_t ws_bytes, PotentialPlan* out);
 
 void make_basis_args(const Geometry& g, const tl_system* s, dev::BasisArgs* p);
+tl_status build_basis(const Geometry& g, const tl_system* s, double* G, double* AG, double* SG,
+                      hipStream_t stream);
 
 size_t box_workspace_bytes(const Geometry& g);
 tl_status assemble_box(const Geometry& g, const tl_system* s, const double* G, const double* AG,

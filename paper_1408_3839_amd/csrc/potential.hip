@@ -14,13 +14,17 @@
 // entry enters one window node once (per site), so the entries are evaluated
 // (ALU-bound, erfc) inside the workgroup that sums them, not stored.
 // Open dims: one factor per nucleus, evaluated directly.  Torus and open
-// transverse dims share one launch.
+// transverse dims share one launch, and for periodic systems that launch can
+// also carry the basis samples of Sec. 3.4 (independent work, one kernel
+// start instead of two).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <vector>
 
 #include "common.h"
+#include "dev_basis.h"
 #include "dev_potential.h"
 #include "host_plans.h"
 
@@ -37,6 +41,24 @@ __global__ __launch_bounds__(256) void potential_kernel(DirectArgs a, FoldArgs f
                                                         int T, int fold_blocks,
                                                         double* __restrict__ P) {
   dev::potential_body(a, f, quad, T, fold_blocks, P, blockIdx.x);
+}
+
+// Basis functions the combined launch carries by value: the kernel
+// arguments stay near 3 KB.
+constexpr int kFusedFn = 8;
+
+// Potential vectors and basis samples of one system in one launch: blocks
+// [0, pot_blocks) run potential_body, the rest basis_body.  The two read only
+// the system and write disjoint arrays; the branch is uniform per workgroup.
+__global__ __launch_bounds__(256) void basis_potential_kernel(
+    dev::BasisArgsN<kFusedFn> b, double* __restrict__ G, double* __restrict__ AG,
+    double* __restrict__ SG, DirectArgs a, FoldArgs f, QuadArgs quad, int T, int fold_blocks,
+    int pot_blocks, double* __restrict__ P) {
+  const int64_t bx = blockIdx.x;
+  if (bx < pot_blocks)
+    dev::potential_body(a, f, quad, T, fold_blocks, P, bx);
+  else
+    dev::basis_body(b, G, AG, SG, bx - pot_blocks);
 }
 
 __global__ __launch_bounds__(256) void box_potential_kernel(BoxArgs p, QuadArgs quad,
@@ -181,6 +203,47 @@ tl_status lattice_sum_potential(const Geometry& g, const tl_system* s, double* P
   return TL_OK;
 }
 
+// Both steps, one launch where the system allows it (periodic dim 0 and
+// m0 <= kFusedFn); otherwise the two launches of the separate calls.  The
+// results are those of build_basis followed by lattice_sum_potential, bit
+// for bit: the same device code runs on the same arguments.
+tl_status build_basis_and_potential(const Geometry& g, const tl_system* s, double* G, double* AG,
+                                    double* SG, double* P, void* ws, size_t ws_bytes,
+                                    hipStream_t stream) {
+  PotentialPlan pp;
+  TL_TRY(plan_potential(g, s, P, ws, ws_bytes, &pp));
+  if (pp.box_dim0 || g.m0 > kFusedFn) {
+    TL_TRY(build_basis(g, s, G, AG, SG, stream));
+    return lattice_sum_potential(g, s, P, ws, ws_bytes, stream);
+  }
+  dev::BasisArgs full;
+  make_basis_args(g, s, &full);
+  dev::BasisArgsN<kFusedFn> b;
+  std::memset(&b, 0, sizeof(b));
+  for (int mu = 0; mu < g.m0; ++mu) b.fn[mu] = full.fn[mu];
+  for (int d = 0; d < 3; ++d) {
+    b.x0[d] = full.x0[d];
+    b.period[d] = full.period[d];
+    b.begin[d] = full.begin[d];
+    b.n[d] = full.n[d];
+    b.periodic[d] = full.periodic[d];
+    b.rows[d] = full.rows[d];
+  }
+  b.total = full.total;
+  b.h = full.h;
+  b.box_origin0 = full.box_origin0;
+  b.box_a = full.box_a;
+  b.m0 = full.m0;
+  const int T = (int)g.pot_terms;
+  const int64_t pot_blocks = (int64_t)pp.fold_blocks + pp.direct_blocks;
+  const int64_t blocks = pot_blocks + ceil_div(b.total, 256);
+  TL_REQUIRE(blocks <= INT32_MAX, "grid too large");
+  hipLaunchKernelGGL(basis_potential_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, b, G,
+                     AG, SG, pp.direct, pp.fold, pp.quad, T, pp.fold_blocks, (int)pot_blocks, P);
+  TL_CHECK_LAUNCH();
+  return TL_OK;
+}
+
 }  // namespace tl
 
 extern "C" tl_status tl_potential_workspace_bytes(const tl_system* sys, size_t* bytes) {
@@ -199,4 +262,15 @@ extern "C" tl_status tl_lattice_sum_potential(const tl_system* sys, double* P_de
   TL_TRY(tl::digest(sys, &g));
   TL_REQUIRE(P_dev != nullptr, "null output array");
   return tl::lattice_sum_potential(g, sys, P_dev, ws_dev, ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" tl_status tl_build_basis_and_potential(const tl_system* sys, double* G_dev,
+                                                  double* AG_dev, double* SG_dev, double* P_dev,
+                                                  void* ws_dev, size_t ws_bytes, void* stream) {
+  tl::clear_error();
+  tl::Geometry g;
+  TL_TRY(tl::digest(sys, &g));
+  TL_REQUIRE(G_dev && AG_dev && SG_dev && P_dev, "null output array");
+  return tl::build_basis_and_potential(g, sys, G_dev, AG_dev, SG_dev, P_dev, ws_dev, ws_bytes,
+                                       (hipStream_t)stream);
 }

@@ -75,9 +75,12 @@ class PeriodicPipeline:
         tl.tl_batched_heigh(self.HSbar[0], self.HSbar[1], self.nblocks, self.m0, self.evals,
                             self.evecs, self.info, stream)
 
+    def basis_and_potential(self, stream=None):
+        tl.tl_build_basis_and_potential(self.handle, self.G, self.AG, self.SG, self.P,
+                                        self.pot_ws, self.pot_ws_bytes, stream)
+
     def run(self, stream=None):
-        self.build_basis(stream)
-        self.lattice_sum_potential(stream)
+        self.basis_and_potential(stream)
         self.assemble(stream)
         self.block_fft(stream)
         self.heigh(stream)
@@ -214,8 +217,8 @@ class BoxPipeline:
         self.eig = DenseEigh(self.Nb, k, with_evecs, device) if k > 0 else None
 
     def assemble(self, stream=None):
-        tl.tl_build_basis(self.handle, self.G, self.AG, self.SG, stream)
-        tl.tl_lattice_sum_potential(self.handle, self.P, self.pot_ws, self.pot_ws_bytes, stream)
+        tl.tl_build_basis_and_potential(self.handle, self.G, self.AG, self.SG, self.P,
+                                        self.pot_ws, self.pot_ws_bytes, stream)
         tl.tl_assemble_core_hamiltonian_block(self.handle, self.G, self.AG, self.SG, self.P,
                                               tl.TL_FP64, 0, self.H, self.S, self.asm_ws,
                                               self.asm_ws_bytes, stream)

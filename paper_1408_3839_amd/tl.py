@@ -96,6 +96,9 @@ SIGNATURES = {
     "tl_lattice_sum_potential": (ctypes.c_int, [ctypes.POINTER(TlSystem), ctypes.c_void_p,
                                                 ctypes.c_void_p, ctypes.c_size_t,
                                                 ctypes.c_void_p]),
+    "tl_build_basis_and_potential": (ctypes.c_int, [ctypes.POINTER(TlSystem)]
+                                     + [ctypes.c_void_p] * 5
+                                     + [ctypes.c_size_t, ctypes.c_void_p]),
     "tl_assemble_core_hamiltonian_block": (
         ctypes.c_int, [ctypes.POINTER(TlSystem), ctypes.c_void_p, ctypes.c_void_p,
                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
@@ -271,6 +274,13 @@ def tl_lattice_sum_potential(sys, P, ws, ws_bytes, stream=None):
     h = _handle(sys)
     _check(load().tl_lattice_sum_potential(h.ref, _ptr(P), _ptr(ws), int(ws_bytes),
                                            _stream(stream)), "tl_lattice_sum_potential")
+
+
+def tl_build_basis_and_potential(sys, G, AG, SG, P, ws, ws_bytes, stream=None):
+    h = _handle(sys)
+    _check(load().tl_build_basis_and_potential(h.ref, _ptr(G), _ptr(AG), _ptr(SG), _ptr(P),
+                                               _ptr(ws), int(ws_bytes), _stream(stream)),
+           "tl_build_basis_and_potential")
 
 
 def tl_assemble_core_hamiltonian_block(sys, G, AG, SG, P, precision, n_slices, H, S, ws,

@@ -101,6 +101,29 @@ def test_potential_parity(name):
         assert np.all(err <= 1e-13 * scale), (name, d, float((err / scale).max()))
 
 
+@pytest.mark.parametrize("name", NAMES + ["box12"])
+def test_basis_and_potential_one_call(name):
+    """The combined call (one launch for periodic m0 <= 8, two otherwise)
+    writes exactly what the two separate calls write."""
+    from paper_1408_3839_amd import tl
+    if name == "box12":
+        from paper_1408_3839_amd.pipeline import BoxPipeline
+        pl = BoxPipeline(wl.box_chain_system("box12", 12, 1.5, [1.0, 2.0], 0.1, [400, 64, 72],
+                                             5, (0.3, 4.0), 10, seed=12))
+    else:
+        pl = _pipeline(SYSTEMS[name]())
+    tl.tl_build_basis(pl.handle, pl.G, pl.AG, pl.SG)
+    tl.tl_lattice_sum_potential(pl.handle, pl.P, pl.pot_ws, pl.pot_ws_bytes)
+    ref = [t.clone() for t in (pl.G, pl.AG, pl.SG, pl.P)]
+    for t in (pl.G, pl.AG, pl.SG, pl.P):
+        t.fill_(float("nan"))
+    tl.tl_build_basis_and_potential(pl.handle, pl.G, pl.AG, pl.SG, pl.P, pl.pot_ws,
+                                    pl.pot_ws_bytes)
+    torch.cuda.synchronize()
+    for got, want in zip((pl.G, pl.AG, pl.SG, pl.P), ref):
+        assert torch.equal(got, want), name
+
+
 @pytest.mark.parametrize("name", NAMES)
 def test_assembly_parity(name):
     sys = SYSTEMS[name]()
