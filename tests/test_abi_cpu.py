@@ -88,6 +88,7 @@ def test_null_outputs_and_small_workspaces_rejected():
     _expect(tl.tl_batched_heigh, tl.TL_EINVAL, 8, 0, 4, 0, 8, 0, 8, 0)
     _expect(tl.tl_batched_heigh, tl.TL_EINVAL, 8, 0, 4, 33, 8, 0, 8, 0)
     _expect(tl.tl_batched_heigh, tl.TL_EINVAL, 0, 0, 4, 4, 8, 0, 8, 0)
+    _expect(tl.tl_build_basis_and_potential, tl.TL_EINVAL, s, 8, 8, 8, 0, 0, 0, 0)
 
 
 def test_workspace_queries():
