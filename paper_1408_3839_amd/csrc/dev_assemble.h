@@ -37,7 +37,10 @@ struct DimArgs {
 // covers all of the tile's shifts of mu.  Rows sit at the stride kc + 2
 // (2 mod 32), so the 32 lanes of an operand read (16 rows, 2 nodes) fall in
 // distinct banks; window node x sits at x + ypad (x / 32), with ypad chosen
-// per dimension so that windows read cn nodes apart do too.  Shared by the
+// per dimension so that windows read cn nodes apart do too.  A dimension
+// with a single shift (S = 1) needs no windows: each Y column is then the G
+// row of its mu over the sub-chunk, which every tile of that dimension
+// stages in its G block and reads with no padding (ypd = 0).  Shared by the
 // host (sizing) and the kernel.
 constexpr int kMaxSrcTile = 64;  // largest tile edge of the source-row kernel
 
@@ -45,9 +48,10 @@ struct TileLayout {
   int t0, nP;               // P rows t0 .. t0+nP-1 (terms below T)
   int offP, offG, offA, offS;  // row blocks; offG/A/S = -1 when the tile has no such row
   int mu0, nmu;             // mu0 .. mu0+nmu-1
+  int ypd;                  // pad doubles per 32 window nodes as read (0: Y from the G rows)
   int ysh_hi[kMaxSrcTile];  // per local mu: largest shift of the tile
   int yoff[kMaxSrcTile];    // per local mu: offset of its window
-  int ylen[kMaxSrcTile];    // per local mu: window length in nodes
+  int ylen[kMaxSrcTile];    // per local mu: window length in nodes (0: not staged)
   int xtotal, total;        // doubles up to the end of the X sources, of everything
 };
 
@@ -66,7 +70,8 @@ __host__ __device__ inline void tile_layout(int M, int N, int S, int cn, int m0,
   L->offP = off;
   off += L->nP * ld;
   L->offG = L->offA = L->offS = -1;
-  if (t0 < T) {
+  const bool yrows = S == 1;  // every column is shift 0: the Y columns are G rows
+  if (t0 < T || yrows) {
     L->offG = off;
     off += m0 * ld;
   }
@@ -82,8 +87,15 @@ __host__ __device__ inline void tile_layout(int M, int N, int S, int cn, int m0,
   const int c1 = min(N, col0 + bn) - 1;
   L->mu0 = col0 / S;
   L->nmu = c1 / S - L->mu0 + 1;
+  L->ypd = yrows ? 0 : ypad;
   for (int u = 0; u < L->nmu; ++u) {
     const int mu = L->mu0 + u;
+    if (yrows) {
+      L->ysh_hi[u] = 0;
+      L->yoff[u] = L->offG + mu * ld;
+      L->ylen[u] = 0;
+      continue;
+    }
     const int sh_lo = max(0, col0 - mu * S), sh_hi = min(S - 1, c1 - mu * S);
     const int len = kc + (sh_hi - sh_lo) * cn;
     L->ysh_hi[u] = sh_hi;
@@ -224,6 +236,7 @@ __device__ inline void contract_f64_src_body(const ContractArgs& a, int b) {
     for (int e = tid; e < zl + kc; e += 256) sm[e] = e < zl ? 0.0 : 1.0;
   }
   __syncthreads();
+  const int ypd = L.ypd;
   // this lane's A rows and B columns as LDS offsets (the node is added);
   // lanes outside the matrix read the zero row
   int xp[RM], xb[RM], yo[RN], yw[RN];
@@ -303,7 +316,7 @@ __device__ inline void contract_f64_src_body(const ContractArgs& a, int b) {
 #pragma unroll
         for (int cb = 0; cb < RN; ++cb) {
           const int w = yw[cb] + k;
-          bv[s][cb] = sm[yo[cb] + w + ((w >> 5) << ysh)];
+          bv[s][cb] = sm[yo[cb] + w + (w >> 5) * ypd];
         }
       }
 #pragma unroll
@@ -322,7 +335,7 @@ __device__ inline void contract_f64_src_body(const ContractArgs& a, int b) {
 #pragma unroll
       for (int cb = 0; cb < RN; ++cb) {
         const int w = yw[cb] + k;
-        bv[cb] = sm[yo[cb] + w + ((w >> 5) << ysh)];
+        bv[cb] = sm[yo[cb] + w + (w >> 5) * ypd];
       }
 #pragma unroll
       for (int rb = 0; rb < RM; ++rb)
