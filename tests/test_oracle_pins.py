@@ -168,6 +168,62 @@ def _brute_force_potential_3d(sys):
     return P3
 
 
+def _nearest_image_factor(c, n, h, K, t, o, shift=0):
+    """Lattice-summed factor at every torus node, from the node coordinate:
+    node x_i = i h is moved to its nearest lattice point j a (ties at half a
+    cell go to the upper point), and the images o + k a, k = -K..K, are
+    integrated over the cell [r - h/2, r + h/2] of the displacement
+    r = x_i - j a in 40-digit arithmetic.  `shift` moves the tie rule by that
+    many nodes (a deliberately wrong window, to show the pin has power)."""
+    mp.mp.dps = 40
+    a = c * h
+    t = mp.mpf(t)
+    out = np.zeros(n)
+    for i in range(n):
+        j = (2 * i + c + 2 * shift) // (2 * c)      # nearest lattice point, integer arithmetic
+        r = mp.mpf(i - j * c) * mp.mpf(h)
+        acc = mp.mpf(0)
+        for k in range(-K, K + 1):
+            ctr = mp.mpf(o) + k * mp.mpf(a)
+            acc += mp.sqrt(mp.pi) / (2 * t) * (mp.erf(t * (r + mp.mpf(h) / 2 - ctr))
+                                                 - mp.erf(t * (r - mp.mpf(h) / 2 - ctr)))
+        out[i] = float(acc)
+    return out
+
+
+@pytest.mark.parametrize("c", [7, 8])
+def test_torus_window_is_nearest_image(c):
+    """Sec. 4.1 eq. (EwaldSumP) with the symmetric image range of Sec. 3.2
+    eq. (EwaldSumE): each torus node sums the 2K+1 images of the site seen
+    from its own nearest lattice point, so the lattice-summed factor is a
+    function of the node's displacement from that point.  Checked for odd
+    and even cell widths against the node coordinate itself, for a site on
+    the cell origin and one two nodes off it, at a diffuse kernel exponent
+    whose farthest image is not negligible; a window off by one node fails."""
+    h = 0.25
+    s = wl.tiny_periodic(L=(5, 1, 1), m0=1, c=c, h=h, R=4, K=(2, 0, 0))
+    n, K = int(s.n[0]), int(s.K[0])
+    for o in (0.0, 2 * h):
+        for t in (0.3, 1.1, 3.0):
+            ref = _nearest_image_factor(c, n, h, K, t, o)
+            got = oracle.lattice_summed_factor(s, 0, t, o)
+            np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+            if t == 0.3:  # the pin separates a window shifted by one node
+                wrong = _nearest_image_factor(c, n, h, K, t, o, shift=1)
+                assert np.abs(wrong - got).max() > 1e-6 * np.abs(ref).max()
+    # the replicated vector is a-periodic and, for a site on the cell origin,
+    # mirror-symmetric about the site: v(x_i) = v(-x_i) on the torus
+    v = oracle.lattice_summed_factor(s, 0, 0.3, 0.0)
+    np.testing.assert_allclose(v, np.roll(v, c), rtol=0, atol=0)
+    mirror = v[(-np.arange(n)) % n]
+    np.testing.assert_allclose(v, mirror, rtol=0, atol=4e-16 * np.abs(v).max())
+    # the same factors, times w_q and Z, are the x vectors of the potential
+    Ps = oracle.potential_vectors(s)
+    for q in range(s.R):
+        ref = float(s.w_q[q]) * _nearest_image_factor(c, n, h, K, float(s.t_q[q]), 0.0)
+        np.testing.assert_allclose(Ps[0][q], ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+
+
 def test_separable_lattice_sum_equals_3d_brute_force():
     """Eq. (EwaldTensorGl)/(EwaldSumP): the rank-(groups x R) separable
     potential and the resulting V blocks equal a direct 3D image sum
