@@ -199,6 +199,29 @@ tl_status tl_assemble_core_hamiltonian_block(const tl_system* sys, const double*
                                              void* ws_dev, size_t ws_bytes, void* stream);
 
 /*
+ * tl_assemble_core_hamiltonian_block_noalloc - the same assembly for callers
+ * that cannot allocate or pass device memory for scratch (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ *   Arguments, outputs and results as tl_assemble_core_hamiltonian_block
+ *   (bit-identical outputs; the same kernels), without ws_dev/ws_bytes: the
+ *   scratch is a static device array of 32 MiB that each device the library
+ *   runs on holds until the process ends.  Calls no hipMalloc/hipFree.
+ *   The device is the current one (hipGetDevice) at the call; its scratch
+ *   address is looked up on the first call on that device.
+ *   Errors: those of tl_assemble_core_hamiltonian_block, and TL_EUNSUPPORTED
+ *   when the system needs more scratch than 32 MiB
+ *   (tl_assemble_workspace_bytes tells); nothing is enqueued then.
+ *   Every call on one device shares that device's scratch: calls that
+ *   overlap on one device (different streams, or different threads) race.
+ *   Calls on one stream are ordered and safe.
+ */
+tl_status tl_assemble_core_hamiltonian_block_noalloc(const tl_system* sys, const double* G_dev,
+                                                     const double* AG_dev, const double* SG_dev,
+                                                     const double* P_dev, tl_precision prec,
+                                                     int n_slices, double* H_dev, double* S_dev,
+                                                     void* stream);
+
+/*
  * tl_set_contraction_events - profiling hook: when both are non-NULL, the
  * assembly and batch calls made afterwards by the calling thread attach
  * start_event and stop_event (hipEvent_t, created with timing) to the launch

@@ -21,6 +21,7 @@
 //   H_k = T_k - V_k.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 #include "dev_assemble.h"
@@ -465,6 +466,44 @@ extern "C" tl_status tl_assemble_workspace_bytes(const tl_system* sys, tl_precis
   return TL_OK;
 }
 
+namespace tl {
+namespace {
+
+// Scratch memory of the allocation-free assembly entry point: a file-scope
+// device array (each device the library runs on holds its own copy until the
+// process ends).  Host code never uses the array's name as an address: the
+// device address is taken once per device with hipGetSymbolAddress and kept.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+tl_status static_scratch(void** out) {
+  int dev = -1;
+  TL_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device index %d outside [0, %d)", dev, kMaxDevices);
+    return TL_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    TL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) {
+      set_error("hipGetSymbolAddress returned a null scratch address");
+      return TL_EHIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TL_OK;
+}
+
+}  // namespace
+}  // namespace tl
+
 extern "C" tl_status tl_assemble_core_hamiltonian_block(const tl_system* sys, const double* G_dev,
                                                         const double* AG_dev,
                                                         const double* SG_dev,
@@ -482,4 +521,32 @@ extern "C" tl_status tl_assemble_core_hamiltonian_block(const tl_system* sys, co
                                  ws_dev, ws_bytes, (hipStream_t)stream);
   return tl::assemble_box(g, sys, G_dev, AG_dev, SG_dev, P_dev, prec, H_dev, S_dev, ws_dev,
                          ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" tl_status tl_assemble_core_hamiltonian_block_noalloc(
+    const tl_system* sys, const double* G_dev, const double* AG_dev, const double* SG_dev,
+    const double* P_dev, tl_precision prec, int n_slices, double* H_dev, double* S_dev,
+    void* stream) {
+  tl::clear_error();
+  tl::Geometry g;
+  TL_TRY(tl::digest(sys, &g));
+  TL_REQUIRE(G_dev && AG_dev && SG_dev && P_dev && H_dev && S_dev, "null array argument");
+  TL_REQUIRE(prec >= TL_FP64 && prec <= TL_SPLIT_FP16, "unknown precision %d", (int)prec);
+  const size_t need =
+      g.mode == TL_MODE_BOX
+          ? tl::box_workspace_bytes(g)
+          : tl::assemble_workspace_bytes(g, prec, n_slices, tl::kDefaultContractBlocks);
+  if (need > tl::kStaticScratchBytes) {
+    tl::set_error("allocation-free assembly: this system needs %zu bytes of scratch, the "
+                  "static scratch holds %zu; use tl_assemble_core_hamiltonian_block",
+                  need, tl::kStaticScratchBytes);
+    return TL_EUNSUPPORTED;
+  }
+  void* ws = nullptr;
+  TL_TRY(tl::static_scratch(&ws));
+  if (g.mode == TL_MODE_PERIODIC)
+    return tl::assemble_periodic(g, G_dev, AG_dev, SG_dev, P_dev, prec, n_slices, H_dev, S_dev,
+                                 ws, tl::kStaticScratchBytes, (hipStream_t)stream);
+  return tl::assemble_box(g, sys, G_dev, AG_dev, SG_dev, P_dev, prec, H_dev, S_dev, ws,
+                         tl::kStaticScratchBytes, (hipStream_t)stream);
 }

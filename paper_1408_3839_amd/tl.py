@@ -104,6 +104,10 @@ SIGNATURES = {
                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                        ctypes.c_void_p]),
+    "tl_assemble_core_hamiltonian_block_noalloc": (
+        ctypes.c_int, [ctypes.POINTER(TlSystem), ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "tl_set_contraction_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "tl_block_fft": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 5
                      + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -289,6 +293,14 @@ def tl_assemble_core_hamiltonian_block(sys, G, AG, SG, P, precision, n_slices, H
     _check(load().tl_assemble_core_hamiltonian_block(
         h.ref, _ptr(G), _ptr(AG), _ptr(SG), _ptr(P), int(precision), int(n_slices), _ptr(H),
         _ptr(S), _ptr(ws), int(ws_bytes), _stream(stream)), "tl_assemble_core_hamiltonian_block")
+
+
+def tl_assemble_core_hamiltonian_block_noalloc(sys, G, AG, SG, P, precision, n_slices, H, S,
+                                               stream=None):
+    h = _handle(sys)
+    _check(load().tl_assemble_core_hamiltonian_block_noalloc(
+        h.ref, _ptr(G), _ptr(AG), _ptr(SG), _ptr(P), int(precision), int(n_slices), _ptr(H),
+        _ptr(S), _stream(stream)), "tl_assemble_core_hamiltonian_block_noalloc")
 
 
 def tl_set_contraction_events(start_event, stop_event):

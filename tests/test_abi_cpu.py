@@ -124,3 +124,16 @@ def test_dense_eigh_validation():
     _expect(tl.tl_dense_gen_eigh_lowest, tl.TL_EINVAL, 8, 8, 100, 101, 8, 8, 8, 8, 1 << 30, 0)
     _expect(tl.tl_dense_gen_eigh_lowest, tl.TL_EINVAL, 0, 8, 100, 10, 8, 8, 8, 8, 1 << 30, 0)
     _expect(tl.tl_dense_gen_eigh_lowest, tl.TL_EWORKSPACE, 8, 8, 100, 10, 8, 8, 8, 8, 1024, 0)
+
+
+def test_noalloc_assembly_rejects_oversize_before_enqueue():
+    """The allocation-free assembly refuses, on the host, a system whose
+    scratch exceeds its static 32 MiB (no device memory is touched: the
+    pointers below are never dereferenced)."""
+    big = wl.tiny_periodic(L=(512, 1, 1), m0=32, c=64, h=0.25, R=64)
+    hb = tl.SystemHandle(big)
+    assert tl.tl_assemble_workspace_bytes(hb, tl.TL_SPLIT_BF16, 8) > 32 << 20
+    fake = 1 << 40
+    msg = _expect(tl.tl_assemble_core_hamiltonian_block_noalloc, tl.TL_EUNSUPPORTED, hb,
+                  fake, fake, fake, fake, tl.TL_SPLIT_BF16, 8, fake, fake, 0)
+    assert "static scratch" in msg
