@@ -36,8 +36,7 @@ struct InstanceJob {
   PotentialPlan pot;
   int T;  // potential terms
   AssemblyPlan asmb;
-  dev::DftArgs dft;
-  int dft_rchunks;
+  dev::FftArgs fft;
   const double* Hb;
   const double* Sb;
   double* evals;
@@ -121,10 +120,14 @@ __global__ __launch_bounds__(256) void batch_combine_kernel(const BatchDesc* __r
   dev::combine_periodic_body(J.asmb.combine, J.asmb.combine_total, lb);
 }
 
-__global__ __launch_bounds__(256) void batch_dft_kernel(const BatchDesc* __restrict__ d) {
-  extern __shared__ double tw[];
+__global__ __launch_bounds__(dev::kFftThreads) void batch_fft_kernel(
+    const BatchDesc* __restrict__ d) {
+  extern __shared__ __align__(16) double smem[];
   TL_BATCH_LOCATE(kDft)
-  dev::dft_axis_body<true, true>(J.dft, lb / J.dft_rchunks, lb % J.dft_rchunks, tw);
+  if (J.fft.blue)  // uniform per workgroup
+    dev::fft_block_body<true>(J.fft, lb, smem);
+  else
+    dev::fft_block_body<false>(J.fft, lb, smem);
 }
 
 template <int MAXM>
@@ -163,6 +166,14 @@ tl_status instance_sizes(const tl_system* s, tl_precision prec, int n_slices, in
   if (!g.periodic[0]) {
     set_error("the batched path needs a periodic x axis");
     return TL_EUNSUPPORTED;
+  }
+  {
+    const int Ls[3] = {g.L[0], 1, 1};
+    dev::FftArgs fa;
+    if (!plan_fft(nullptr, nullptr, Ls, g.m0, 2, &fa)) {
+      set_error("the batched path takes L <= 2048, or 7-smooth L <= 4096 (L = %d)", g.L[0]);
+      return TL_EUNSUPPORTED;
+    }
   }
   out->pot_ws = align_up(potential_workspace_bytes(g, s), 256);
   out->asm_ws = align_up(assemble_workspace_bytes(g, prec, n_slices, want), 256);
@@ -252,12 +263,11 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
                          is.asm_ws, plan->want_blocks, &J.asmb, 64));
     // one lattice axis: transform H and S (outer = 2) along L
     double* Hbar = buf->HSbar + 2 * ohs;
-    J.dft.in = H;
-    J.dft.out = Hbar;
-    J.dft.len = g.L[0];
-    J.dft.inner = (int64_t)g.m0 * g.m0;
-    J.dft.real_in = 1;
-    J.dft_rchunks = (int)ceil_div(J.dft.inner, 256);
+    const int Ls[3] = {g.L[0], 1, 1};
+    if (!plan_fft(H, Hbar, Ls, g.m0, 2, &J.fft)) {
+      set_error("instance %d: no LDS FFT plan for L = %d", i, g.L[0]);
+      return TL_EUNSUPPORTED;
+    }
     J.Hb = Hbar;
     J.Sb = Hbar + 2 * g.block_elems;
     J.evals = buf->evals + oev;
@@ -271,7 +281,7 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
     blocks[kContract] = J.asmb.contract_blocks;
     blocks[kReduce] = ceil_div(J.asmb.reduce_total, 256);
     blocks[kCombine] = ceil_div(J.asmb.combine_total, 4);
-    blocks[kDft] = 2LL * g.L[0] * J.dft_rchunks;
+    blocks[kDft] = ceil_div(J.fft.cols, J.fft.W);
     blocks[kHeigh] = g.L[0];
     for (int st = 0; st < kStages; ++st) d->prefix[st][i + 1] = d->prefix[st][i] + blocks[st];
     ob += g.basis_elems;
@@ -358,8 +368,9 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
   TL_CHECK_LAUNCH();
   hipLaunchKernelGGL(batch_combine_kernel, dim3(blocks(kCombine)), dim3(256), 0, stream, d);
   TL_CHECK_LAUNCH();
-  hipLaunchKernelGGL(batch_dft_kernel, dim3(blocks(kDft)), dim3(256),
-                     sizeof(double) * std::max<size_t>(2 * (size_t)plan->max_len, 2 * 256),
+  size_t fft_lds = 0;
+  for (int i = 0; i < hd->count; ++i) fft_lds = std::max(fft_lds, dev::fft_lds_bytes(hd->job[i].fft));
+  hipLaunchKernelGGL(batch_fft_kernel, dim3(blocks(kDft)), dim3(dev::kFftThreads), fft_lds,
                      stream, d);
   TL_CHECK_LAUNCH();
   if (plan->max_m0 <= 8)

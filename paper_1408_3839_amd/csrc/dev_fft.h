@@ -1,5 +1,7 @@
-// Device code of step a6 (block DFT over one lattice axis), shared by the
-// single-system and the batched launches.
+// Device code of step a6 (Fourier transform of block columns over the lattice
+// index), shared by the single-system and the batched launches: the LDS FFT
+// of whole lattices, and a direct DFT along one axis for lines longer than a
+// workgroup's LDS holds.
 #pragma once
 #include "common.h"
 
@@ -87,6 +89,364 @@ __device__ inline void dft_axis_body(const DftArgs& a, int64_t oj, int64_t by, d
   const int64_t o = (outer * a.len + j) * a.inner + r;
   a.out[2 * o] = re;
   a.out[2 * o + 1] = im;
+}
+
+// ------------------------------------------------------------------------
+// Block FFT in LDS.  A workgroup takes W real columns (entries (b, e) of the
+// batch of block columns, W/2 complex lines) over the whole lattice and
+// transforms them with every axis pass in LDS, so each input value is read
+// once and each output value written once.
+//   * Two real columns form one complex line z = x_a 2^-s_a + i x_b 2^-s_b,
+//     each scaled by a power of two to unit maximum (exact), so the rounding
+//     of each column stays relative to its own size; after the transform
+//     X_a(j) = (Z(j) + conj Z(-j))/2, X_b(j) = (Z(j) - conj Z(-j))/(2i).
+//   * Each axis of 7-smooth length is done by self-sorting (Stockham)
+//     radix-8/4/2/3/5/7 passes: a pass reads all its butterflies' points into
+//     registers, the workgroup synchronises, and writes them to their sorted
+//     places (in place, one buffer).
+//   * A single axis of another length L uses Bluestein's chirp-z form:
+//     w_L^(jk) = c(j) c(k) conj c(j-k), c(k) = exp(-i pi k^2/L), a cyclic
+//     convolution of length M >= 2L-1 (M 7-smooth) done by two forward FFTs
+//     of length M (the inverse as conj FFT conj) with the transform of the
+//     chirp filter formed once per workgroup.
+// Twiddles w_n^m = T2[m >> 6] T1[m & 63] from two small LDS tables per axis.
+constexpr int kFftPoints = 4096;  // complex points of a workgroup's buffer (64 KB)
+constexpr int kFftThreads = 512;  // threads per workgroup (8 waves)
+constexpr int kFftMaxPasses = 16;
+
+struct FftAxis {
+  int n;       // transform length (lattice extent, or Bluestein length M)
+  int S;       // buffer points after this axis (stride of its index)
+  int O;       // lines before this axis (product of the earlier extents)
+  int npass;
+  int tw_off;  // first complex entry of this axis' tables (T1: 64, T2: ceil(n/64))
+  unsigned char rad[kFftMaxPasses];
+};
+
+struct FftArgs {
+  const double* in;  // [cols/E][P][E] real
+  double* out;       // [cols/E][P][E] complex (interleaved)
+  int64_t E;         // entries of a block (m0*m0)
+  int64_t cols;      // real columns: batch * E
+  int L[3];          // lattice extents (1 for absent axes)
+  int P;             // L[0] L[1] L[2]
+  int W;             // real columns per workgroup (2..16, a power of two)
+  int naxes;
+  FftAxis ax[3];
+  int blue;          // 1: one axis of length blue_L by Bluestein, ax[0].n = M
+  int blue_L;
+  int nbuf;          // buffer points per line: P, or M
+  int tw_total;      // complex table entries of all axes
+};
+
+__host__ __device__ inline size_t fft_lds_bytes(const FftArgs& a) {
+  return sizeof(double) *
+         ((size_t)a.W * a.nbuf + 2 * (size_t)a.tw_total + (kFftThreads / 64 + 1) * (size_t)a.W);
+}
+
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ double2 c_mi(double2 a) { return make_double2(a.y, -a.x); }  // -i a
+
+// cos(2 pi m / R), sin(2 pi m / R) for the odd radices, m in [1, (R-1)/2]
+__device__ __forceinline__ constexpr double rcos(int R, int m) {
+  return R == 3 ? -0.5
+       : R == 5 ? (m == 1 ? 0.30901699437494742410 : -0.80901699437494742410)
+                : (m == 1 ? 0.62348980185873353053
+                          : (m == 2 ? -0.22252093395631440429 : -0.90096886790241912624));
+}
+__device__ __forceinline__ constexpr double rsin(int R, int m) {
+  return R == 3 ? 0.86602540378443864676
+       : R == 5 ? (m == 1 ? 0.95105651629515357212 : 0.58778525229247312917)
+                : (m == 1 ? 0.78183148246802980871
+                          : (m == 2 ? 0.97492791218182360702 : 0.43388373911755812048));
+}
+
+__device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
+  const double2 t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
+  const double2 t2 = c_add(a1, a3), t3 = c_mi(c_sub(a1, a3));
+  a0 = c_add(t0, t2);
+  a1 = c_add(t1, t3);
+  a2 = c_sub(t0, t2);
+  a3 = c_sub(t1, t3);
+}
+
+// forward DFT of R points in place: y_k = sum_t v_t exp(-2 pi i k t / R)
+template <int R>
+__device__ __forceinline__ void dft_small(double2 (&v)[R]) {
+  if constexpr (R == 2) {
+    const double2 t = v[0];
+    v[0] = c_add(t, v[1]);
+    v[1] = c_sub(t, v[1]);
+  } else if constexpr (R == 4) {
+    dft4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    constexpr double s = 0.70710678118654752440;
+    o1 = make_double2(s * (o1.x + o1.y), s * (o1.y - o1.x));    // * exp(-i pi/4)
+    o2 = c_mi(o2);                                              // * -i
+    o3 = make_double2(s * (o3.y - o3.x), -s * (o3.x + o3.y));   // * exp(-3 i pi/4)
+    v[0] = c_add(e0, o0);
+    v[4] = c_sub(e0, o0);
+    v[1] = c_add(e1, o1);
+    v[5] = c_sub(e1, o1);
+    v[2] = c_add(e2, o2);
+    v[6] = c_sub(e2, o2);
+    v[3] = c_add(e3, o3);
+    v[7] = c_sub(e3, o3);
+  } else {  // odd R: pair t with R - t
+    constexpr int h = (R - 1) / 2;
+    double2 sp[h], sm[h];
+    double2 y0 = v[0];
+#pragma unroll
+    for (int t = 1; t <= h; ++t) {
+      sp[t - 1] = c_add(v[t], v[R - t]);
+      sm[t - 1] = c_sub(v[t], v[R - t]);
+      y0 = c_add(y0, sp[t - 1]);
+    }
+    double2 out[R];
+    out[0] = y0;
+#pragma unroll
+    for (int k = 1; k <= h; ++k) {
+      double2 A = v[0], B = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int t = 1; t <= h; ++t) {
+        const int m = (k * t) % R;
+        const double c = rcos(R, m <= h ? m : R - m);
+        const double sn = m <= h ? rsin(R, m) : -rsin(R, R - m);
+        A.x += c * sp[t - 1].x;
+        A.y += c * sp[t - 1].y;
+        B.x += sn * sm[t - 1].x;
+        B.y += sn * sm[t - 1].y;
+      }
+      out[k] = make_double2(A.x + B.y, A.y - B.x);      // A - i B
+      out[R - k] = make_double2(A.x - B.y, A.y + B.x);  // A + i B
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = out[k];
+  }
+}
+
+__device__ __forceinline__ double2 fft_twiddle(const double2* tab, int n, int m) {
+  const double2* t2 = tab + 64;
+  return c_mul(t2[m >> 6], tab[m & 63]);
+}
+
+// One self-sorting pass of radix R over every line of axis `ax` (Wc complex
+// columns interleaved, layout [outer][i][inner][column]).  Ns = product of
+// the radices already applied on this axis.
+template <int R>
+__device__ void fft_pass(double2* buf, int Wc, const FftAxis& ax, int Ns, const double2* tab) {
+  constexpr int PT = kFftPoints / kFftThreads;  // points per thread (Wc * n * S * O <= kFftPoints)
+  constexpr int NB = (PT + R - 1) / R;           // butterflies per thread
+  const int n = ax.n, nq = n / R, S = ax.S;
+  const int stride = S * Wc;
+  const int count = Wc * S * nq * ax.O;
+  const int tstep = n / (Ns * R);
+  double2 v[NB][R];
+  int dst[NB], tws[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int b = (int)threadIdx.x + kFftThreads * u;
+    if (b < count) {
+      const int c = b % Wc;
+      int r = b / Wc;
+      const int ii = r % S;
+      r /= S;
+      const int j = r % nq, o = r / nq;
+      const int base = (o * n * S + ii) * Wc + c;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[u][t] = buf[base + (j + t * nq) * stride];
+      const int k = j % Ns;
+      dst[u] = base + ((j - k) * R + k) * stride;
+      tws[u] = k * tstep;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int b = (int)threadIdx.x + kFftThreads * u;
+    if (b < count) {
+      if (Ns > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) v[u][t] = c_mul(v[u][t], fft_twiddle(tab, n, tws[u] * t));
+      }
+      dft_small<R>(v[u]);
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[dst[u] + t * Ns * stride] = v[u][t];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ inline void fft_axis(double2* buf, int Wc, const FftAxis& ax, const double2* tabs) {
+  // the radices come sorted (8s, 4s, 2s, 3s, 5s, 7s): one loop per radix
+  const double2* tab = tabs + ax.tw_off;
+  int Ns = 1, p = 0;
+  for (; p < ax.npass && ax.rad[p] == 8; ++p, Ns *= 8) fft_pass<8>(buf, Wc, ax, Ns, tab);
+  for (; p < ax.npass && ax.rad[p] == 4; ++p, Ns *= 4) fft_pass<4>(buf, Wc, ax, Ns, tab);
+  for (; p < ax.npass && ax.rad[p] == 2; ++p, Ns *= 2) fft_pass<2>(buf, Wc, ax, Ns, tab);
+  for (; p < ax.npass && ax.rad[p] == 3; ++p, Ns *= 3) fft_pass<3>(buf, Wc, ax, Ns, tab);
+  for (; p < ax.npass && ax.rad[p] == 5; ++p, Ns *= 5) fft_pass<5>(buf, Wc, ax, Ns, tab);
+  for (; p < ax.npass && ax.rad[p] == 7; ++p, Ns *= 7) fft_pass<7>(buf, Wc, ax, Ns, tab);
+}
+
+// chirp c(k) = exp(-i pi k^2 / L) from the exact residue k^2 mod 2L
+__device__ __forceinline__ double2 chirp(int k, int L) {
+  const int r = (int)(((int64_t)k * k) % (2 * (int64_t)L));
+  double s, c;
+  sincospi((double)r / (double)L, &s, &c);
+  return make_double2(c, -s);
+}
+
+// lattice point -k (every axis negated modulo its extent)
+__device__ __forceinline__ int neg_point(int k, const int* L) {
+  const int k3 = k % L[2], r = k / L[2];
+  const int k2 = r % L[1], k1 = r / L[1];
+  const int n1 = k1 ? L[0] - k1 : 0, n2 = k2 ? L[1] - k2 : 0, n3 = k3 ? L[2] - k3 : 0;
+  return (n1 * L[1] + n2) * L[2] + n3;
+}
+
+// One workgroup: real columns [group*W, group*W + W) of the batch.
+template <bool BLUE>
+__device__ void fft_block_body(const FftArgs& a, int64_t group, double* smem) {
+  const int tid = (int)threadIdx.x;
+  const int W = a.W, Wc = W >> 1, P = a.P, nbuf = a.nbuf;
+  double2* buf = (double2*)smem;
+  double2* tabs = (double2*)(smem + (size_t)W * nbuf);
+  constexpr int NW = kFftThreads / 64;
+  double* red = smem + (size_t)W * nbuf + 2 * (size_t)a.tw_total;  // [NW][W] wave maxima
+  double* scl = red + NW * W;                                      // [W] column exponents
+  // twiddle tables of every axis: T1[i] = w^i (i < 64), T2[i] = w^(64 i)
+  for (int idx = tid; idx < a.tw_total; idx += kFftThreads) {
+    int d = 0;
+    while (d + 1 < a.naxes && idx >= a.ax[d + 1].tw_off) ++d;
+    const int n = a.ax[d].n, i = idx - a.ax[d].tw_off;
+    const int e = i < 64 ? i % n : (int)(((int64_t)64 * (i - 64)) % n);
+    double s, c;
+    sincospi(-2.0 * (double)e / (double)n, &s, &c);
+    tabs[idx] = make_double2(c, s);
+  }
+  __syncthreads();
+  // Bluestein: transform of the chirp filter b(m) = conj c(m), b(M-m) = b(m),
+  // held in registers by the threads that multiply by it (m = tid + kFftThreads u)
+  constexpr int NBH = BLUE ? kFftPoints / kFftThreads : 1;
+  double2 bh[NBH];
+  if (BLUE) {
+    const int M = a.ax[0].n, L = a.blue_L;
+    for (int m = tid; m < M; m += kFftThreads) {
+      double2 v = make_double2(0.0, 0.0);
+      if (m < L) v = chirp(m, L);
+      else if (M - m < L) v = chirp(M - m, L);
+      buf[m] = make_double2(v.x, -v.y);
+    }
+    __syncthreads();
+    fft_axis(buf, 1, a.ax[0], tabs);
+    const double invM = 1.0 / (double)M;
+#pragma unroll
+    for (int u = 0; u < NBH; ++u) {
+      const int m = tid + kFftThreads * u;
+      bh[u] = m < M ? make_double2(buf[m].x * invM, buf[m].y * invM) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+  }
+  // load W real columns (coalesced rows of W entries), track column maxima
+  const int64_t q0 = group * W;
+  const int nq = (int)(a.cols - q0 < W ? a.cols - q0 : W);
+  const int myq = tid % W;  // W divides the thread count: the thread keeps its column
+  const bool has = myq < nq;
+  const int64_t qg = q0 + myq;
+  const int64_t bq = has ? qg / a.E : 0, eq = has ? qg % a.E : 0;
+  const double* src = a.in + bq * P * a.E + eq;
+  double mx = 0.0;
+  for (int k = tid / W; k < P; k += kFftThreads / W) {
+    const double x = has ? src[(int64_t)k * a.E] : 0.0;
+    smem[(size_t)k * W + myq] = x;
+    mx = fmax(mx, fabs(x));
+  }
+  for (int off = W; off < 64; off <<= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((tid & 63) < W) red[(tid >> 6) * W + myq] = mx;
+  __syncthreads();
+  if (tid < W) {
+    double m = red[tid];
+    for (int w = 1; w < NW; ++w) m = fmax(m, red[w * W + tid]);
+    int ex = 0;
+    if (m > 0.0) frexp(m, &ex);
+    scl[tid] = (double)ex;
+  }
+  __syncthreads();
+  // scale to unit maximum (and chirp, zero padding for Bluestein)
+  if (BLUE) {
+    const int M = a.ax[0].n, L = a.blue_L;
+    for (int idx = tid; idx < Wc * M; idx += kFftThreads) {
+      const int m = idx / Wc, c = idx % Wc;
+      double2 z = make_double2(0.0, 0.0);
+      if (m < L) {
+        const double2 x = buf[idx];
+        z = c_mul(make_double2(ldexp(x.x, -(int)scl[2 * c]), ldexp(x.y, -(int)scl[2 * c + 1])),
+                  chirp(m, L));
+      }
+      buf[idx] = z;
+    }
+  } else {
+    for (int idx = tid; idx < Wc * P; idx += kFftThreads) {
+      const int c = idx % Wc;
+      const double2 x = buf[idx];
+      buf[idx] = make_double2(ldexp(x.x, -(int)scl[2 * c]), ldexp(x.y, -(int)scl[2 * c + 1]));
+    }
+  }
+  __syncthreads();
+  if (BLUE) {
+    const int M = a.ax[0].n, L = a.blue_L;
+    fft_axis(buf, Wc, a.ax[0], tabs);
+#pragma unroll
+    for (int u = 0; u < NBH; ++u) {
+      const int m = tid + kFftThreads * u;
+      if (m < M)
+        for (int c = 0; c < Wc; ++c) {
+          const double2 z = c_mul(buf[m * Wc + c], bh[u]);
+          buf[m * Wc + c] = make_double2(z.x, -z.y);
+        }
+    }
+    __syncthreads();
+    fft_axis(buf, Wc, a.ax[0], tabs);
+    for (int idx = tid; idx < Wc * L; idx += kFftThreads) {
+      const double2 z = buf[idx];
+      buf[idx] = c_mul(make_double2(z.x, -z.y), chirp(idx / Wc, L));
+    }
+    __syncthreads();
+  } else {
+    for (int d = 0; d < a.naxes; ++d) fft_axis(buf, Wc, a.ax[d], tabs);
+  }
+  // split the packed columns, undo the scaling, store rows of W entries
+  double* dst = a.out + 2 * (bq * P * a.E + eq);
+  const int sh = has ? (int)scl[myq] : 0;
+  const int c = myq >> 1;
+  for (int k = tid / W; k < P; k += kFftThreads / W) {
+    if (!has) continue;
+    const double2 z = buf[k * Wc + c];
+    const double2 y = buf[neg_point(k, a.L) * Wc + c];
+    double xr, xi;
+    if (myq & 1) {
+      xr = 0.5 * (z.y + y.y);
+      xi = 0.5 * (y.x - z.x);
+    } else {
+      xr = 0.5 * (z.x + y.x);
+      xi = 0.5 * (z.y - y.y);
+    }
+    double2* o = (double2*)(dst + 2 * (int64_t)k * a.E);
+    *o = make_double2(ldexp(xr, sh), ldexp(xi, sh));
+  }
 }
 
 }  // namespace dev

@@ -1,20 +1,31 @@
 // Step a6: Fourier block-diagonalisation of a 3-level block-circulant matrix.
 //   Abar_j = sum_k w1^(j1 k1) w2^(j2 k2) w3^(j3 k3) A_k,  w_l = exp(-2 pi i / L_l)
 // (Lemma 2.2, eq. (DiagMLcirc); Appendix, Proposition on block-circulant
-// diagonalisation).  F_L = F_L1 x F_L2 x F_L3 is applied one lattice axis at
-// a time; each pass is a batched 1D DFT along that axis for every entry of
-// every m0 x m0 block.  Twiddles use the exact residue (j k mod L), so the
-// phase is never formed from a large angle.
+// diagonalisation), at the O(m0^2 L^d log L) cost of Sec. 4.2.
+// F_L = F_L1 x F_L2 x F_L3 is applied to every entry of every m0 x m0 block.
+// Lattices whose buffer fits a workgroup's LDS (every extent 7-smooth and
+// L1 L2 L3 <= 4096, or one axis of any length up to 2048 by Bluestein) take
+// the LDS FFT: one launch, each workgroup a set of entry columns over the
+// whole lattice, no workspace.  Longer lines fall back to a direct DFT along
+// one axis at a time (twiddles from the exact residue j k mod L).
 #include <algorithm>
+#include <cstring>
 
 #include "common.h"
 #include "dev_fft.h"
+#include "host_plans.h"
 
 namespace tl {
 namespace {
 
 using dev::DftArgs;
 constexpr int kMaxTwiddle = dev::kMaxTwiddle;
+
+template <bool BLUE>
+__global__ __launch_bounds__(dev::kFftThreads) void fft_block_kernel(dev::FftArgs a) {
+  extern __shared__ __align__(16) double smem[];
+  dev::fft_block_body<BLUE>(a, blockIdx.x, smem);
+}
 
 template <bool REAL_IN, bool TABLE>
 __global__ __launch_bounds__(256) void dft_axis_kernel(DftArgs a) {
@@ -38,17 +49,123 @@ tl_status launch_axis(const DftArgs& a, int64_t outer, hipStream_t stream) {
   return TL_OK;
 }
 
+bool smooth7(int n) {
+  for (int p : {2, 3, 5, 7})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+bool factor_axis(int n, dev::FftAxis* ax) {
+  ax->n = n;
+  ax->npass = 0;
+  int r = n;
+  auto push = [&](int R) {
+    if (ax->npass >= dev::kFftMaxPasses) return false;
+    ax->rad[ax->npass++] = (unsigned char)R;
+    r /= R;
+    return true;
+  };
+  while (r % 8 == 0)
+    if (!push(8)) return false;
+  while (r % 4 == 0)
+    if (!push(4)) return false;
+  while (r % 2 == 0)
+    if (!push(2)) return false;
+  for (int R : {3, 5, 7})
+    while (r % R == 0)
+      if (!push(R)) return false;
+  return r == 1;
+}
+
 }  // namespace
+
+bool plan_fft(const double* in, double* out, const int L[3], int m0, int64_t batch,
+              dev::FftArgs* a) {
+  std::memset(a, 0, sizeof(*a));
+  a->in = in;
+  a->out = out;
+  a->E = (int64_t)m0 * m0;
+  a->cols = batch * a->E;
+  a->P = 1;
+  for (int d = 0; d < 3; ++d) {
+    a->L[d] = L[d];
+    a->P *= L[d];
+  }
+  if (a->P > dev::kFftPoints) return false;
+  int axes[3], na = 0;
+  for (int d = 0; d < 3; ++d)
+    if (L[d] > 1) axes[na++] = d;
+  a->naxes = na;
+  if (na == 1 && !smooth7(L[axes[0]])) {
+    int M = 2 * L[axes[0]] - 1;
+    while (!smooth7(M)) ++M;
+    if (M > dev::kFftPoints) return false;
+    a->blue = 1;
+    a->blue_L = L[axes[0]];
+    a->nbuf = M;
+    dev::FftAxis& ax = a->ax[0];
+    if (!factor_axis(M, &ax)) return false;
+    ax.S = 1;
+    ax.O = 1;
+  } else {
+    a->nbuf = a->P;
+    for (int i = 0; i < na; ++i) {
+      const int d = axes[i];
+      dev::FftAxis& ax = a->ax[i];
+      if (!factor_axis(L[d], &ax)) return false;
+      ax.S = 1;
+      for (int e = d + 1; e < 3; ++e) ax.S *= L[e];
+      ax.O = 1;
+      for (int e = 0; e < d; ++e) ax.O *= L[e];
+    }
+  }
+  int tw = 0;
+  for (int i = 0; i < (a->blue ? 1 : na); ++i) {
+    a->ax[i].tw_off = tw;
+    tw += 64 + (int)ceil_div(a->ax[i].n, 64);
+  }
+  a->tw_total = tw;
+  int W = 2 * (dev::kFftPoints / a->nbuf);
+  int w2 = 2;
+  while (2 * w2 <= W && 2 * w2 <= 16) w2 *= 2;
+  a->W = w2;
+  return true;
+}
+
+tl_status launch_fft(const dev::FftArgs& a, hipStream_t stream) {
+  const dim3 grid((unsigned)ceil_div(a.cols, a.W)), blk(dev::kFftThreads);
+  const size_t shmem = dev::fft_lds_bytes(a);
+  if (a.blue)
+    hipLaunchKernelGGL(fft_block_kernel<true>, grid, blk, shmem, stream, a);
+  else
+    hipLaunchKernelGGL(fft_block_kernel<false>, grid, blk, shmem, stream, a);
+  TL_CHECK_LAUNCH();
+  return TL_OK;
+}
+
+size_t block_fft_workspace(int L1, int L2, int L3, int m0, int batch) {
+  const int L[3] = {L1, L2, L3};
+  dev::FftArgs a;
+  if (plan_fft(nullptr, nullptr, L, m0, batch, &a)) return 0;
+  const int na = (L1 > 1) + (L2 > 1) + (L3 > 1);
+  const int64_t total = (int64_t)batch * L1 * L2 * L3 * m0 * m0;
+  return na >= 2 ? align_up(sizeof(double) * 2 * (size_t)total, 256) : 0;
+}
 
 tl_status block_fft(const double* in, int L1, int L2, int L3, int m0, int batch, double* out,
                     void* ws, size_t ws_bytes, hipStream_t stream) {
   const int L[3] = {L1, L2, L3};
+  {
+    dev::FftArgs fa;
+    if (plan_fft(in, out, L, m0, batch, &fa)) return launch_fft(fa, stream);
+  }
+  // lines longer than the LDS FFT holds: direct DFT, one axis per launch
   const int64_t E = (int64_t)m0 * m0;
   const int64_t total = (int64_t)batch * L1 * L2 * L3 * E;
   int axes[3], na = 0;
   for (int d = 0; d < 3; ++d)
     if (L[d] > 1) axes[na++] = d;
-  size_t need = na >= 2 ? align_up(sizeof(double) * 2 * (size_t)total, 256) : 0;
+  size_t need = block_fft_workspace(L1, L2, L3, m0, batch);
   if (ws_bytes < need || (need && !ws)) {
     set_error("block_fft workspace: need %zu bytes, got %zu", need, ws_bytes);
     return TL_EWORKSPACE;
@@ -83,9 +200,8 @@ extern "C" tl_status tl_block_fft_workspace_bytes(int L1, int L2, int L3, int m0
   tl::clear_error();
   TL_REQUIRE(bytes != nullptr, "null output");
   TL_REQUIRE(L1 >= 1 && L2 >= 1 && L3 >= 1 && m0 >= 1 && batch >= 1, "invalid sizes");
-  int na = (L1 > 1) + (L2 > 1) + (L3 > 1);
-  int64_t total = (int64_t)batch * L1 * L2 * L3 * m0 * m0;
-  *bytes = na >= 2 ? tl::align_up(sizeof(double) * 2 * (size_t)total, 256) : 0;
+  TL_REQUIRE((int64_t)L1 * L2 * L3 <= (1 << 22), "lattice too large");
+  *bytes = tl::block_fft_workspace(L1, L2, L3, m0, batch);
   return TL_OK;
 }
 

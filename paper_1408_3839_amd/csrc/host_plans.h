@@ -58,6 +58,11 @@ void make_basis_args(const Geometry& g, const tl_system* s, dev::BasisArgs* p);
 tl_status build_basis(const Geometry& g, const tl_system* s, double* G, double* AG, double* SG,
                       hipStream_t stream);
 
+// Block FFT over the lattice index in LDS (one launch, no workspace); false
+// when the lattice does not fit a workgroup's buffer.
+bool plan_fft(const double* in, double* out, const int L[3], int m0, int64_t batch,
+              dev::FftArgs* a);
+
 size_t box_workspace_bytes(const Geometry& g);
 tl_status assemble_box(const Geometry& g, const tl_system* s, const double* G, const double* AG,
                        const double* SG, const double* P, tl_precision prec, double* H,

@@ -84,7 +84,9 @@ def test_null_outputs_and_small_workspaces_rejected():
     _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EINVAL, s, 8, 8, 8, 8, 7, 0, 8, 8,
             0, 0, 0)
     _expect(tl.tl_block_fft, tl.TL_EINVAL, 8, 0, 1, 1, 4, 1, 8, 0, 0, 0)
-    _expect(tl.tl_block_fft, tl.TL_EWORKSPACE, 8, 4, 4, 1, 4, 1, 8, 0, 0, 0)
+    # lattices the LDS FFT cannot hold (a non-7-smooth extent on one of several
+    # axes) take the per-axis direct DFT, which needs a workspace
+    _expect(tl.tl_block_fft, tl.TL_EWORKSPACE, 8, 11, 3, 1, 4, 1, 8, 0, 0, 0)
     _expect(tl.tl_batched_heigh, tl.TL_EINVAL, 8, 0, 4, 0, 8, 0, 8, 0)
     _expect(tl.tl_batched_heigh, tl.TL_EINVAL, 8, 0, 4, 33, 8, 0, 8, 0)
     _expect(tl.tl_batched_heigh, tl.TL_EINVAL, 0, 0, 4, 4, 8, 0, 8, 0)
@@ -96,8 +98,14 @@ def test_workspace_queries():
         s = wl.config(cid)
         assert tl.tl_potential_workspace_bytes(s) == 0
         assert tl.tl_assemble_workspace_bytes(s) % 256 == 0
+    # whole lattices in LDS: chains up to L = 2048 (any length), 7-smooth
+    # lattices of up to 4096 cells
     assert tl.tl_block_fft_workspace_bytes(64, 1, 1, 8, 2) == 0
-    assert tl.tl_block_fft_workspace_bytes(8, 8, 8, 10, 2) == 8 * 2 * 512 * 100 * 2
+    assert tl.tl_block_fft_workspace_bytes(8, 8, 8, 10, 2) == 0
+    assert tl.tl_block_fft_workspace_bytes(2039, 1, 1, 4, 2) == 0
+    assert tl.tl_block_fft_workspace_bytes(4099, 1, 1, 4, 2) == 0      # one axis: no workspace
+    assert tl.tl_block_fft_workspace_bytes(11, 3, 1, 4, 2) == 8 * 2 * 33 * 16 * 2
+    assert tl.tl_block_fft_workspace_bytes(16, 16, 32, 2, 1) == 8 * 2 * 8192 * 4
 
 
 def test_box_mode_queries_and_rejections():
