@@ -283,6 +283,81 @@ def batch_section(steps: int, warmup: int):
     return out
 
 
+def fft_bytes(systems) -> float:
+    """Algorithmic HBM bytes of the block FFT of H and S: every real entry of
+    the block columns read once (8 B) and every complex k-block entry written
+    once (16 B)."""
+    return float(sum(2 * s.m0 * s.m0 * int(np.prod(s.L)) * (8 + 16) for s in systems))
+
+
+def lattice_sum_bytes(systems):
+    """(algorithmic, written) HBM bytes of the lattice-summed potential
+    vectors: per dimension 8 T (n~ + n) on a torus (the master vector on the
+    accompanying grid n~ = n + 256 read once, the replicated vector written
+    once) and 8 T n in an open dimension (written once); the kernel forms the
+    master entries where it sums them, so it only writes 8 T n per dim."""
+    from paper_1408_3839_amd import tl
+    alg = wr = 0.0
+    for s in systems:
+        T = tl.tl_query_sizes(s)["pot_terms"]
+        for d in range(3):
+            n = int(s.n[d])
+            wr += 8.0 * T * n
+            alg += 8.0 * T * ((n + 256) + n if s.periodic[d] else n)
+    return alg, wr
+
+
+def stage_section(replicas=(1, 8), reps: int = 5):
+    """Lattice sum (a3) and block FFT (a6) of the ragged batch against HBM:
+    each stage's kernel timed with HIP events attached to its launch, on the
+    64-instance batch and on the batch replicated so that its arrays exceed
+    the 256 MB last-level cache."""
+    import torch
+    from paper_1408_3839_amd import tl, workloads
+    from paper_1408_3839_amd.pipeline import BatchPipeline
+
+    base = workloads.batch(64)
+    out = {}
+    for rep in replicas:
+        systems = base * rep
+        bp = BatchPipeline(systems)
+        for _ in range(2):
+            bp.run()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        times = {}
+        for name, stage in (("fft", tl.TL_STAGE_FFT), ("lattice_sum", tl.TL_STAGE_LATTICE_SUM)):
+            ms = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                b.record(stream)
+                tl.tl_set_stage_events(stage, a.cuda_event, b.cuda_event)
+                bp.run()
+                tl.tl_set_stage_events(stage, None, None)
+                torch.cuda.synchronize()
+                ms.append(a.elapsed_time(b))
+            times[name] = float(np.median(ms))
+        fb = fft_bytes(systems)
+        alg, wr = lattice_sum_bytes(systems)
+        out[f"x{rep}"] = {
+            "instances": len(systems),
+            "fft": {"bound": "hbm", "kernel": "batch_fft_kernel", "avg_kernel_ms": times["fft"],
+                    "algorithmic_bytes": fb,
+                    "achieved": fb / (times["fft"] * 1e-3) / 1e9, "peak": 8000.0,
+                    "unit": "GB/s", "frac": fb / (times["fft"] * 1e-3) / 8e12},
+            "lattice_sum": {"bound": "hbm", "kernel": "batch_potential_kernel",
+                            "avg_kernel_ms": times["lattice_sum"], "algorithmic_bytes": alg,
+                            "written_bytes": wr,
+                            "achieved": alg / (times["lattice_sum"] * 1e-3) / 1e9,
+                            "peak": 8000.0, "unit": "GB/s",
+                            "frac": alg / (times["lattice_sum"] * 1e-3) / 8e12},
+        }
+        del bp
+        torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +374,10 @@ def main():
                          "HBM byte counters) and exit")
     ap.add_argument("--no-box", action="store_true", help="skip the open-chain section")
     ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch section")
+    ap.add_argument("--no-stages", action="store_true",
+                    help="skip the lattice-sum / FFT HBM section")
+    ap.add_argument("--stages-only", action="store_true",
+                    help="print only the lattice-sum / FFT HBM section")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -315,6 +394,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes_read": 8 * n, "calibration_copy_bytes_written": 8 * n}))
+        return
+
+    if args.stages_only:
+        print(json.dumps({"stage_rooflines": stage_section()}))
         return
 
     from paper_1408_3839_amd import workloads
@@ -417,6 +500,8 @@ def main():
         out["box_chain"] = box_chain_section(min(args.steps, 5), 1)
     if not args.no_batch:
         out["batch"] = batch_section(min(args.steps, 10), 2)
+    if not args.no_stages:
+        out["stage_rooflines"] = stage_section()
     print(json.dumps(out))
 
 

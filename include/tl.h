@@ -232,6 +232,23 @@ tl_status tl_assemble_core_hamiltonian_block_noalloc(const tl_system* sys, const
 tl_status tl_set_contraction_events(void* start_event, void* stop_event);
 
 /*
+ * tl_set_stage_events - the same profiling hook for one stage of the path:
+ *   TL_STAGE_CONTRACTION  the 1D-contraction launch (as above),
+ *   TL_STAGE_LATTICE_SUM  the lattice-sum launch of tl_lattice_sum_potential
+ *                         (torus and open transverse dims) and of the batch,
+ *   TL_STAGE_FFT          the LDS block-FFT launch of tl_block_fft and of the
+ *                         batch.
+ * Events are per calling thread and stay owned by the caller; NULL, NULL
+ * switches the stage's hook off.  TL_EINVAL for an unknown stage or a
+ * single null event.
+ */
+#define TL_STAGE_CONTRACTION 0
+#define TL_STAGE_LATTICE_SUM 1
+#define TL_STAGE_FFT 2
+#define TL_STAGE_COUNT 3
+tl_status tl_set_stage_events(int stage, void* start_event, void* stop_event);
+
+/*
  * tl_block_fft - Fourier block-diagonalisation of 3-level block-circulant
  * matrices (Lemma 2.2 eq. (DiagMLcirc); Appendix, Proposition on
  * block-circulant diagonalisation):
@@ -322,7 +339,7 @@ tl_status tl_dense_gen_eigh_lowest(const double* H_dev, const double* S_dev, int
  * Same arithmetic per instance as the single-system calls (bitwise equal
  * for equal want_blocks).
  */
-#define TL_MAX_BATCH 256
+#define TL_MAX_BATCH 512
 typedef struct {
   int count, precision, n_slices, want_blocks;
   int max_m0, max_len;

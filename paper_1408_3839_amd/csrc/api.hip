@@ -19,6 +19,15 @@ void set_error(const char* fmt, ...) {
 }
 void clear_error() { g_err[0] = 0; }
 
+// Profiling hook: caller events attached to one stage's kernel launch.
+static thread_local hipEvent_t g_stage_ev[TL_STAGE_COUNT][2] = {};
+
+void stage_events(int stage, hipEvent_t* start, hipEvent_t* stop) {
+  hipEvent_t a = g_stage_ev[stage][0], b = g_stage_ev[stage][1];
+  *start = a && b ? a : nullptr;
+  *stop = a && b ? b : nullptr;
+}
+
 static bool is_int_multiple(double v, double h) {
   double q = v / h;
   return std::fabs(q - std::round(q)) < 1e-9 * std::fmax(1.0, std::fabs(q));
@@ -134,6 +143,17 @@ const char* tl_status_string(tl_status s) {
 }
 
 const char* tl_last_error(void) { return tl::g_err; }
+
+tl_status tl_set_stage_events(int stage, void* start_event, void* stop_event) {
+  tl::clear_error();
+  TL_REQUIRE(stage >= 0 && stage < TL_STAGE_COUNT, "stage %d outside [0, %d)", stage,
+             TL_STAGE_COUNT);
+  TL_REQUIRE((start_event == nullptr) == (stop_event == nullptr),
+             "give both events or neither");
+  tl::g_stage_ev[stage][0] = (hipEvent_t)start_event;
+  tl::g_stage_ev[stage][1] = (hipEvent_t)stop_event;
+  return TL_OK;
+}
 
 tl_status tl_query_sizes(const tl_system* sys, tl_sizes* out) {
   tl::clear_error();

@@ -59,13 +59,8 @@ __global__ __launch_bounds__(256) void combine_periodic_kernel(CombineArgs a, in
 
 }  // namespace
 
-// Optional HIP events recorded around the contraction launch of the next
-// assembly calls of this thread (profiling hook for measured rooflines).
-thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
-
 void contraction_events(hipEvent_t* start, hipEvent_t* stop) {
-  *start = g_ev_start;
-  *stop = g_ev_stop;
+  stage_events(TL_STAGE_CONTRACTION, start, stop);
 }
 
 namespace {
@@ -407,8 +402,8 @@ tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream) {
     TL_CHECK_LAUNCH();
   }
   // the profiling events (if set) are attached to the contraction launch
-  const hipEvent_t e0 = g_ev_start && g_ev_stop ? g_ev_start : nullptr;
-  const hipEvent_t e1 = e0 ? g_ev_stop : nullptr;
+  hipEvent_t e0, e1;
+  contraction_events(&e0, &e1);
   const dim3 cgrid((unsigned)ap.contract_blocks), cblk(256);
   if (ap.prec == TL_SPLIT_BF16)
     launch_split_contraction<__bf16>(ap, stream, e0, e1);
@@ -446,12 +441,7 @@ tl_status assemble_periodic(const Geometry& g, const double* G, const double* AG
 }  // namespace tl
 
 extern "C" tl_status tl_set_contraction_events(void* start_event, void* stop_event) {
-  tl::clear_error();
-  TL_REQUIRE((start_event == nullptr) == (stop_event == nullptr),
-             "give both events or neither");
-  tl::g_ev_start = (hipEvent_t)start_event;
-  tl::g_ev_stop = (hipEvent_t)stop_event;
-  return TL_OK;
+  return tl_set_stage_events(TL_STAGE_CONTRACTION, start_event, stop_event);
 }
 
 extern "C" tl_status tl_assemble_workspace_bytes(const tl_system* sys, tl_precision prec,

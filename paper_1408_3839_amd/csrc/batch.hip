@@ -23,6 +23,7 @@ enum Stage {
   kContract,
   kReduce,
   kCombine,
+  kFftTables,
   kDft,
   kHeigh,
   kStages
@@ -120,6 +121,14 @@ __global__ __launch_bounds__(256) void batch_combine_kernel(const BatchDesc* __r
   dev::combine_periodic_body(J.asmb.combine, J.asmb.combine_total, lb);
 }
 
+__global__ __launch_bounds__(dev::kFftThreads) void batch_fft_tables_kernel(
+    const BatchDesc* __restrict__ d) {
+  extern __shared__ __align__(16) double smem[];
+  TL_BATCH_LOCATE(kFftTables)
+  (void)lb;
+  dev::fft_blue_tables_body(J.fft, smem);
+}
+
 __global__ __launch_bounds__(dev::kFftThreads) void batch_fft_kernel(
     const BatchDesc* __restrict__ d) {
   extern __shared__ __align__(16) double smem[];
@@ -139,7 +148,7 @@ __global__ __launch_bounds__(MAXM * MAXM < 64 ? 64 : MAXM * MAXM) void batch_hei
 
 struct InstanceSizes {
   Geometry g;
-  size_t pot_ws, asm_ws;
+  size_t pot_ws, asm_ws, fft_ws;
 };
 
 tl_status instance_sizes(const tl_system* s, tl_precision prec, int n_slices, int want,
@@ -174,6 +183,7 @@ tl_status instance_sizes(const tl_system* s, tl_precision prec, int n_slices, in
       set_error("the batched path takes L <= 2048, or 7-smooth L <= 4096 (L = %d)", g.L[0]);
       return TL_EUNSUPPORTED;
     }
+    out->fft_ws = fft_blue_table_bytes(fa);
   }
   out->pot_ws = align_up(potential_workspace_bytes(g, s), 256);
   out->asm_ws = align_up(assemble_workspace_bytes(g, prec, n_slices, want), 256);
@@ -217,7 +227,7 @@ extern "C" tl_status tl_batch_plan_create(const tl_system* systems, int count, t
     out->hs_elems += 2 * g.block_elems;
     out->eval_elems += (int64_t)g.L[0] * g.m0;
     out->kblocks += g.L[0];
-    out->ws_bytes += is.pot_ws + is.asm_ws;
+    out->ws_bytes += is.pot_ws + is.asm_ws + is.fft_ws;
     out->max_m0 = std::max(out->max_m0, g.m0);
     out->max_len = std::max(out->max_len, g.L[0]);
   }
@@ -268,6 +278,7 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
       set_error("instance %d: no LDS FFT plan for L = %d", i, g.L[0]);
       return TL_EUNSUPPORTED;
     }
+    set_fft_blue_tables(&J.fft, ws + is.pot_ws + is.asm_ws);
     J.Hb = Hbar;
     J.Sb = Hbar + 2 * g.block_elems;
     J.evals = buf->evals + oev;
@@ -281,6 +292,7 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
     blocks[kContract] = J.asmb.contract_blocks;
     blocks[kReduce] = ceil_div(J.asmb.reduce_total, 256);
     blocks[kCombine] = ceil_div(J.asmb.combine_total, 4);
+    blocks[kFftTables] = J.fft.blue ? 1 : 0;
     blocks[kDft] = ceil_div(J.fft.cols, J.fft.W);
     blocks[kHeigh] = g.L[0];
     for (int st = 0; st < kStages; ++st) d->prefix[st][i + 1] = d->prefix[st][i] + blocks[st];
@@ -289,7 +301,7 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
     ohs += 2 * g.block_elems;
     oev += (int64_t)g.L[0] * g.m0;
     okb += g.L[0];
-    ows += is.pot_ws + is.asm_ws;
+    ows += is.pot_ws + is.asm_ws + is.fft_ws;
   }
   std::memcpy(host_desc, d, sizeof(BatchDesc));
   return TL_OK;
@@ -330,7 +342,10 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
   hipLaunchKernelGGL(batch_basis_kernel, dim3(blocks(kBasis)), dim3(256), 0, stream, d);
   TL_CHECK_LAUNCH();
   if (blocks(kPotential)) {
-    hipLaunchKernelGGL(batch_potential_kernel, dim3(blocks(kPotential)), dim3(256), 0, stream, d);
+    hipEvent_t p0, p1;
+    stage_events(TL_STAGE_LATTICE_SUM, &p0, &p1);
+    launch_with_events(batch_potential_kernel, dim3(blocks(kPotential)), dim3(256), 0, stream,
+                       p0, p1, d);
     TL_CHECK_LAUNCH();
   }
   if (prec == TL_SPLIT_BF16) {
@@ -342,7 +357,7 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
     TL_CHECK_LAUNCH();
   }
   // the profiling events (if set) are attached to the contraction launch
-  const hipEvent_t e0 = ev0 && ev1 ? ev0 : nullptr, e1 = e0 ? ev1 : nullptr;
+  const hipEvent_t e0 = ev0, e1 = ev1;
   const dim3 cgrid(blocks(kContract)), cblk(256);
   if (prec == TL_SPLIT_BF16)
     launch_batch_split<__bf16>(plan->n_slices, blocks(kContract), d, stream, e0, e1);
@@ -368,10 +383,20 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
   TL_CHECK_LAUNCH();
   hipLaunchKernelGGL(batch_combine_kernel, dim3(blocks(kCombine)), dim3(256), 0, stream, d);
   TL_CHECK_LAUNCH();
-  size_t fft_lds = 0;
-  for (int i = 0; i < hd->count; ++i) fft_lds = std::max(fft_lds, dev::fft_lds_bytes(hd->job[i].fft));
-  hipLaunchKernelGGL(batch_fft_kernel, dim3(blocks(kDft)), dim3(dev::kFftThreads), fft_lds,
-                     stream, d);
+  size_t fft_lds = 0, tab_lds = 0;
+  for (int i = 0; i < hd->count; ++i) {
+    fft_lds = std::max(fft_lds, dev::fft_lds_bytes(hd->job[i].fft));
+    if (hd->job[i].fft.blue) tab_lds = std::max(tab_lds, dev::fft_tables_lds_bytes(hd->job[i].fft));
+  }
+  if (blocks(kFftTables)) {
+    hipLaunchKernelGGL(batch_fft_tables_kernel, dim3(blocks(kFftTables)), dim3(dev::kFftThreads),
+                       tab_lds, stream, d);
+    TL_CHECK_LAUNCH();
+  }
+  hipEvent_t f0, f1;
+  stage_events(TL_STAGE_FFT, &f0, &f1);
+  launch_with_events(batch_fft_kernel, dim3(blocks(kDft)), dim3(dev::kFftThreads), fft_lds,
+                     stream, f0, f1, d);
   TL_CHECK_LAUNCH();
   if (plan->max_m0 <= 8)
     hipLaunchKernelGGL(batch_heigh_kernel<8>, dim3(blocks(kHeigh)), dim3(64), 0, stream, d);

@@ -16,6 +16,8 @@ namespace tl {
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
 void clear_error();
+// events of the profiling hook for `stage` (TL_STAGE_*); both null when unset
+void stage_events(int stage, hipEvent_t* start, hipEvent_t* stop);
 
 #define TL_REQUIRE(cond, ...)            \
   do {                                   \

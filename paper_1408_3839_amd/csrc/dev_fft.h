@@ -107,8 +107,8 @@ __device__ inline void dft_axis_body(const DftArgs& a, int64_t oj, int64_t by, d
 //   * A single axis of another length L uses Bluestein's chirp-z form:
 //     w_L^(jk) = c(j) c(k) conj c(j-k), c(k) = exp(-i pi k^2/L), a cyclic
 //     convolution of length M >= 2L-1 (M 7-smooth) done by two forward FFTs
-//     of length M (the inverse as conj FFT conj) with the transform of the
-//     chirp filter formed once per workgroup.
+//     of length M (the inverse as conj FFT conj); the chirp and the transform
+//     of the chirp filter are tabulated once per length by a small kernel.
 // Twiddles w_n^m = T2[m >> 6] T1[m & 63] from two small LDS tables per axis.
 constexpr int kFftPoints = 4096;  // complex points of a workgroup's buffer (64 KB)
 constexpr int kFftThreads = 512;  // threads per workgroup (8 waves)
@@ -130,15 +130,20 @@ struct FftArgs {
   int64_t cols;      // real columns: batch * E
   int L[3];          // lattice extents (1 for absent axes)
   int P;             // L[0] L[1] L[2]
-  int W;             // real columns per workgroup (2..16, a power of two)
+  int W;             // real columns per workgroup (2..64, a power of two)
   int naxes;
   FftAxis ax[3];
   int blue;          // 1: one axis of length blue_L by Bluestein, ax[0].n = M
   int blue_L;
   int nbuf;          // buffer points per line: P, or M
   int tw_total;      // complex table entries of all axes
+  double2* chirp;    // Bluestein: c(k), k < blue_L (device, written by the tables kernel)
+  double2* bhat;     // Bluestein: transform of the chirp filter / M, M entries
 };
 
+__host__ __device__ inline size_t fft_tables_lds_bytes(const FftArgs& a) {
+  return sizeof(double) * (2 * (size_t)a.ax[0].n + 2 * (64 + ((size_t)a.ax[0].n + 63) / 64));
+}
 __host__ __device__ inline size_t fft_lds_bytes(const FftArgs& a) {
   return sizeof(double) *
          ((size_t)a.W * a.nbuf + 2 * (size_t)a.tw_total + (kFftThreads / 64 + 1) * (size_t)a.W);
@@ -245,31 +250,69 @@ __device__ __forceinline__ double2 fft_twiddle(const double2* tab, int n, int m)
 // One self-sorting pass of radix R over every line of axis `ax` (Wc complex
 // columns interleaved, layout [outer][i][inner][column]).  Ns = product of
 // the radices already applied on this axis.
+// Elementwise step folded into the first pass of an axis, applied to each
+// point (position m on its line, complex column c) as the pass reads it.
+struct PassPre {
+  int kind;            // 0: none; 1: scale each column to unit maximum;
+                       // 2: scale and multiply by the chirp c(m), zero for m >= L;
+                       // 3: multiply by the filter's transform, conjugate
+  const double* scl;   // [2 Wc] column exponents (kinds 1, 2)
+  const double2* tab;  // chirp (kind 2) or the filter's transform (kind 3), global
+  int L;               // chirp length (kind 2)
+};
+
 template <int R>
-__device__ void fft_pass(double2* buf, int Wc, const FftAxis& ax, int Ns, const double2* tab) {
+__device__ void fft_pass(double2* buf, int Wc, const FftAxis& ax, int Ns, const double2* tab,
+                         const PassPre& pre) {
   constexpr int PT = kFftPoints / kFftThreads;  // points per thread (Wc * n * S * O <= kFftPoints)
   constexpr int NB = (PT + R - 1) / R;           // butterflies per thread
   const int n = ax.n, nq = n / R, S = ax.S;
   const int stride = S * Wc;
   const int count = Wc * S * nq * ax.O;
   const int tstep = n / (Ns * R);
+  const int lw = __ffs(Wc) - 1;  // Wc is a power of two
+  const bool ns_pow2 = (Ns & (Ns - 1)) == 0;
   double2 v[NB][R];
   int dst[NB], tws[NB];
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int b = (int)threadIdx.x + kFftThreads * u;
     if (b < count) {
-      const int c = b % Wc;
-      int r = b / Wc;
-      const int ii = r % S;
-      r /= S;
-      const int j = r % nq, o = r / nq;
+      const int c = b & (Wc - 1);
+      int r = b >> lw, ii = 0, j = r, o = 0;
+      if (S > 1) {
+        ii = r % S;
+        r /= S;
+        j = r;
+      }
+      if (ax.O > 1) {
+        j = r % nq;
+        o = r / nq;
+      }
       const int base = (o * n * S + ii) * Wc + c;
 #pragma unroll
       for (int t = 0; t < R; ++t) v[u][t] = buf[base + (j + t * nq) * stride];
-      const int k = j % Ns;
+      const int k = ns_pow2 ? (j & (Ns - 1)) : j % Ns;
       dst[u] = base + ((j - k) * R + k) * stride;
       tws[u] = k * tstep;
+      if (pre.kind == 1 || pre.kind == 2) {
+        const int ea = -(int)pre.scl[2 * c], eb = -(int)pre.scl[2 * c + 1];
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[u][t] = make_double2(ldexp(v[u][t].x, ea), ldexp(v[u][t].y, eb));
+      }
+      if (pre.kind == 2) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int m = j + t * nq;
+          v[u][t] = m < pre.L ? c_mul(v[u][t], pre.tab[m]) : make_double2(0.0, 0.0);
+        }
+      } else if (pre.kind == 3) {
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const double2 z = c_mul(v[u][t], pre.tab[j + t * nq]);
+          v[u][t] = make_double2(z.x, -z.y);
+        }
+      }
     }
   }
   __syncthreads();
@@ -277,9 +320,14 @@ __device__ void fft_pass(double2* buf, int Wc, const FftAxis& ax, int Ns, const 
   for (int u = 0; u < NB; ++u) {
     const int b = (int)threadIdx.x + kFftThreads * u;
     if (b < count) {
-      if (Ns > 1) {
+      if (Ns > 1) {  // w^(k t n/(Ns R)) = (w^(k n/(Ns R)))^t: one lookup, then powers
+        const double2 w1 = fft_twiddle(tab, n, tws[u]);
+        double2 wt = w1;
 #pragma unroll
-        for (int t = 1; t < R; ++t) v[u][t] = c_mul(v[u][t], fft_twiddle(tab, n, tws[u] * t));
+        for (int t = 1; t < R; ++t) {
+          v[u][t] = c_mul(v[u][t], wt);
+          if (t + 1 < R) wt = c_mul(wt, w1);
+        }
       }
       dft_small<R>(v[u]);
 #pragma unroll
@@ -289,16 +337,19 @@ __device__ void fft_pass(double2* buf, int Wc, const FftAxis& ax, int Ns, const 
   __syncthreads();
 }
 
-__device__ inline void fft_axis(double2* buf, int Wc, const FftAxis& ax, const double2* tabs) {
-  // the radices come sorted (8s, 4s, 2s, 3s, 5s, 7s): one loop per radix
+__device__ inline void fft_axis(double2* buf, int Wc, const FftAxis& ax, const double2* tabs,
+                                const PassPre& pre) {
+  // the radices come sorted (8s, 4s, 2s, 3s, 5s, 7s): one loop per radix;
+  // `pre` goes with the first pass only
   const double2* tab = tabs + ax.tw_off;
+  const PassPre none{0, nullptr, nullptr, 0};
   int Ns = 1, p = 0;
-  for (; p < ax.npass && ax.rad[p] == 8; ++p, Ns *= 8) fft_pass<8>(buf, Wc, ax, Ns, tab);
-  for (; p < ax.npass && ax.rad[p] == 4; ++p, Ns *= 4) fft_pass<4>(buf, Wc, ax, Ns, tab);
-  for (; p < ax.npass && ax.rad[p] == 2; ++p, Ns *= 2) fft_pass<2>(buf, Wc, ax, Ns, tab);
-  for (; p < ax.npass && ax.rad[p] == 3; ++p, Ns *= 3) fft_pass<3>(buf, Wc, ax, Ns, tab);
-  for (; p < ax.npass && ax.rad[p] == 5; ++p, Ns *= 5) fft_pass<5>(buf, Wc, ax, Ns, tab);
-  for (; p < ax.npass && ax.rad[p] == 7; ++p, Ns *= 7) fft_pass<7>(buf, Wc, ax, Ns, tab);
+  for (; p < ax.npass && ax.rad[p] == 8; ++p, Ns *= 8) fft_pass<8>(buf, Wc, ax, Ns, tab, p ? none : pre);
+  for (; p < ax.npass && ax.rad[p] == 4; ++p, Ns *= 4) fft_pass<4>(buf, Wc, ax, Ns, tab, p ? none : pre);
+  for (; p < ax.npass && ax.rad[p] == 2; ++p, Ns *= 2) fft_pass<2>(buf, Wc, ax, Ns, tab, p ? none : pre);
+  for (; p < ax.npass && ax.rad[p] == 3; ++p, Ns *= 3) fft_pass<3>(buf, Wc, ax, Ns, tab, p ? none : pre);
+  for (; p < ax.npass && ax.rad[p] == 5; ++p, Ns *= 5) fft_pass<5>(buf, Wc, ax, Ns, tab, p ? none : pre);
+  for (; p < ax.npass && ax.rad[p] == 7; ++p, Ns *= 7) fft_pass<7>(buf, Wc, ax, Ns, tab, p ? none : pre);
 }
 
 // chirp c(k) = exp(-i pi k^2 / L) from the exact residue k^2 mod 2L
@@ -311,10 +362,40 @@ __device__ __forceinline__ double2 chirp(int k, int L) {
 
 // lattice point -k (every axis negated modulo its extent)
 __device__ __forceinline__ int neg_point(int k, const int* L) {
+  if (L[1] == 1 && L[2] == 1) return k ? L[0] - k : 0;
   const int k3 = k % L[2], r = k / L[2];
   const int k2 = r % L[1], k1 = r / L[1];
   const int n1 = k1 ? L[0] - k1 : 0, n2 = k2 ? L[1] - k2 : 0, n3 = k3 ? L[2] - k3 : 0;
   return (n1 * L[1] + n2) * L[2] + n3;
+}
+
+// Bluestein tables of one chain length L (one workgroup): the chirp c(k),
+// k < L, and the transform of the filter b(m) = conj c(m), b(M - m) = b(m)
+// (zero elsewhere), divided by M.  They depend on L only and are read from
+// the L2 cache by every workgroup of the transform.
+__device__ void fft_blue_tables_body(const FftArgs& a, double* smem) {
+  const int tid = (int)threadIdx.x;
+  const int M = a.ax[0].n, L = a.blue_L;
+  double2* buf = (double2*)smem;
+  double2* tabs = (double2*)(smem + 2 * (size_t)M);
+  for (int idx = tid; idx < 64 + (M + 63) / 64; idx += kFftThreads) {
+    const int e = idx < 64 ? idx % M : (int)(((int64_t)64 * (idx - 64)) % M);
+    double s, c;
+    sincospi(-2.0 * (double)e / (double)M, &s, &c);
+    tabs[idx] = make_double2(c, s);
+  }
+  for (int m = tid; m < M; m += kFftThreads) {
+    double2 v = make_double2(0.0, 0.0);
+    if (m < L) v = chirp(m, L);
+    else if (M - m < L) v = chirp(M - m, L);
+    buf[m] = make_double2(v.x, -v.y);
+    if (m < L) a.chirp[m] = v;
+  }
+  __syncthreads();
+  fft_axis(buf, 1, a.ax[0], tabs, PassPre{0, nullptr, nullptr, 0});  // tables start at 0
+  const double invM = 1.0 / (double)M;
+  for (int m = tid; m < M; m += kFftThreads)
+    a.bhat[m] = make_double2(buf[m].x * invM, buf[m].y * invM);
 }
 
 // One workgroup: real columns [group*W, group*W + W) of the batch.
@@ -327,6 +408,24 @@ __device__ void fft_block_body(const FftArgs& a, int64_t group, double* smem) {
   constexpr int NW = kFftThreads / 64;
   double* red = smem + (size_t)W * nbuf + 2 * (size_t)a.tw_total;  // [NW][W] wave maxima
   double* scl = red + NW * W;                                      // [W] column exponents
+  // load W real columns: every value of the thread in flight at once (rows
+  // of W consecutive entries per wave load, W divides the thread count so
+  // each thread keeps its column)
+  const int64_t q0 = group * W;
+  const int nq = (int)(a.cols - q0 < W ? a.cols - q0 : W);
+  const int myq = tid % W;
+  const bool has = myq < nq;
+  const int64_t qg = q0 + myq;
+  const int64_t bq = has ? qg / a.E : 0, eq = has ? qg % a.E : 0;
+  const double* src = a.in + bq * P * a.E + eq;
+  const int k0 = tid / W, kstep = kFftThreads / W;
+  constexpr int LPT = 2 * kFftPoints / kFftThreads;  // W * P <= 2 kFftPoints
+  double xv[LPT];
+#pragma unroll
+  for (int u = 0; u < LPT; ++u) {
+    const int k = k0 + u * kstep;
+    xv[u] = (has && k < P) ? src[(int64_t)k * a.E] : 0.0;
+  }
   // twiddle tables of every axis: T1[i] = w^i (i < 64), T2[i] = w^(64 i)
   for (int idx = tid; idx < a.tw_total; idx += kFftThreads) {
     int d = 0;
@@ -337,42 +436,12 @@ __device__ void fft_block_body(const FftArgs& a, int64_t group, double* smem) {
     sincospi(-2.0 * (double)e / (double)n, &s, &c);
     tabs[idx] = make_double2(c, s);
   }
-  __syncthreads();
-  // Bluestein: transform of the chirp filter b(m) = conj c(m), b(M-m) = b(m),
-  // held in registers by the threads that multiply by it (m = tid + kFftThreads u)
-  constexpr int NBH = BLUE ? kFftPoints / kFftThreads : 1;
-  double2 bh[NBH];
-  if (BLUE) {
-    const int M = a.ax[0].n, L = a.blue_L;
-    for (int m = tid; m < M; m += kFftThreads) {
-      double2 v = make_double2(0.0, 0.0);
-      if (m < L) v = chirp(m, L);
-      else if (M - m < L) v = chirp(M - m, L);
-      buf[m] = make_double2(v.x, -v.y);
-    }
-    __syncthreads();
-    fft_axis(buf, 1, a.ax[0], tabs);
-    const double invM = 1.0 / (double)M;
-#pragma unroll
-    for (int u = 0; u < NBH; ++u) {
-      const int m = tid + kFftThreads * u;
-      bh[u] = m < M ? make_double2(buf[m].x * invM, buf[m].y * invM) : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-  }
-  // load W real columns (coalesced rows of W entries), track column maxima
-  const int64_t q0 = group * W;
-  const int nq = (int)(a.cols - q0 < W ? a.cols - q0 : W);
-  const int myq = tid % W;  // W divides the thread count: the thread keeps its column
-  const bool has = myq < nq;
-  const int64_t qg = q0 + myq;
-  const int64_t bq = has ? qg / a.E : 0, eq = has ? qg % a.E : 0;
-  const double* src = a.in + bq * P * a.E + eq;
   double mx = 0.0;
-  for (int k = tid / W; k < P; k += kFftThreads / W) {
-    const double x = has ? src[(int64_t)k * a.E] : 0.0;
-    smem[(size_t)k * W + myq] = x;
-    mx = fmax(mx, fabs(x));
+#pragma unroll
+  for (int u = 0; u < LPT; ++u) {
+    const int k = k0 + u * kstep;
+    if (k < P) smem[(size_t)k * W + myq] = xv[u];
+    mx = fmax(mx, fabs(xv[u]));
   }
   for (int off = W; off < 64; off <<= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
   if ((tid & 63) < W) red[(tid >> 6) * W + myq] = mx;
@@ -385,57 +454,31 @@ __device__ void fft_block_body(const FftArgs& a, int64_t group, double* smem) {
     scl[tid] = (double)ex;
   }
   __syncthreads();
-  // scale to unit maximum (and chirp, zero padding for Bluestein)
+  // the transforms; the column scaling, the chirps and the filter product
+  // are folded into the first pass of each transform
   if (BLUE) {
-    const int M = a.ax[0].n, L = a.blue_L;
-    for (int idx = tid; idx < Wc * M; idx += kFftThreads) {
-      const int m = idx / Wc, c = idx % Wc;
-      double2 z = make_double2(0.0, 0.0);
-      if (m < L) {
-        const double2 x = buf[idx];
-        z = c_mul(make_double2(ldexp(x.x, -(int)scl[2 * c]), ldexp(x.y, -(int)scl[2 * c + 1])),
-                  chirp(m, L));
-      }
-      buf[idx] = z;
-    }
-  } else {
-    for (int idx = tid; idx < Wc * P; idx += kFftThreads) {
-      const int c = idx % Wc;
-      const double2 x = buf[idx];
-      buf[idx] = make_double2(ldexp(x.x, -(int)scl[2 * c]), ldexp(x.y, -(int)scl[2 * c + 1]));
-    }
-  }
-  __syncthreads();
-  if (BLUE) {
-    const int M = a.ax[0].n, L = a.blue_L;
-    fft_axis(buf, Wc, a.ax[0], tabs);
-#pragma unroll
-    for (int u = 0; u < NBH; ++u) {
-      const int m = tid + kFftThreads * u;
-      if (m < M)
-        for (int c = 0; c < Wc; ++c) {
-          const double2 z = c_mul(buf[m * Wc + c], bh[u]);
-          buf[m * Wc + c] = make_double2(z.x, -z.y);
-        }
-    }
-    __syncthreads();
-    fft_axis(buf, Wc, a.ax[0], tabs);
-    for (int idx = tid; idx < Wc * L; idx += kFftThreads) {
-      const double2 z = buf[idx];
-      buf[idx] = c_mul(make_double2(z.x, -z.y), chirp(idx / Wc, L));
-    }
-    __syncthreads();
-  } else {
-    for (int d = 0; d < a.naxes; ++d) fft_axis(buf, Wc, a.ax[d], tabs);
+    fft_axis(buf, Wc, a.ax[0], tabs, PassPre{2, scl, a.chirp, a.blue_L});
+    fft_axis(buf, Wc, a.ax[0], tabs, PassPre{3, nullptr, a.bhat, 0});
+  } else if (a.naxes > 0) {
+    fft_axis(buf, Wc, a.ax[0], tabs, PassPre{1, scl, nullptr, 0});
+    for (int d = 1; d < a.naxes; ++d) fft_axis(buf, Wc, a.ax[d], tabs, PassPre{0, nullptr, nullptr, 0});
   }
   // split the packed columns, undo the scaling, store rows of W entries
   double* dst = a.out + 2 * (bq * P * a.E + eq);
   const int sh = has ? (int)scl[myq] : 0;
   const int c = myq >> 1;
-  for (int k = tid / W; k < P; k += kFftThreads / W) {
-    if (!has) continue;
-    const double2 z = buf[k * Wc + c];
-    const double2 y = buf[neg_point(k, a.L) * Wc + c];
+  if (!has) return;  // no barrier follows
+  for (int k = k0; k < P; k += kstep) {
+    const int nk = neg_point(k, a.L);
+    double2 z = buf[k * Wc + c];
+    double2 y = buf[nk * Wc + c];
+    if (BLUE) {  // the convolution's inverse transform (conj) and the chirp
+      z = c_mul(make_double2(z.x, -z.y), a.chirp[k]);
+      y = c_mul(make_double2(y.x, -y.y), a.chirp[nk]);
+    } else if (a.naxes == 0) {  // one cell: the scaling still applies
+      z = make_double2(ldexp(z.x, -(int)scl[2 * c]), ldexp(z.y, -(int)scl[2 * c + 1]));
+      y = z;
+    }
     double xr, xi;
     if (myq & 1) {
       xr = 0.5 * (z.y + y.y);

@@ -6,7 +6,8 @@
 // Lattices whose buffer fits a workgroup's LDS (every extent 7-smooth and
 // L1 L2 L3 <= 4096, or one axis of any length up to 2048 by Bluestein) take
 // the LDS FFT: one launch, each workgroup a set of entry columns over the
-// whole lattice, no workspace.  Longer lines fall back to a direct DFT along
+// whole lattice (Bluestein lengths: one more small launch that tabulates the
+// chirp and the filter's transform, L + M complex values of workspace).  Longer lines fall back to a direct DFT along
 // one axis at a time (twiddles from the exact residue j k mod L).
 #include <algorithm>
 #include <cstring>
@@ -20,6 +21,11 @@ namespace {
 
 using dev::DftArgs;
 constexpr int kMaxTwiddle = dev::kMaxTwiddle;
+
+__global__ __launch_bounds__(dev::kFftThreads) void fft_blue_tables_kernel(dev::FftArgs a) {
+  extern __shared__ __align__(16) double smem[];
+  dev::fft_blue_tables_body(a, smem);
+}
 
 template <bool BLUE>
 __global__ __launch_bounds__(dev::kFftThreads) void fft_block_kernel(dev::FftArgs a) {
@@ -127,18 +133,35 @@ bool plan_fft(const double* in, double* out, const int L[3], int m0, int64_t bat
   a->tw_total = tw;
   int W = 2 * (dev::kFftPoints / a->nbuf);
   int w2 = 2;
-  while (2 * w2 <= W && 2 * w2 <= 16) w2 *= 2;
+  while (2 * w2 <= W && 2 * w2 <= 64) w2 *= 2;
   a->W = w2;
   return true;
 }
 
+size_t fft_blue_table_bytes(const dev::FftArgs& a) {
+  return a.blue ? align_up(sizeof(double2) * ((size_t)a.blue_L + a.ax[0].n), 256) : 0;
+}
+
+void set_fft_blue_tables(dev::FftArgs* a, void* ws) {
+  if (!a->blue) return;
+  a->chirp = (double2*)ws;
+  a->bhat = a->chirp + a->blue_L;
+}
+
 tl_status launch_fft(const dev::FftArgs& a, hipStream_t stream) {
+  if (a.blue) {
+    hipLaunchKernelGGL(fft_blue_tables_kernel, dim3(1), dim3(dev::kFftThreads),
+                       dev::fft_tables_lds_bytes(a), stream, a);
+    TL_CHECK_LAUNCH();
+  }
   const dim3 grid((unsigned)ceil_div(a.cols, a.W)), blk(dev::kFftThreads);
   const size_t shmem = dev::fft_lds_bytes(a);
+  hipEvent_t e0, e1;
+  stage_events(TL_STAGE_FFT, &e0, &e1);
   if (a.blue)
-    hipLaunchKernelGGL(fft_block_kernel<true>, grid, blk, shmem, stream, a);
+    launch_with_events(fft_block_kernel<true>, grid, blk, shmem, stream, e0, e1, a);
   else
-    hipLaunchKernelGGL(fft_block_kernel<false>, grid, blk, shmem, stream, a);
+    launch_with_events(fft_block_kernel<false>, grid, blk, shmem, stream, e0, e1, a);
   TL_CHECK_LAUNCH();
   return TL_OK;
 }
@@ -146,7 +169,7 @@ tl_status launch_fft(const dev::FftArgs& a, hipStream_t stream) {
 size_t block_fft_workspace(int L1, int L2, int L3, int m0, int batch) {
   const int L[3] = {L1, L2, L3};
   dev::FftArgs a;
-  if (plan_fft(nullptr, nullptr, L, m0, batch, &a)) return 0;
+  if (plan_fft(nullptr, nullptr, L, m0, batch, &a)) return fft_blue_table_bytes(a);
   const int na = (L1 > 1) + (L2 > 1) + (L3 > 1);
   const int64_t total = (int64_t)batch * L1 * L2 * L3 * m0 * m0;
   return na >= 2 ? align_up(sizeof(double) * 2 * (size_t)total, 256) : 0;
@@ -157,7 +180,15 @@ tl_status block_fft(const double* in, int L1, int L2, int L3, int m0, int batch,
   const int L[3] = {L1, L2, L3};
   {
     dev::FftArgs fa;
-    if (plan_fft(in, out, L, m0, batch, &fa)) return launch_fft(fa, stream);
+    if (plan_fft(in, out, L, m0, batch, &fa)) {
+      const size_t need = fft_blue_table_bytes(fa);
+      if (ws_bytes < need || (need && !ws)) {
+        set_error("block_fft workspace: need %zu bytes, got %zu", need, ws_bytes);
+        return TL_EWORKSPACE;
+      }
+      set_fft_blue_tables(&fa, ws);
+      return launch_fft(fa, stream);
+    }
   }
   // lines longer than the LDS FFT holds: direct DFT, one axis per launch
   const int64_t E = (int64_t)m0 * m0;

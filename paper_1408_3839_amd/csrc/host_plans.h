@@ -62,6 +62,9 @@ tl_status build_basis(const Geometry& g, const tl_system* s, double* G, double* 
 // when the lattice does not fit a workgroup's buffer.
 bool plan_fft(const double* in, double* out, const int L[3], int m0, int64_t batch,
               dev::FftArgs* a);
+// workspace of the Bluestein tables (0 for 7-smooth lattices) and their place in it
+size_t fft_blue_table_bytes(const dev::FftArgs& a);
+void set_fft_blue_tables(dev::FftArgs* a, void* ws);
 
 size_t box_workspace_bytes(const Geometry& g);
 tl_status assemble_box(const Geometry& g, const tl_system* s, const double* G, const double* AG,

@@ -173,7 +173,9 @@ tl_status lattice_sum_potential(const Geometry& g, const tl_system* s, double* P
   const int T = (int)g.pot_terms;
   const int blocks = pp.fold_blocks + pp.direct_blocks;
   if (blocks > 0) {
-    hipLaunchKernelGGL(potential_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+    hipEvent_t e0, e1;
+    stage_events(TL_STAGE_LATTICE_SUM, &e0, &e1);
+    launch_with_events(potential_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, e0, e1,
                        pp.direct, pp.fold, pp.quad, T, pp.fold_blocks, P);
     TL_CHECK_LAUNCH();
   }

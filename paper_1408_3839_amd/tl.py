@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libtl.so")
 TL_OK, TL_EINVAL, TL_EUNSUPPORTED, TL_EHIP, TL_EWORKSPACE = 0, -1, -2, -3, -4
 TL_FP64, TL_FP32, TL_SPLIT_BF16, TL_SPLIT_FP16 = 0, 1, 2, 3
 TL_MODE_PERIODIC, TL_MODE_BOX = 0, 1
+TL_STAGE_CONTRACTION, TL_STAGE_LATTICE_SUM, TL_STAGE_FFT = 0, 1, 2
 PRECISIONS = {"fp64": TL_FP64, "fp32": TL_FP32, "split_bf16": TL_SPLIT_BF16,
               "split_fp16": TL_SPLIT_FP16}
 
@@ -61,7 +62,7 @@ class TlSizes(ctypes.Structure):
     ]
 
 
-TL_MAX_BATCH = 256
+TL_MAX_BATCH = 512
 
 
 class TlBatchPlan(ctypes.Structure):
@@ -109,6 +110,7 @@ SIGNATURES = {
                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "tl_set_contraction_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tl_set_stage_events": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "tl_block_fft": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 5
                      + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "tl_batched_heigh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
@@ -307,6 +309,13 @@ def tl_set_contraction_events(start_event, stop_event):
     """start_event/stop_event: raw hipEvent_t handles (int) or None."""
     _check(load().tl_set_contraction_events(start_event, stop_event),
            "tl_set_contraction_events")
+
+
+def tl_set_stage_events(stage, start_event, stop_event):
+    """Profiling events (raw hipEvent_t handles or None) attached to one
+    stage's kernel launch (TL_STAGE_*)."""
+    _check(load().tl_set_stage_events(int(stage), start_event, stop_event),
+           "tl_set_stage_events")
 
 
 def tl_block_fft(inp, L1, L2, L3, m0, batch, out, ws=None, ws_bytes=0, stream=None):

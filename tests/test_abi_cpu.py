@@ -98,11 +98,13 @@ def test_workspace_queries():
         s = wl.config(cid)
         assert tl.tl_potential_workspace_bytes(s) == 0
         assert tl.tl_assemble_workspace_bytes(s) % 256 == 0
-    # whole lattices in LDS: chains up to L = 2048 (any length), 7-smooth
-    # lattices of up to 4096 cells
+    # whole lattices in LDS: 7-smooth lattices of up to 4096 cells need no
+    # workspace; other chain lengths up to 2048 (Bluestein) keep the chirp
+    # c(k), k < L, and the filter's transform (M = 4096 points) there
     assert tl.tl_block_fft_workspace_bytes(64, 1, 1, 8, 2) == 0
     assert tl.tl_block_fft_workspace_bytes(8, 8, 8, 10, 2) == 0
-    assert tl.tl_block_fft_workspace_bytes(2039, 1, 1, 4, 2) == 0
+    assert tl.tl_block_fft_workspace_bytes(2039, 1, 1, 4, 2) == 384 * 256   # 16 (2039 + 4096)
+    assert tl.tl_block_fft_workspace_bytes(37, 1, 1, 4, 2) == 7 * 256      # 16 (37 + 75)
     assert tl.tl_block_fft_workspace_bytes(4099, 1, 1, 4, 2) == 0      # one axis: no workspace
     assert tl.tl_block_fft_workspace_bytes(11, 3, 1, 4, 2) == 8 * 2 * 33 * 16 * 2
     assert tl.tl_block_fft_workspace_bytes(16, 16, 32, 2, 1) == 8 * 2 * 8192 * 4

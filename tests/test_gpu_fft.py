@@ -79,7 +79,8 @@ def _random(shape, seed, spread=0.0):
 ])
 def test_lds_fft_parity(shape):
     b, L1, L2, L3, m0 = shape
-    assert tl.tl_block_fft_workspace_bytes(L1, L2, L3, m0, b) == 0
+    # no workspace but the Bluestein tables (at most L + 4096 complex values)
+    assert tl.tl_block_fft_workspace_bytes(L1, L2, L3, m0, b) <= 16 * (L1 + 4096) + 256
     A = _random((b, L1, L2, L3, m0, m0), seed=sum(shape))
     _check(A, _gpu_fft(A))
 
