@@ -87,8 +87,15 @@ def cpu_baseline(sys, budget_s: float = 12.0):
             break
     dt = time.perf_counter() - t0
     entries = sys.ncells * sys.m0 * sys.m0
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": entries * reps / dt, "unit": "entries/s", "cores": int(threads),
+        "cpu_model": cpu_model, "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": f"{reps} full solves of the workload (assembly + block DFT + "
                   f"{sys.ncells} k-block eigensolves) in {dt:.1f} s",
@@ -96,27 +103,58 @@ def cpu_baseline(sys, budget_s: float = 12.0):
     }, (H, S, Hb, Sb, evals)
 
 
-def eig_errors(ev_gpu, Hb, Sb, m0):
-    """Max |d lambda| over all eigenvalues and over those whose first-order
-    condition (|H| + |lambda| |S|) |u|^2 (u^H S u = 1) is below 1e6."""
+def eig_errors(ev_gpu, Hb, Sb, m0, ok=None):
+    """Eigenvalue errors against LAPACK on the reference pencils, with each
+    eigenvalue's first-order condition (|H| + |lambda| |S|) |u|^2 (u^H S u = 1):
+    the maxima over all eigenvalues and over those with condition <= 1e6, and
+    the counts (total, within 1e-6 Ha, condition above 1e6).  `ok` masks the
+    blocks the GPU solved (info = 0)."""
     import scipy.linalg as sla
     Hf = Hb.reshape(-1, m0, m0)
     Sf = Sb.reshape(-1, m0, m0)
     ev = ev_gpu.reshape(-1, m0)
+    if ok is None:
+        ok = np.ones(Hf.shape[0], dtype=bool)
     worst_all = worst_ok = 0.0
     cmax = 0.0
-    for j in range(Hf.shape[0]):
+    n = n_in = n_ill = n_ok_in = n_ok = 0
+    for j in np.nonzero(ok)[0]:
         lam, U = sla.eigh(Hf[j], Sf[j])
         cond = (np.linalg.norm(Hf[j], 2) + np.abs(lam) * np.linalg.norm(Sf[j], 2)) * \
             np.sum(np.abs(U) ** 2, axis=0)
         d = np.abs(ev[j] - lam)
         worst_all = max(worst_all, float(d.max()))
-        ok = cond <= 1e6
-        if ok.any():
-            worst_ok = max(worst_ok, float(d[ok].max()))
+        good = cond <= 1e6
+        # a near-singular block may move its ill-conditioned eigenvalues past
+        # the others: well-conditioned ones are matched to the nearest
+        dn = np.abs(ev[j][None, :] - lam[:, None]).min(axis=1)
+        if good.any():
+            worst_ok = max(worst_ok, float(dn[good].max()))
         cmax = max(cmax, float(cond.max()))
+        n += m0
+        n_in += int(np.sum(d <= 1e-6))
+        n_ill += int(np.sum(~good))
+        n_ok += int(np.sum(good))
+        n_ok_in += int(np.sum(dn[good] <= 1e-6))
     return {"max_abs_dlambda_all_Ha": worst_all, "max_abs_dlambda_cond_le_1e6_Ha": worst_ok,
-            "max_eig_condition": cmax}
+            "max_eig_condition": cmax, "n_eigs": n, "n_eigs_within_1e-6_Ha": n_in,
+            "n_eigs_cond_gt_1e6": n_ill, "n_eigs_cond_le_1e6": n_ok,
+            "n_eigs_cond_le_1e6_within_1e-6_Ha": n_ok_in}
+
+
+def entry_errors(H, S, Hr, Sr, scale):
+    """Entry errors of H (and S) against the oracle: relative to max|H|, and
+    per entry to its no-cancellation scale over the entries whose scale is at
+    least 1e-14 of the largest (entries below carry no digits at FP64's
+    resolution of the block column), with the count above 1e-10."""
+    floor = scale >= 1e-14 * scale.max()
+    rel = np.abs(H - Hr)[floor] / scale[floor]
+    return {"max_abs_dH_over_max_H": float(np.abs(H - Hr).max() / np.abs(Hr).max()),
+            "max_abs_dS_over_max_S": float(np.abs(S - Sr).max() / np.abs(Sr).max()),
+            "max_rel_dH_over_scale_floor_1e-14": float(rel.max()),
+            "n_entries_floor_1e-14": int(floor.sum()),
+            "n_entries_dH_over_scale_gt_1e-10": int(np.sum(rel > 1e-10)),
+            "n_entries": int(H.size)}
 
 
 def measure(sys_, precision, n_slices, steps, warmup):
@@ -232,6 +270,39 @@ def box_chain_section(steps: int, warmup: int):
     }
 
 
+def cubic_section(steps: int, warmup: int):
+    """The periodic (8,8,8) lattice with a two-site cell (m0 = 10, R_tot = 64,
+    240^3 grid, 3-level block FFT to 512 k-blocks): whole-path graph replays
+    in FP64 and in the split modes, entries and eigenvalues against the FP64
+    oracle."""
+    import oracle
+    from paper_1408_3839_amd import workloads
+    s = workloads.config(5)
+    Hr, Sr, scale = oracle.core_hamiltonian_blocks(s)
+    Hb, Sb = oracle.block_dft(Hr), oracle.block_dft(Sr)
+    entries = s.ncells * s.m0 * s.m0
+    out = {"workload": "periodic (8,8,8) lattice, a=3.0 bohr, sites Z=1 at 0 and Z=2 at "
+                       "(0.7,0.7,0.7); m0=10 (4s + 2 p shells); grid 240^3, h=0.1; R=32 "
+                       "(64 terms); 512 k-blocks",
+           "entries_per_step": entries}
+    fp64_ms = None
+    for prec, nsl in (("fp64", 0), ("split_bf16", 6), ("split_fp16", 5)):
+        r = measure(s, prec, nsl, steps, warmup)
+        acc = {"ms_per_step": r["ms_per_step"], "contraction_ms": r["contraction_ms"],
+               "entries_per_s": entries / (r["ms_per_step"] * 1e-3),
+               "k_blocks_per_s": s.ncells / (r["ms_per_step"] * 1e-3),
+               "k_blocks_not_definite": int(np.sum(r["info"].reshape(-1) > 0))}
+        acc.update(entry_errors(r["H"], r["S"], Hr, Sr, scale))
+        ok = r["info"].reshape(-1) == 0
+        if ok.any():
+            acc.update(eig_errors(r["evals"], Hb, Sb, s.m0, ok))
+        if prec == "fp64":
+            fp64_ms = r["ms_per_step"]
+        acc["speedup_vs_fp64"] = fp64_ms / r["ms_per_step"]
+        out[prec + (f"x{nsl}" if nsl else "")] = acc
+    return out
+
+
 def batch_section(steps: int, warmup: int):
     """64 ragged periodic (L,1,1) instances, whole chain, one launch per
     stage, replayed as one HIP graph; FP64 and split-BF16 x6, each with the
@@ -246,6 +317,7 @@ def batch_section(steps: int, warmup: int):
                        "h=0.0625, R=24", "instances": len(systems)}
     entries = sum(int(s.L[0]) * s.m0 * s.m0 for s in systems)
     flops = sum(contraction_flops(s, tl.tl_query_sizes(s)) for s in systems)
+    results = {}
     for prec, nsl in (("fp64", 0), ("split_bf16", 6)):
         want, tuning = autotune.tune_batch(systems, precision=prec, n_slices=nsl, cache_path=None)
         bp = BatchPipeline(systems, precision=prec, n_slices=nsl, want_blocks=want)
@@ -269,17 +341,67 @@ def batch_section(steps: int, warmup: int):
         torch.cuda.synchronize()
         cms = a.elapsed_time(b)
         mult = nsl * (nsl + 1) // 2 if nsl else 1
+        info = bp.buf["info"].cpu().numpy()
+        nkb = int(info.size)
         out[prec + (f"x{nsl}" if nsl else "")] = {
             "ms_per_step": ms, "entries_per_s": entries / (ms * 1e-3),
-            "k_blocks_per_s": sum(int(s.L[0]) for s in systems) / (ms * 1e-3),
+            "k_blocks_per_s": nkb / (ms * 1e-3),
+            "k_blocks_solved_per_s": int(np.sum(info == 0)) / (ms * 1e-3),
+            "k_blocks_flagged_not_definite": int(np.sum(info > 0)),
+            "k_blocks": nkb,
             "contraction_ms": cms,
             "contraction_tflops": flops * mult / (cms * 1e-3) / 1e12,
             "tuned_want_blocks": want,
             "tuning_contraction_ms": {str(k): round(v, 4) for k, v in tuning.items()},
         }
+        results[prec] = (bp.buf["evals"].cpu().numpy(), info, bp.buf["HSbar"].cpu().numpy(),
+                         bp.buf["HS"].cpu().numpy())
         del bp
         torch.cuda.synchronize()
     out["entries_per_step"] = entries
+    # split against the FP64 GPU path: entries, and eigenvalues of the blocks
+    # both solved, with each eigenvalue's condition in the FP64 pencil
+    import scipy.linalg as sla
+    ev64, inf64, hsb64, hs64 = results["fp64"]
+    evs, infs, _, hss = results["split_bf16"]
+    off = oe = ok_ = 0
+    worst_all = worst_ok = 0.0
+    n = n_in = n_ill = n_ok = n_ok_in = 0
+    for s in systems:
+        L, m0 = int(s.L[0]), s.m0
+        be = L * m0 * m0
+        Hb = hsb64[2 * off:2 * (off + be)].reshape(L, m0, m0, 2)
+        Sb = hsb64[2 * (off + be):2 * (off + 2 * be)].reshape(L, m0, m0, 2)
+        Hb = Hb[..., 0] + 1j * Hb[..., 1]
+        Sb = Sb[..., 0] + 1j * Sb[..., 1]
+        for j in range(L):
+            if inf64[ok_ + j] != 0 or infs[ok_ + j] != 0:
+                continue
+            lam, U = sla.eigh(Hb[j], Sb[j])
+            cond = (np.linalg.norm(Hb[j], 2) + np.abs(lam) * np.linalg.norm(Sb[j], 2)) * \
+                np.sum(np.abs(U) ** 2, axis=0)
+            e_s = evs[oe + j * m0:oe + (j + 1) * m0]
+            d = np.abs(e_s - ev64[oe + j * m0:oe + (j + 1) * m0])
+            worst_all = max(worst_all, float(d.max()))
+            good = cond <= 1e6
+            # well-conditioned eigenvalues matched to the nearest split one
+            dn = np.abs(e_s[None, :] - lam[:, None]).min(axis=1)
+            if good.any():
+                worst_ok = max(worst_ok, float(dn[good].max()))
+            n += m0
+            n_in += int(np.sum(d <= 1e-6))
+            n_ill += int(np.sum(~good))
+            n_ok += int(np.sum(good))
+            n_ok_in += int(np.sum(dn[good] <= 1e-6))
+        off += 2 * be
+        oe += L * m0
+        ok_ += L
+    out["split_bf16x6_vs_fp64"] = {
+        "max_abs_dHS_over_max": float(np.abs(hss - hs64).max() / np.abs(hs64).max()),
+        "max_abs_dlambda_all_Ha": worst_all, "max_abs_dlambda_cond_le_1e6_Ha": worst_ok,
+        "n_eigs_compared": n, "n_eigs_within_1e-6_Ha": n_in, "n_eigs_cond_gt_1e6": n_ill,
+        "n_eigs_cond_le_1e6": n_ok, "n_eigs_cond_le_1e6_within_1e-6_Ha": n_ok_in,
+        "speedup_vs_fp64": out["fp64"]["ms_per_step"] / out["split_bf16x6"]["ms_per_step"]}
     return out
 
 
@@ -374,6 +496,7 @@ def main():
                          "HBM byte counters) and exit")
     ap.add_argument("--no-box", action="store_true", help="skip the open-chain section")
     ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch section")
+    ap.add_argument("--no-cubic", action="store_true", help="skip the (8,8,8) lattice section")
     ap.add_argument("--no-stages", action="store_true",
                     help="skip the lattice-sum / FFT HBM section")
     ap.add_argument("--stages-only", action="store_true",
@@ -476,17 +599,11 @@ def main():
         for (prec, nsl), r in results.items():
             acc = {"ms_per_step": r["ms_per_step"], "contraction_ms": r["contraction_ms"],
                    "entries_per_s": entries / (r["ms_per_step"] * 1e-3),
-                   "max_abs_dH_over_max_H": float(np.abs(r["H"] - Hr).max() / np.abs(Hr).max()),
-                   # entries above the denormal range (MFMA flushes denormals)
-                   "max_rel_dH_over_scale":
-                       float(np.max(np.where(scale > 1e-280, np.abs(r["H"] - Hr)
-                                             / np.where(scale > 0, scale, 1.0), 0.0))),
-                   "k_blocks_not_definite": int(np.sum(r["info"] > 0))}
-            ok = r["info"] == 0
+                   "k_blocks_not_definite": int(np.sum(r["info"].reshape(-1) > 0))}
+            acc.update(entry_errors(r["H"], r["S"], Hr, Sr, scale))
+            ok = r["info"].reshape(-1) == 0
             if ok.any():
-                e = eig_errors(np.where(ok[:, None], r["evals"], 0.0)[ok], Hb.reshape(
-                    -1, sys_.m0, sys_.m0)[ok], Sb.reshape(-1, sys_.m0, sys_.m0)[ok], sys_.m0)
-                acc.update(e)
+                acc.update(eig_errors(r["evals"], Hb, Sb, sys_.m0, ok))
             acc["roofline_frac"] = roofline(prec, nsl, r)["frac"]
             table[f"{prec}" + (f"x{nsl}" if nsl else "")] = acc
         out["precision_modes"] = table
@@ -498,6 +615,8 @@ def main():
                 k: fp64["contraction_ms"] / v["contraction_ms"] for k, v in table.items()}
     if not args.no_box:
         out["box_chain"] = box_chain_section(min(args.steps, 5), 1)
+    if not args.no_cubic:
+        out["cubic_lattice"] = cubic_section(min(args.steps, 20), 2)
     if not args.no_batch:
         out["batch"] = batch_section(min(args.steps, 10), 2)
     if not args.no_stages:

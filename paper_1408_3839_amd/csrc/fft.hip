@@ -86,7 +86,7 @@ bool factor_axis(int n, dev::FftAxis* ax) {
 }  // namespace
 
 bool plan_fft(const double* in, double* out, const int L[3], int m0, int64_t batch,
-              dev::FftArgs* a) {
+              dev::FftArgs* a, int min_groups) {
   std::memset(a, 0, sizeof(*a));
   a->in = in;
   a->out = out;
@@ -131,9 +131,12 @@ bool plan_fft(const double* in, double* out, const int L[3], int m0, int64_t bat
     tw += 64 + (int)ceil_div(a->ax[i].n, 64);
   }
   a->tw_total = tw;
+  // columns per workgroup: as many as the LDS buffer holds (at most 64),
+  // halved while that would leave fewer than min_groups workgroups
   int W = 2 * (dev::kFftPoints / a->nbuf);
   int w2 = 2;
   while (2 * w2 <= W && 2 * w2 <= 64) w2 *= 2;
+  while (w2 > 2 && ceil_div(a->cols, w2) < min_groups) w2 /= 2;
   a->W = w2;
   return true;
 }
@@ -169,7 +172,8 @@ tl_status launch_fft(const dev::FftArgs& a, hipStream_t stream) {
 size_t block_fft_workspace(int L1, int L2, int L3, int m0, int batch) {
   const int L[3] = {L1, L2, L3};
   dev::FftArgs a;
-  if (plan_fft(nullptr, nullptr, L, m0, batch, &a)) return fft_blue_table_bytes(a);
+  if (plan_fft(nullptr, nullptr, L, m0, batch, &a, kFftSingleGroups))
+    return fft_blue_table_bytes(a);
   const int na = (L1 > 1) + (L2 > 1) + (L3 > 1);
   const int64_t total = (int64_t)batch * L1 * L2 * L3 * m0 * m0;
   return na >= 2 ? align_up(sizeof(double) * 2 * (size_t)total, 256) : 0;
@@ -180,7 +184,7 @@ tl_status block_fft(const double* in, int L1, int L2, int L3, int m0, int batch,
   const int L[3] = {L1, L2, L3};
   {
     dev::FftArgs fa;
-    if (plan_fft(in, out, L, m0, batch, &fa)) {
+    if (plan_fft(in, out, L, m0, batch, &fa, kFftSingleGroups)) {
       const size_t need = fft_blue_table_bytes(fa);
       if (ws_bytes < need || (need && !ws)) {
         set_error("block_fft workspace: need %zu bytes, got %zu", need, ws_bytes);

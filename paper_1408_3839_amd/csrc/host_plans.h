@@ -59,9 +59,12 @@ tl_status build_basis(const Geometry& g, const tl_system* s, double* G, double* 
                       hipStream_t stream);
 
 // Block FFT over the lattice index in LDS (one launch, no workspace); false
-// when the lattice does not fit a workgroup's buffer.
+// when the lattice does not fit a workgroup's buffer.  min_groups: fewer
+// columns per workgroup while the launch would have fewer workgroups (a
+// single system's transform is latency-bound; a batch has many instances).
+constexpr int kFftSingleGroups = 256;
 bool plan_fft(const double* in, double* out, const int L[3], int m0, int64_t batch,
-              dev::FftArgs* a);
+              dev::FftArgs* a, int min_groups = 1);
 // workspace of the Bluestein tables (0 for 7-smooth lattices) and their place in it
 size_t fft_blue_table_bytes(const dev::FftArgs& a);
 void set_fft_blue_tables(dev::FftArgs* a, void* ws);

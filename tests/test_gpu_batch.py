@@ -99,6 +99,32 @@ def test_ragged_64_chain_batch():
     torch.cuda.synchronize()
     info = bp.buf["info"].cpu().numpy()
     assert np.all(info >= 0)
+    # every flagged k-block has a numerically singular Sbar_j (smallest
+    # eigenvalue within rounding of zero), every clearly definite one is solved
+    hsbar = bp.buf["HSbar"].cpu().numpy()
+    eps = 2.0 ** -52
+    off = ok_ = 0
+    flagged = 0
+    for s, v in zip(systems, bp.views):
+        L, m0 = int(s.L[0]), s.m0
+        be = L * m0 * m0
+        Sb = hsbar[2 * (off + be):2 * (off + 2 * be)].reshape(L, m0, m0, 2)
+        Sb = Sb[..., 0] + 1j * Sb[..., 1]
+        inf = v["info"].cpu().numpy()
+        for j in range(L):
+            w = np.linalg.eigvalsh(0.5 * (Sb[j] + Sb[j].conj().T))
+            tiny = 64 * m0 * eps * np.abs(w).max()
+            if inf[j] > 0:
+                flagged += 1
+                assert w[0] <= tiny, (s.name, j, w[0], tiny)
+            elif w[0] > 1e3 * tiny:
+                ok_ += 1
+            if w[0] > 1e3 * tiny:
+                assert inf[j] == 0, (s.name, j)
+        off += 2 * be
+    print(f"\nragged batch: {int(np.sum(info > 0))} of {info.size} k-blocks flagged "
+          f"(Sbar_j not numerically definite), {ok_} clearly definite and solved")
+    assert flagged == int(np.sum(info > 0))
     order = np.argsort([int(s.L[0]) for s in systems])
     for i in list(order[:3]) + [int(order[-1])]:
         s, v = systems[i], bp.views[i]

@@ -216,6 +216,38 @@ def _eig_tol(Hj, Sj, lam_ref, U_ref, c=256.0):
     return 1e-10 * np.maximum(1.0, np.abs(lam_ref)) + c * eps * (nh + np.abs(lam_ref) * ns) * un
 
 
+@pytest.mark.parametrize("evecs", [False, True], ids=["evals-only", "with-evecs"])
+def test_heigh_ill_conditioned_block_vs_50_digits(evecs):
+    """The k = 0 block of the (64,1,1) chain (kappa(Sbar) ~ 7e13), as the
+    FP64 oracle forms it, through both eigensolver routes (Householder +
+    Sturm without eigenvectors, Jacobi with them): errors against the
+    eigenvalues of the same pencil in 50-digit arithmetic, next to LAPACK's
+    (Sec. 4.2 eq. (HF-FSpace-Block))."""
+    from mp_pencil import mp_generalized_eigvals
+    from test_conditioning_cpu import c2_kblocks
+    Hb, Sb = c2_kblocks()
+    H0, S0 = Hb[:1], Sb[:1]
+    ref = mp_generalized_eigvals(H0[0], S0[0])
+    lam, U = sla.eigh(H0[0], S0[0])
+    ev, _, info = _run_heigh(H0, S0, evecs=evecs)
+    assert info[0] == 0
+    err_gpu = np.abs(ev[0] - ref)
+    err_lap = np.abs(lam - ref)
+    eps = 2.0 ** -52
+    cond = (np.linalg.norm(H0[0], 2) + np.abs(ref) * np.linalg.norm(S0[0], 2)) * \
+        np.sum(np.abs(U) ** 2, axis=0)
+    print(f"\nk = 0 block ({'eigenvalues only' if not evecs else 'with eigenvectors'}):")
+    for i in range(len(ref)):
+        print(f"  lambda {ref[i]: .12f}  GPU error {err_gpu[i]:.2e}  LAPACK error "
+              f"{err_lap[i]:.2e}  condition {cond[i]:.2e}")
+    print(f"  max error: GPU {err_gpu.max():.2e}, LAPACK {err_lap.max():.2e}")
+    # both within the first-order bound of their rounding; the well
+    # conditioned eigenvalues to 1e-10
+    assert np.all(err_gpu <= 256 * eps * cond + 1e-10)
+    ok = cond <= 1e6
+    assert np.all(err_gpu[ok] <= 1e-10)
+
+
 @pytest.mark.parametrize("m", [1, 2, 3, 7, 8, 9, 13, 16, 17, 31, 32])
 def test_heigh_random_pencils(m):
     rng = np.random.default_rng(100 + m)
