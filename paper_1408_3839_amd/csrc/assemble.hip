@@ -42,13 +42,13 @@ __global__ __launch_bounds__(256) void contract_f64_src_kernel(ContractArgs a) {
 __global__ __launch_bounds__(256) void contract_f32_kernel(ContractArgs a) {
   contract_f32_body(a, blockIdx.x);
 }
-template <typename LowT>
-__global__ __launch_bounds__(256) void slice_kernel(SliceArgs a) {
-  slice_body<LowT>(a, blockIdx.x);
-}
 template <typename LowT, int S>
-__global__ __launch_bounds__(256) void contract_split_kernel(SplitArgs a) {
-  contract_split_body<LowT, S>(a, blockIdx.x);
+__global__ __launch_bounds__(256) void rowmax_kernel(RowMaxArgs a) {
+  rowmax_body<LowT, S>(a, blockIdx.x);
+}
+template <typename LowT, int S, int SPT>
+__global__ __launch_bounds__(kSplitThreads) void contract_split_kernel(SplitArgs a) {
+  contract_split_src_body<LowT, S, SPT>(a, blockIdx.x);
 }
 __global__ __launch_bounds__(256) void reduce_partials_kernel(ReduceArgs a, int64_t total) {
   reduce_partials_body(a, total, blockIdx.x);
@@ -72,16 +72,18 @@ struct Plan {
   int total_blocks;
 };
 
-// Tiling of the three contractions: 32 x 32 tiles, node chunks split so that
-// about `want` workgroups cover the chip (at least two 64-node stages each).
-Plan make_plan(const Geometry& g, int want_blocks) {
+// Tiling of the three contractions: tile x tile tiles (32 for FP64/FP32, 64
+// for the split modes), node chunks split so that about `want` workgroups
+// cover the chip (at least two 64-node stages each).
+Plan make_plan(const Geometry& g, int want_blocks, int tile = kBM, int tile_n = 0) {
+  if (tile_n <= 0) tile_n = tile;
   Plan p;
   size_t off = 0;
   int nblk = 0;
   for (int d = 0; d < 3; ++d) {
     p.M[d] = (int)((g.pot_terms + 2) * g.m0);
     p.N[d] = g.m0 * g.shifts[d];
-    int64_t tiles = ceil_div(p.M[d], kBM) * ceil_div(p.N[d], kBN);
+    int64_t tiles = ceil_div(p.M[d], tile) * ceil_div(p.N[d], tile_n);
     int64_t want = std::max<int64_t>(1, ceil_div(want_blocks, tiles));
     int64_t maxsplit = std::max<int64_t>(1, g.n[d] / (2 * kKT));
     int ks = (int)std::min(want, maxsplit);
@@ -89,7 +91,7 @@ Plan make_plan(const Geometry& g, int want_blocks) {
     ks = (int)ceil_div(g.n[d], kchunk);
     p.ks[d] = ks;
     p.kchunk[d] = kchunk;
-    p.tiles_n[d] = (int)ceil_div(p.N[d], kBN);
+    p.tiles_n[d] = (int)ceil_div(p.N[d], tile_n);
     p.blocks[d] = (int)(tiles * ks);
     nblk += p.blocks[d];
     p.part_off[d] = off;
@@ -102,25 +104,27 @@ Plan make_plan(const Geometry& g, int want_blocks) {
   return p;
 }
 
-// Extra workspace of the split modes: slices of X and G rows and their scales.
+// Extra workspace of the split modes: the exponents of the row maxima of the
+// P, G, AG and SG rows of every dimension.
 struct SplitPlan {
-  size_t xs_off[3], ys_off[3], xsc_off[3], ysc_off[3];
+  size_t ex_off[3][4];
+  size_t gs_off[3];
+  int ldg[3];
   size_t bytes;
 };
 
-SplitPlan make_split_plan(const Geometry& g, const Plan& plan, int s, size_t base) {
+SplitPlan make_split_plan(const Geometry& g, int s, size_t base) {
   SplitPlan sp;
   size_t off = base;
-  for (int d = 0; d < 3; ++d) {
-    const size_t ld = align_up((size_t)g.n[d], kSliceAlign);
-    sp.xs_off[d] = off;
-    off += align_up(2 * (size_t)s * plan.M[d] * ld, 256);
-    sp.ys_off[d] = off;
-    off += align_up(2 * (size_t)s * g.m0 * ld, 256);
-    sp.xsc_off[d] = off;
-    off += align_up(sizeof(double) * (size_t)plan.M[d], 256);
-    sp.ysc_off[d] = off;
-    off += align_up(sizeof(double) * (size_t)g.m0, 256);
+  for (int d = 0; d < 3; ++d)
+    for (int k = 0; k < 4; ++k) {
+      sp.ex_off[d][k] = off;
+      off += align_up(sizeof(int) * (size_t)(k == 0 ? g.pot_terms : g.m0), 256);
+    }
+  for (int d = 0; d < 3; ++d) {  // G-row slices, two copies, 2-byte elements
+    sp.ldg[d] = (int)align_up((size_t)g.n[d] + 64, 8);  // even: 4-byte aligned rows
+    sp.gs_off[d] = off;
+    off += align_up(2 * 2 * (size_t)s * g.m0 * sp.ldg[d], 256);
   }
   sp.bytes = off;
   return sp;
@@ -193,28 +197,45 @@ int choose_kc(const Plan& plan, const Geometry& g, int d, int ypad, int tile, si
 }
 
 int default_slices(tl_precision prec) { return prec == TL_SPLIT_FP16 ? 5 : 6; }
+// beta s + 1 bits of the rounded integer and its bias must fit an int64
+int max_slices(tl_precision prec) { return prec == TL_SPLIT_FP16 ? 6 : 7; }
+
+// Source rows of the worst 64-row split tile: its P rows plus G, AG, SG rows.
+int split_src_rows(const Geometry& g) {
+  const int M = (int)((g.pot_terms + 2) * g.m0), T = (int)g.pot_terms, m0 = g.m0;
+  int worst = 0;
+  for (int row0 = 0; row0 < M; row0 += kSplitTile) {
+    const int r1 = std::min(M, row0 + kSplitTile) - 1, t0 = row0 / m0, t1 = r1 / m0;
+    const int nP = t0 < T ? std::min(t1, T - 1) - t0 + 1 : 0;
+    const int n = nP + (t0 < T ? m0 : 0) + (t0 <= T && T <= t1 ? m0 : 0) +
+                  (t0 <= T + 1 && T + 1 <= t1 ? m0 : 0);
+    worst = std::max(worst, n);
+  }
+  return worst;
+}
 
 }  // namespace
 
 size_t assemble_workspace_bytes(const Geometry& g, tl_precision prec, int n_slices,
                                 int want_blocks) {
-  Plan plan = make_plan(g, want_blocks);
-  if (!is_split(prec)) return plan.bytes;
-  int S = n_slices > 0 ? n_slices : default_slices(prec);
-  return make_split_plan(g, plan, S, plan.bytes).bytes;
+  if (!is_split(prec)) return make_plan(g, want_blocks).bytes;
+  const Plan plan = make_plan(g, want_blocks, kSplitTile, kSplitTileN);
+  const int s = n_slices > 0 ? n_slices : default_slices(prec);
+  return make_split_plan(g, s, plan.bytes).bytes;
 }
 
 tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, const double* SG,
                         const double* P, tl_precision prec, int n_slices, double* H, double* S,
                         void* ws, size_t ws_bytes, int want_blocks, AssemblyPlan* out,
                         int tile_hint) {
-  Plan plan = make_plan(g, want_blocks);
+  Plan plan = is_split(prec) ? make_plan(g, want_blocks, kSplitTile, kSplitTileN)
+                             : make_plan(g, want_blocks);
   const int nsl = is_split(prec) ? (n_slices > 0 ? n_slices : default_slices(prec)) : 0;
-  if (is_split(prec) && (nsl < 2 || nsl > kMaxSlices)) {
-    set_error("n_slices = %d outside [2, %d]", n_slices, kMaxSlices);
+  if (is_split(prec) && (nsl < 2 || nsl > max_slices(prec))) {
+    set_error("n_slices = %d outside [2, %d]", n_slices, max_slices(prec));
     return TL_EINVAL;
   }
-  const SplitPlan sp = make_split_plan(g, plan, nsl, plan.bytes);
+  const SplitPlan sp = make_split_plan(g, std::max(nsl, 2), plan.bytes);
   const size_t need = is_split(prec) ? sp.bytes : plan.bytes;
   if (ws == nullptr || ws_bytes < need) {
     set_error("assembly workspace: need %zu bytes, got %zu", need, ws_bytes);
@@ -287,48 +308,46 @@ tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, co
     if (ap.src_tile == 0)
       for (int d = 0; d < 3; ++d) a.d[d].kc = 0;
   }
-  // split modes: slicing pass and sliced contraction
+  // split modes: row maxima, then the split contraction from the FP64 rows
+  // (64 x 64 tiles: the plan's tiles_n and block counts are for that edge)
   if (is_split(prec)) {
-    SliceArgs& sa = ap.slice;
-    sa.m0 = g.m0;
-    sa.T = (int)g.pot_terms;
-    sa.s = nsl;
-    int rb = 0;
+    RowMaxArgs& ra = ap.rowmax;
+    int nb = 0;
     for (int d = 0; d < 3; ++d) {
-      sa.P[d] = P + g.pot_off[d];
-      sa.G[d] = G + g.basis_off[d];
-      sa.AG[d] = AG + g.basis_off[d];
-      sa.SG[d] = SG + g.basis_off[d];
-      sa.xs[d] = wsb + sp.xs_off[d];
-      sa.ys[d] = wsb + sp.ys_off[d];
-      sa.xscale[d] = (double*)(wsb + sp.xsc_off[d]);
-      sa.yscale[d] = (double*)(wsb + sp.ysc_off[d]);
-      sa.n[d] = g.n[d];
-      sa.M[d] = plan.M[d];
-      sa.ld[d] = (int)align_up((size_t)g.n[d], kSliceAlign);
+      const double* srcs[4] = {P + g.pot_off[d], G + g.basis_off[d], AG + g.basis_off[d],
+                               SG + g.basis_off[d]};
+      for (int k = 0; k < 4; ++k) {
+        ra.src[d][k] = srcs[k];
+        ra.ex[d][k] = (int*)(wsb + sp.ex_off[d][k]);
+        ra.rows[d][k] = k == 0 ? (int)g.pot_terms : g.m0;
+        ra.begin[4 * d + k] = nb;
+        nb += ra.rows[d][k];
+      }
+      ra.n[d] = g.n[d];
+      ra.gs[d] = wsb + sp.gs_off[d];
+      ra.ldg[d] = sp.ldg[d];
     }
-    for (int d = 0; d < 3; ++d) {
-      sa.rows_begin[d] = rb;
-      rb += plan.M[d];
-    }
-    for (int d = 0; d < 3; ++d) {
-      sa.rows_begin[3 + d] = rb;
-      rb += g.m0;
-    }
-    sa.rows_begin[6] = rb;
-    ap.slice_blocks = rb;
+    ra.m0 = g.m0;
+    ra.begin[12] = nb;
+    ap.rowmax_blocks = nb;
     SplitArgs& q = ap.split;
     q.m0 = g.m0;
-    q.s = nsl;
+    q.T = (int)g.pot_terms;
+    int bb = 0;
     for (int d = 0; d < 3; ++d) {
       SplitDimArgs& r = q.d[d];
-      r.xs = wsb + sp.xs_off[d];
-      r.ys = wsb + sp.ys_off[d];
-      r.xscale = (const double*)(wsb + sp.xsc_off[d]);
-      r.yscale = (const double*)(wsb + sp.ysc_off[d]);
+      r.G = G + g.basis_off[d];
+      r.AG = AG + g.basis_off[d];
+      r.SG = SG + g.basis_off[d];
+      r.P = P + g.pot_off[d];
+      r.eP = ra.ex[d][0];
+      r.eG = ra.ex[d][1];
+      r.eA = ra.ex[d][2];
+      r.eS = ra.ex[d][3];
+      r.gs = ra.gs[d];
+      r.ldg = ra.ldg[d];
       r.part = a.d[d].part;
       r.n = g.n[d];
-      r.ld = (int)align_up((size_t)g.n[d], kSliceAlign);
       r.S = g.shifts[d];
       r.cn = a.d[d].cn;
       r.M = plan.M[d];
@@ -336,8 +355,13 @@ tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, co
       r.kchunk = plan.kchunk[d];
       r.ks = plan.ks[d];
       r.tiles_n = plan.tiles_n[d];
-      r.block_begin = a.d[d].block_begin;
+      r.block_begin = bb;
+      bb += plan.blocks[d];
     }
+    ap.contract_blocks = bb;
+    const int rows = split_src_rows(g);
+    ap.split_spt = rows <= 64 ? 2 : 4;  // staging passes of 32 rows
+    ap.split_lds = split_lds_bytes(nsl, 32 * ap.split_spt);
   }
   // partial sums -> compact C_l
   ReduceArgs& ra = ap.reduce;
@@ -374,31 +398,54 @@ tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, co
 
 namespace {
 
+template <typename LowT, int SPT>
+void launch_split_s(const AssemblyPlan& ap, hipStream_t stream, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid((unsigned)ap.contract_blocks), blk(kSplitThreads);
+  const size_t lds = ap.split_lds;
+  switch (ap.n_slices) {
+    case 2: launch_with_events(contract_split_kernel<LowT, 2, SPT>, grid, blk, lds, stream, e0, e1, ap.split); break;
+    case 3: launch_with_events(contract_split_kernel<LowT, 3, SPT>, grid, blk, lds, stream, e0, e1, ap.split); break;
+    case 4: launch_with_events(contract_split_kernel<LowT, 4, SPT>, grid, blk, lds, stream, e0, e1, ap.split); break;
+    case 5: launch_with_events(contract_split_kernel<LowT, 5, SPT>, grid, blk, lds, stream, e0, e1, ap.split); break;
+    case 6: launch_with_events(contract_split_kernel<LowT, 6, SPT>, grid, blk, lds, stream, e0, e1, ap.split); break;
+    default: launch_with_events(contract_split_kernel<LowT, 7, SPT>, grid, blk, lds, stream, e0, e1, ap.split); break;
+  }
+}
+
+template <typename LowT>
+void launch_rowmax_t(const AssemblyPlan& ap, hipStream_t stream) {
+  const dim3 grid((unsigned)ap.rowmax_blocks), blk(256);
+  switch (ap.n_slices) {
+    case 2: hipLaunchKernelGGL((rowmax_kernel<LowT, 2>), grid, blk, 0, stream, ap.rowmax); break;
+    case 3: hipLaunchKernelGGL((rowmax_kernel<LowT, 3>), grid, blk, 0, stream, ap.rowmax); break;
+    case 4: hipLaunchKernelGGL((rowmax_kernel<LowT, 4>), grid, blk, 0, stream, ap.rowmax); break;
+    case 5: hipLaunchKernelGGL((rowmax_kernel<LowT, 5>), grid, blk, 0, stream, ap.rowmax); break;
+    case 6: hipLaunchKernelGGL((rowmax_kernel<LowT, 6>), grid, blk, 0, stream, ap.rowmax); break;
+    default: hipLaunchKernelGGL((rowmax_kernel<LowT, 7>), grid, blk, 0, stream, ap.rowmax); break;
+  }
+}
+
+void launch_rowmax(const AssemblyPlan& ap, hipStream_t stream) {
+  if (ap.prec == TL_SPLIT_BF16)
+    launch_rowmax_t<__bf16>(ap, stream);
+  else
+    launch_rowmax_t<_Float16>(ap, stream);
+}
+
 template <typename LowT>
 void launch_split_contraction(const AssemblyPlan& ap, hipStream_t stream, hipEvent_t e0,
                               hipEvent_t e1) {
-  const dim3 grid((unsigned)ap.contract_blocks), blk(256);
-  switch (ap.n_slices) {
-    case 2: launch_with_events(contract_split_kernel<LowT, 2>, grid, blk, 0, stream, e0, e1, ap.split); break;
-    case 3: launch_with_events(contract_split_kernel<LowT, 3>, grid, blk, 0, stream, e0, e1, ap.split); break;
-    case 4: launch_with_events(contract_split_kernel<LowT, 4>, grid, blk, 0, stream, e0, e1, ap.split); break;
-    case 5: launch_with_events(contract_split_kernel<LowT, 5>, grid, blk, 0, stream, e0, e1, ap.split); break;
-    case 6: launch_with_events(contract_split_kernel<LowT, 6>, grid, blk, 0, stream, e0, e1, ap.split); break;
-    case 7: launch_with_events(contract_split_kernel<LowT, 7>, grid, blk, 0, stream, e0, e1, ap.split); break;
-    default: launch_with_events(contract_split_kernel<LowT, 8>, grid, blk, 0, stream, e0, e1, ap.split); break;
-  }
+  if (ap.split_spt <= 2)
+    launch_split_s<LowT, 2>(ap, stream, e0, e1);
+  else
+    launch_split_s<LowT, 4>(ap, stream, e0, e1);
 }
 
 }  // namespace
 
 tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream) {
-  if (ap.prec == TL_SPLIT_BF16) {
-    hipLaunchKernelGGL(slice_kernel<__bf16>, dim3((unsigned)ap.slice_blocks), dim3(256), 0, stream,
-                       ap.slice);
-    TL_CHECK_LAUNCH();
-  } else if (ap.prec == TL_SPLIT_FP16) {
-    hipLaunchKernelGGL(slice_kernel<_Float16>, dim3((unsigned)ap.slice_blocks), dim3(256), 0,
-                       stream, ap.slice);
+  if (is_split(ap.prec)) {
+    launch_rowmax(ap, stream);
     TL_CHECK_LAUNCH();
   }
   // the profiling events (if set) are attached to the contraction launch

@@ -19,7 +19,7 @@ namespace {
 enum Stage {
   kBasis = 0,
   kPotential,
-  kSlice,
+  kRowMax,
   kContract,
   kReduce,
   kCombine,
@@ -79,10 +79,10 @@ __global__ __launch_bounds__(256) void batch_potential_kernel(const BatchDesc* _
   dev::potential_body(J.pot.direct, J.pot.fold, J.pot.quad, J.T, J.pot.fold_blocks, J.pot.P, lb);
 }
 
-template <typename LowT>
-__global__ __launch_bounds__(256) void batch_slice_kernel(const BatchDesc* __restrict__ d) {
-  TL_BATCH_LOCATE(kSlice)
-  dev::slice_body<LowT>(J.asmb.slice, (int)lb);
+template <typename LowT, int S>
+__global__ __launch_bounds__(256) void batch_rowmax_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kRowMax)
+  dev::rowmax_body<LowT, S>(J.asmb.rowmax, (int)lb);
 }
 
 __global__ __launch_bounds__(256) void batch_contract_f64_kernel(const BatchDesc* __restrict__ d) {
@@ -104,11 +104,11 @@ __global__ __launch_bounds__(256) void batch_contract_f32_kernel(const BatchDesc
   dev::contract_f32_body(J.asmb.contract, (int)lb);
 }
 
-template <typename LowT, int S>
-__global__ __launch_bounds__(256) void batch_contract_split_kernel(
+template <typename LowT, int S, int SPT>
+__global__ __launch_bounds__(dev::kSplitThreads) void batch_contract_split_kernel(
     const BatchDesc* __restrict__ d) {
   TL_BATCH_LOCATE(kContract)
-  dev::contract_split_body<LowT, S>(J.asmb.split, (int)lb);
+  dev::contract_split_src_body<LowT, S, SPT>(J.asmb.split, (int)lb);
 }
 
 __global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchDesc* __restrict__ d) {
@@ -210,6 +210,9 @@ extern "C" tl_status tl_batch_plan_create(const tl_system* systems, int count, t
   out->n_slices = (prec == TL_SPLIT_BF16 || prec == TL_SPLIT_FP16)
                       ? (n_slices > 0 ? n_slices : (prec == TL_SPLIT_FP16 ? 5 : 6))
                       : 0;
+  if (out->n_slices)
+    TL_REQUIRE(out->n_slices >= 2 && out->n_slices <= (prec == TL_SPLIT_FP16 ? 6 : 7),
+               "n_slices = %d outside [2, %d]", out->n_slices, prec == TL_SPLIT_FP16 ? 6 : 7);
   out->want_blocks = want_blocks;
   out->desc_bytes = sizeof(BatchDesc);
   for (int i = 0; i < count; ++i) {
@@ -288,7 +291,7 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
     int64_t blocks[kStages];
     blocks[kBasis] = ceil_div(g.basis_elems, 256);
     blocks[kPotential] = (int64_t)J.pot.fold_blocks + J.pot.direct_blocks;
-    blocks[kSlice] = J.asmb.slice_blocks;
+    blocks[kRowMax] = J.asmb.rowmax_blocks;
     blocks[kContract] = J.asmb.contract_blocks;
     blocks[kReduce] = ceil_div(J.asmb.reduce_total, 256);
     blocks[kCombine] = ceil_div(J.asmb.combine_total, 4);
@@ -309,19 +312,40 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
 
 namespace {
 
+template <typename LowT, int SPT>
+void launch_batch_split_s(int S, unsigned grid, size_t lds, const BatchDesc* d,
+                          hipStream_t stream, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 g(grid), b(dev::kSplitThreads);
+  switch (S) {
+    case 2: launch_with_events(batch_contract_split_kernel<LowT, 2, SPT>, g, b, lds, stream, e0, e1, d); break;
+    case 3: launch_with_events(batch_contract_split_kernel<LowT, 3, SPT>, g, b, lds, stream, e0, e1, d); break;
+    case 4: launch_with_events(batch_contract_split_kernel<LowT, 4, SPT>, g, b, lds, stream, e0, e1, d); break;
+    case 5: launch_with_events(batch_contract_split_kernel<LowT, 5, SPT>, g, b, lds, stream, e0, e1, d); break;
+    case 6: launch_with_events(batch_contract_split_kernel<LowT, 6, SPT>, g, b, lds, stream, e0, e1, d); break;
+    default: launch_with_events(batch_contract_split_kernel<LowT, 7, SPT>, g, b, lds, stream, e0, e1, d); break;
+  }
+}
+
 template <typename LowT>
-void launch_batch_split(int S, unsigned grid, const BatchDesc* d, hipStream_t stream, hipEvent_t e0,
-                        hipEvent_t e1) {
+void launch_batch_rowmax(int S, unsigned grid, const BatchDesc* d, hipStream_t stream) {
   const dim3 g(grid), b(256);
   switch (S) {
-    case 2: launch_with_events(batch_contract_split_kernel<LowT, 2>, g, b, 0, stream, e0, e1, d); break;
-    case 3: launch_with_events(batch_contract_split_kernel<LowT, 3>, g, b, 0, stream, e0, e1, d); break;
-    case 4: launch_with_events(batch_contract_split_kernel<LowT, 4>, g, b, 0, stream, e0, e1, d); break;
-    case 5: launch_with_events(batch_contract_split_kernel<LowT, 5>, g, b, 0, stream, e0, e1, d); break;
-    case 6: launch_with_events(batch_contract_split_kernel<LowT, 6>, g, b, 0, stream, e0, e1, d); break;
-    case 7: launch_with_events(batch_contract_split_kernel<LowT, 7>, g, b, 0, stream, e0, e1, d); break;
-    default: launch_with_events(batch_contract_split_kernel<LowT, 8>, g, b, 0, stream, e0, e1, d); break;
+    case 2: hipLaunchKernelGGL((batch_rowmax_kernel<LowT, 2>), g, b, 0, stream, d); break;
+    case 3: hipLaunchKernelGGL((batch_rowmax_kernel<LowT, 3>), g, b, 0, stream, d); break;
+    case 4: hipLaunchKernelGGL((batch_rowmax_kernel<LowT, 4>), g, b, 0, stream, d); break;
+    case 5: hipLaunchKernelGGL((batch_rowmax_kernel<LowT, 5>), g, b, 0, stream, d); break;
+    case 6: hipLaunchKernelGGL((batch_rowmax_kernel<LowT, 6>), g, b, 0, stream, d); break;
+    default: hipLaunchKernelGGL((batch_rowmax_kernel<LowT, 7>), g, b, 0, stream, d); break;
   }
+}
+
+template <typename LowT>
+void launch_batch_split(int S, int spt, unsigned grid, size_t lds, const BatchDesc* d,
+                        hipStream_t stream, hipEvent_t e0, hipEvent_t e1) {
+  if (spt <= 2)
+    launch_batch_split_s<LowT, 2>(S, grid, lds, d, stream, e0, e1);
+  else
+    launch_batch_split_s<LowT, 4>(S, grid, lds, d, stream, e0, e1);
 }
 
 }  // namespace
@@ -348,21 +372,28 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
                        p0, p1, d);
     TL_CHECK_LAUNCH();
   }
-  if (prec == TL_SPLIT_BF16) {
-    hipLaunchKernelGGL(batch_slice_kernel<__bf16>, dim3(blocks(kSlice)), dim3(256), 0, stream, d);
+  size_t split_lds = 0;
+  int split_spt = 2;
+  if (prec == TL_SPLIT_BF16 || prec == TL_SPLIT_FP16) {
+    if (prec == TL_SPLIT_BF16)
+      launch_batch_rowmax<__bf16>(plan->n_slices, blocks(kRowMax), d, stream);
+    else
+      launch_batch_rowmax<_Float16>(plan->n_slices, blocks(kRowMax), d, stream);
     TL_CHECK_LAUNCH();
-  } else if (prec == TL_SPLIT_FP16) {
-    hipLaunchKernelGGL(batch_slice_kernel<_Float16>, dim3(blocks(kSlice)), dim3(256), 0, stream,
-                       d);
-    TL_CHECK_LAUNCH();
+    for (int i = 0; i < hd->count; ++i) {
+      split_lds = std::max(split_lds, hd->job[i].asmb.split_lds);
+      split_spt = std::max(split_spt, hd->job[i].asmb.split_spt);
+    }
   }
   // the profiling events (if set) are attached to the contraction launch
   const hipEvent_t e0 = ev0, e1 = ev1;
   const dim3 cgrid(blocks(kContract)), cblk(256);
   if (prec == TL_SPLIT_BF16)
-    launch_batch_split<__bf16>(plan->n_slices, blocks(kContract), d, stream, e0, e1);
+    launch_batch_split<__bf16>(plan->n_slices, split_spt, blocks(kContract), split_lds, d, stream,
+                               e0, e1);
   else if (prec == TL_SPLIT_FP16)
-    launch_batch_split<_Float16>(plan->n_slices, blocks(kContract), d, stream, e0, e1);
+    launch_batch_split<_Float16>(plan->n_slices, split_spt, blocks(kContract), split_lds, d,
+                                 stream, e0, e1);
   else if (prec == TL_FP32)
     launch_with_events(batch_contract_f32_kernel, cgrid, cblk, 0, stream, e0, e1, d);
   else {

@@ -454,17 +454,24 @@ __device__ inline void contract_f32_body(const ContractArgs& a, int b) {
 
 // ---------------------------------------------------------------- split modes
 // Operand splitting in the manner of Ozaki, Ogita, Oishi & Rump (2012): each
-// row r of X (and of G) is scaled by a power of two sigma_r >= max|row|, and
-// the scaled values are cut into integer slices
-//   x/sigma = sum_k n_k 2^(-k beta),  |n_1| <= 2^beta, |n_k| <= 2^(beta-1),
-// each exactly representable in bf16 (beta = 8) or fp16 (beta = 9).  A slice
-// product summed over one 32-node MFMA (16x16x32) stays below 2^24 and is
-// exact in FP32; all products of one level a + b are accumulated in FP32 over
-// one MFMA step and then added to a per-level FP64 accumulator.  Only the
-// products with a + b <= s + 1 are formed (triangular truncation).
+// row r of X (and each column of Y) is scaled by a power of two
+// sigma_r >= max|row|, and the scaled value is cut into integer slices
+//   x / sigma = sum_k d_k 2^(-k beta),  |d_1| <= 2^beta, |d_k| <= 2^(beta-1),
+// each exactly representable in bf16 (beta = 8) or fp16 (beta = 9).  The
+// slices of one value come from the bits of the integer N = rint(x 2^(beta s)
+// / sigma): with a bias of 2^(beta-1) in every lower field, the fields minus
+// the bias are the balanced digits d_k (k >= 2) and the top field is d_1.
+// Slice products are integers below 2^(2 beta); one 32-node MFMA sums 32 of
+// them per pair, so each level a + b stays exact in its FP32 accumulator up
+// to level 1 over two MFMA steps (higher levels carry their rounding below
+// 2^-52 of the entry), and every 64 nodes the level sums are added to one
+// FP64 accumulator with their weights 2^(-beta (a + b + 2)).  Only the
+// products with a + b < s are formed (triangular truncation).
 
 constexpr int kMaxSlices = 8;
-constexpr int kSliceAlign = 8;       // slice rows padded to a multiple of 8 nodes
+constexpr int kSplitTile = 64;  // rows and columns of a split workgroup tile
+constexpr int kSplitK = 32;     // nodes per MFMA step (16x16x32)
+constexpr int kSplitLd = 32;    // halves per LDS slice row (conflict-free for 16-byte reads)
 
 template <typename T>
 struct LowTraits;
@@ -477,85 +484,77 @@ struct LowTraits<_Float16> {
   static constexpr int beta = 9;
 };
 
-struct SliceArgs {
-  const double* P[3];
-  const double* G[3];
-  const double* AG[3];
-  const double* SG[3];
-  void* xs[3];          // [s][M][n] slices of X rows
-  void* ys[3];          // [s][m0][n] slices of G rows
-  double* xscale[3];    // [M]
-  double* yscale[3];    // [m0]
-  int n[3], M[3], ld[3];  // ld: padded row stride of the slices
-  int rows_begin[7];    // X rows of dims 0..2, then G rows of dims 0..2
-  int m0, T, s;
+// Row maxima of the contraction's source rows as power-of-two exponents
+// e with 2^e > max|row| (0 for a zero row): P rows (terms), G, AG and SG rows.
+// The G rows (the Y operands, shifted copies of m0 rows) are also sliced
+// here, once: gs[d] holds [2][s][m0][ldg] slices, copy 0 at node j (mod n),
+// copy 1 one node later, so that every run of 4 nodes starts on a 4-byte
+// boundary in one of the copies (ldg >= n + 64, a multiple of 8, the tail
+// cyclic).
+struct RowMaxArgs {
+  const double* src[3][4];  // per dim: P, G, AG, SG
+  int* ex[3][4];            // per dim: exponents of the P, G, AG, SG rows
+  int rows[3][4];           // per dim: T, m0, m0, m0
+  int begin[13];            // workgroup prefix over the 12 (dim, kind) row sets
+  int n[3];
+  void* gs[3];              // per dim: slices of the G rows (LowT)
+  int ldg[3];
+  int m0;
 };
 
-// Workgroup per row: max |value| (power-of-two scale), then the slices.
-template <typename LowT>
-__device__ inline void slice_body(const SliceArgs& a, int b) {
-  constexpr int beta = LowTraits<LowT>::beta;
+template <typename LowT, int S>
+__device__ inline void slice_one(double x, int e, LowT* dst, int64_t qstride);
+
+template <typename LowT, int S>
+__device__ inline void rowmax_body(const RowMaxArgs& a, int b) {
   __shared__ double wmax[4];
+  __shared__ int eshared;
   int k = 0;
-  while (k < 6 && b >= a.rows_begin[k + 1]) ++k;
-  const bool isx = k < 3;
-  const int d = isx ? k : k - 3;
-  const int row = b - a.rows_begin[k];
+  while (k < 11 && b >= a.begin[k + 1]) ++k;
+  const int d = k >> 2, kind = k & 3;
+  const int row = b - a.begin[k];
   const int n = a.n[d];
-  const double* base;
-  const double* pot = nullptr;
-  if (isx) {
-    const int t = row / a.m0, nu = row - t * a.m0;
-    base = (t < a.T ? a.G[d] : (t == a.T ? a.AG[d] : a.SG[d])) + (int64_t)nu * n;
-    if (t < a.T) pot = a.P[d] + (int64_t)t * n;
-  } else {
-    base = a.G[d] + (int64_t)row * n;
-  }
+  const double* src = a.src[d][kind] + (int64_t)row * n;
   double mx = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double v = pot ? pot[i] * base[i] : base[i];
-    mx = fmax(mx, fabs(v));
-  }
-  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(src[i]));
+  mx = wave_max_dpp(mx);
   if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
   __syncthreads();
-  mx = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
-  // sigma = 2^e >= mx, so |x / sigma| <= 1 exactly
-  int e = 0;
-  if (mx > 0.0) {
-    frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+  if (threadIdx.x == 0) {
+    mx = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    int e = 0;
+    if (mx > 0.0) frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1): 2^e > mx
+    a.ex[d][kind][row] = e;
+    eshared = e;
   }
-  const double sigma = ldexp(1.0, e), inv = ldexp(1.0, -e);
-  if (threadIdx.x == 0) (isx ? a.xscale[d] : a.yscale[d])[row] = sigma;
-  LowT* out = (LowT*)(isx ? a.xs[d] : a.ys[d]);
-  const int64_t rows = isx ? a.M[d] : a.m0;
-  const int ld = a.ld[d];
-  for (int i = threadIdx.x; i < ld; i += blockDim.x) {
-    if (i >= n) {  // zero padding up to the aligned stride
-      for (int q = 1; q <= a.s; ++q) out[((int64_t)(q - 1) * rows + row) * ld + i] = (LowT)0.0f;
-      continue;
-    }
-    double v = (pot ? pot[i] * base[i] : base[i]) * inv;
-    for (int q = 1; q <= a.s; ++q) {
-      double sc = ldexp(1.0, q * beta);
-      double nk = rint(v * sc);
-      v = fma(-nk, ldexp(1.0, -q * beta), v);
-      out[((int64_t)(q - 1) * rows + row) * ld + i] = (LowT)nk;
-    }
+  if (kind != 1) return;  // uniform per workgroup
+  __syncthreads();
+  const int e = eshared, ldg = a.ldg[d];
+  LowT* gs = (LowT*)a.gs[d];
+  const int64_t qstride = (int64_t)a.m0 * ldg;
+  for (int j = threadIdx.x; j < ldg; j += blockDim.x) {
+    const int n0 = j % n, n1 = (j + n - 1) % n;
+    slice_one<LowT, S>(src[n0], e, gs + (int64_t)row * ldg + j, qstride);
+    slice_one<LowT, S>(src[n1], e, gs + ((int64_t)S * a.m0 + row) * ldg + j, qstride);
   }
 }
 
 struct SplitDimArgs {
-  const void* xs;       // [s][M][ld]
-  const void* ys;       // [s][m0][ld]
-  const double* xscale;
-  const double* yscale;
-  double* part;
-  int n, ld, S, cn, M, N, kchunk, ks, tiles_n, block_begin;
+  const double* G;
+  const double* AG;
+  const double* SG;
+  const double* P;
+  const int* eP;     // exponents of the P, G, AG, SG rows (rowmax_body)
+  const int* eG;
+  const int* eA;
+  const int* eS;
+  const void* gs;    // slices of the G rows, [2][s][m0][ldg] (rowmax_body)
+  double* part;      // [ks][M][N]
+  int n, S, cn, M, N, kchunk, ks, tiles_n, block_begin, ldg;
 };
 struct SplitArgs {
   SplitDimArgs d[3];
-  int m0, s;
+  int m0, T;
 };
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -578,138 +577,256 @@ struct Vec8<_Float16> {
   }
 };
 
-template <typename T, int N>
-struct VecN {
-  typedef T type __attribute__((ext_vector_type(N)));
-};
+// Slices of NV values scaled by 2^-e, written as NV-element vectors of slice
+// q to dst[q * qstride] (LDS).
+template <typename LowT, int S, int NV>
+__device__ inline void slice_values(const double (&x)[NV], int e, LowT* dst, int qstride) {
+  typedef LowT vN __attribute__((ext_vector_type(NV)));
+  constexpr int beta = LowTraits<LowT>::beta;
+  constexpr uint64_t half = uint64_t(1) << (beta - 1);
+  constexpr uint64_t mask = (uint64_t(1) << beta) - 1;
+  // bias 2^(beta-1) in each of the s-1 lower fields
+  constexpr uint64_t bias = [] {
+    uint64_t b = 0;
+    for (int k = 0; k < S - 1; ++k) b |= half << (beta * k);
+    return b;
+  }();
+  vN out[S];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const double N = rint(ldexp(x[j], beta * S - e));  // |N| <= 2^(beta s), an integer
+    const double hi = floor(N * 0x1p-32);
+    const double lo = fma(-hi, 0x1p32, N);               // exact, in [0, 2^32)
+    const int64_t Ni = (int64_t)(((uint64_t)(int64_t)(int)hi << 32) | (uint64_t)(uint32_t)lo);
+    const uint64_t u = (uint64_t)Ni + bias;
+#pragma unroll
+    for (int k = 1; k < S; ++k) {  // slice S-k: field k-1 from the bottom
+      const int dv = (int)((u >> (beta * (k - 1))) & mask) - (int)half;
+      out[S - k][j] = (LowT)(float)dv;
+    }
+    out[0][j] = (LowT)(float)(int)((int64_t)u >> (beta * (S - 1)));
+  }
+#pragma unroll
+  for (int q = 0; q < S; ++q) *(vN*)(dst + q * qstride) = out[q];
+}
 
-// Stages of 64 nodes (32 for more than six slices, to fit LDS); a thread
-// stages NPT consecutive nodes of one X row and of one Y column per slice
-// with one vector load and one vector LDS store each.  All products of a
-// level are accumulated in FP32 over the stage (exact for the integer
-// slices, see above) and added once to the level's FP64 accumulator.
+// One value's s slices, slice q at dst[q * qstride].
 template <typename LowT, int S>
-__device__ inline void contract_split_body(const SplitArgs& a, int b) {
+__device__ inline void slice_one(double x, int e, LowT* dst, int64_t qstride) {
+  constexpr int beta = LowTraits<LowT>::beta;
+  constexpr uint64_t half = uint64_t(1) << (beta - 1);
+  constexpr uint64_t mask = (uint64_t(1) << beta) - 1;
+  constexpr uint64_t bias = [] {
+    uint64_t b = 0;
+    for (int k = 0; k < S - 1; ++k) b |= half << (beta * k);
+    return b;
+  }();
+  const double N = rint(ldexp(x, beta * S - e));
+  const double hi = floor(N * 0x1p-32);
+  const double lo = fma(-hi, 0x1p32, N);
+  const int64_t Ni = (int64_t)(((uint64_t)(int64_t)(int)hi << 32) | (uint64_t)(uint32_t)lo);
+  const uint64_t u = (uint64_t)Ni + bias;
+#pragma unroll
+  for (int k = 1; k < S; ++k)
+    dst[(S - k) * qstride] = (LowT)(float)((int)((u >> (beta * (k - 1))) & mask) - (int)half);
+  dst[0] = (LowT)(float)(int)((int64_t)u >> (beta * (S - 1)));
+}
+
+// Split contraction from FP64 source rows, 64 x 128 tiles (16 waves, each a
+// 32 x 16 quadrant of 2 x 1 MFMA blocks).  Per 32-node step the workgroup
+// stages the distinct P and G/AG/SG rows of its X rows in LDS, forms X =
+// p_t g_nu and slices it into LDS once (shared by the 8 waves of a row
+// half); the Y columns g_mu(. - s a) are copied from the G-row slices of the
+// pre-pass (two aligned copies, L2-resident); then the triangular slice
+// products run on BF16/FP16 MFMA with FP32 level accumulators.  X slices
+// never reach HBM.  Dynamic LDS: X slices s 64 kSplitLd halves, Y slices
+// s 128 kSplitLd halves, then the FP64 X sources (the tile's P rows and its
+// G, AG, SG rows, at most 32 SPT) at 32 nodes.  beta s must stay below 63
+// (the integer N and its bias).
+constexpr int kSplitTileN = 128;
+constexpr int kSplitThreads = 1024;
+
+template <typename LowT, int S, int SPT>
+__device__ inline void contract_split_src_body(const SplitArgs& a, int b) {
   typedef typename Vec8<LowT>::type v8;
   constexpr int beta = LowTraits<LowT>::beta;
-  constexpr int STG = S <= 6 ? 64 : 32;
-  constexpr int NPT = STG / 8;
-  constexpr int LDS_ROW = STG + 8;
-  typedef typename VecN<LowT, NPT>::type vrun;
-  __shared__ __attribute__((aligned(16))) LowT Xl[S][kBM][LDS_ROW];
-  __shared__ __attribute__((aligned(16))) LowT Yl[S][kBN][LDS_ROW];
+  constexpr int TM = kSplitTile, TN = kSplitTileN, LD = kSplitLd;
+  extern __shared__ __attribute__((aligned(16))) double smem_d[];
+  LowT* Xs = (LowT*)smem_d;           // [S][64][LD]
+  LowT* Ys = Xs + S * TM * LD;        // [S][128][LD]
+  double* src = (double*)(Ys + S * TN * LD);  // FP64 source rows, [rows][32]
   const int dd = b >= a.d[2].block_begin ? 2 : (b >= a.d[1].block_begin ? 1 : 0);
   const SplitDimArgs& p = a.d[dd];
   const int local = b - p.block_begin;
   const int z = local % p.ks;
   const int rest = local / p.ks;
-  const int col0 = (rest % p.tiles_n) * kBN;
-  const int row0 = (rest / p.tiles_n) * kBM;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int kbeg = z * p.kchunk;
-  const int kend = min(p.n, kbeg + p.kchunk);
-  const int wm = wave >> 1, wn = wave & 1;
-  const LowT* xs = (const LowT*)p.xs;
-  const LowT* ys = (const LowT*)p.ys;
-  const int sr = tid >> 3;              // row / column within the tile (0..31)
-  const int sk = (tid & 7) * NPT;       // first node of the thread's run
-  const int xrow = row0 + sr, ycol = col0 + sr;
-  const bool xok = xrow < p.M, yok = ycol < p.N;
-  const int mu = yok ? ycol / p.S : 0;
-  const int ysh = yok ? (ycol - mu * p.S) * p.cn : 0;
-  const int64_t xstride = (int64_t)p.M * p.ld, ystride = (int64_t)a.m0 * p.ld;
-  const LowT* xbase = xs + (int64_t)xrow * p.ld;
-  const LowT* ybase = ys + (int64_t)mu * p.ld;
-  vrun xr[S], yr[S];
-  auto stage = [&](int k0) {
-    const int i0 = k0 + sk;
-    // X: rows are padded to a multiple of 8 nodes, runs are aligned
-    if (xok && i0 + NPT <= kend) {
-#pragma unroll
-      for (int q = 0; q < S; ++q) xr[q] = *(const vrun*)(xbase + q * xstride + i0);
+  const int col0 = (rest % p.tiles_n) * TN;
+  const int row0 = (rest / p.tiles_n) * TM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 3, wn = wave & 7;
+  const int kbeg = z * p.kchunk, kend = min(p.n, kbeg + p.kchunk);
+  const int m0 = a.m0, T = a.T;
+  // source rows of the tile: P rows t0..t0+nP-1, then G, AG, SG blocks of m0
+  const int r1 = min(p.M, row0 + TM) - 1;
+  const int t0 = row0 / m0, t1 = r1 / m0;
+  const int nP = t0 < T ? min(t1, T - 1) - t0 + 1 : 0;
+  const bool hasG = t0 < T, hasA = t0 <= T && T <= t1, hasS = t0 <= T + 1 && T + 1 <= t1;
+  const int offG = nP, offA = offG + (hasG ? m0 : 0), offS = offA + (hasA ? m0 : 0);
+  const int nsrc = offS + (hasS ? m0 : 0);
+  // this thread slices 2 nodes (k = 2 (tid & 15) ..) of X row tid / 16
+  const int xr = tid >> 4, xk = (tid & 15) * 2;
+  const int xrow = row0 + xr;
+  const bool xok = xrow < p.M;
+  int ex = 0, xa = -1, xb = 0;
+  if (xok) {
+    const int xt = xrow / m0, xnu = xrow - xt * m0;
+    if (xt < T) {
+      xa = xt - t0;
+      xb = offG + xnu;
+      ex = p.eP[xt] + p.eG[xnu];
+    } else if (xt == T) {
+      xb = offA + xnu;
+      ex = p.eA[xnu];
     } else {
-#pragma unroll
-      for (int q = 0; q < S; ++q)
-#pragma unroll
-        for (int e = 0; e < NPT; ++e)
-          xr[q][e] = (xok && i0 + e < kend) ? xbase[q * xstride + i0 + e] : (LowT)0.0f;
+      xb = offS + xnu;
+      ex = p.eS[xnu];
     }
-    // Y: the cyclic shift may misalign the run or wrap around the torus
-    int src0 = i0 - ysh;
-    if (src0 < 0) src0 += p.n;
-    if (yok && i0 + NPT <= kend && src0 % NPT == 0 && src0 + NPT <= p.n) {
-#pragma unroll
-      for (int q = 0; q < S; ++q) yr[q] = *(const vrun*)(ybase + q * ystride + src0);
-    } else {
-#pragma unroll
-      for (int e = 0; e < NPT; ++e) {
-        int src = src0 + e;
-        if (src >= p.n) src -= p.n;
-        const bool ok = yok && i0 + e < kend;
-#pragma unroll
-        for (int q = 0; q < S; ++q) yr[q][e] = ok ? ybase[q * ystride + src] : (LowT)0.0f;
-      }
-    }
+  }
+  // and copies 4 nodes (k = 4 (tid & 7) ..) of Y column tid / 8: the
+  // pre-sliced G row of mu at nodes k - s cn (mod n), from the copy in which
+  // that run starts on a 4-byte boundary
+  const int yc = tid >> 3, yk = (tid & 7) * 4;
+  const int ycol = col0 + yc;
+  const bool yok = ycol < p.N;
+  const int ymu = yok ? ycol / p.S : 0;
+  const int ysh = yok ? (ycol - ymu * p.S) * p.cn : 0;
+  const LowT* gsl = (const LowT*)p.gs;
+  const int64_t gq = (int64_t)m0 * p.ldg;
+  // staging of the FP64 X sources: rows of 32 nodes, 32 rows per pass
+  auto src_row = [&](int r) -> const double* {
+    if (r < offG) return p.P + (int64_t)(t0 + r) * p.n;
+    if (r < offA) return p.G + (int64_t)(r - offG) * p.n;
+    if (r < offS) return p.AG + (int64_t)(r - offA) * p.n;
+    return p.SG + (int64_t)(r - offS) * p.n;
   };
-  auto commit = [&]() {
+  const int skn = tid & 31, srr = tid >> 5;
+  // the next step's loads are issued before this step's MFMAs (registers);
+  // the sources reach LDS after them, the Y slices after the barrier.  Nodes
+  // past the chunk end have X = 0 (zero sources): their Y slices need no mask.
+  double sv[SPT];
+  uint2 yw[S];
+  auto load = [&](int k0) {
+    const int kn = k0 + skn;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int r = srr + 32 * u;
+      sv[u] = (r < nsrc && kn < kend) ? src_row(r)[kn] : 0.0;
+    }
+    int node = k0 + yk - ysh;
+    if (node < 0) node += p.n;
+    if (node >= p.n) node -= p.n;
+    const int cp = node & 1;
+    const uint32_t* g32 =
+        (const uint32_t*)(gsl + (cp * S * m0 + ymu) * (int64_t)p.ldg) + ((node + cp) >> 1);
 #pragma unroll
     for (int q = 0; q < S; ++q) {
-      *(vrun*)&Xl[q][sr][sk] = xr[q];
-      *(vrun*)&Yl[q][sr][sk] = yr[q];
+      const uint32_t* gq32 = g32 + q * (gq >> 1);
+      yw[q] = make_uint2(gq32[0], gq32[1]);
     }
   };
-  double acc[S][4];
+  auto store_src = [&]() {  // src is read by slice_step only: may overlap the MFMAs
 #pragma unroll
-  for (int l = 0; l < S; ++l)
+    for (int u = 0; u < SPT; ++u) {
+      const int r = srr + 32 * u;
+      if (r < nsrc) src[r * kSplitK + skn] = sv[u];
+    }
+  };
+  auto slice_step = [&]() {  // writes Xs and Ys: after the barrier that ends the MFMAs
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[l][r] = 0.0;
-  stage(kbeg);
-  commit();
-  __syncthreads();
-  for (int k0 = kbeg; k0 < kend; k0 += STG) {
-    const bool more = k0 + STG < kend;
-    if (more) stage(k0 + STG);
-    f32x4 c32[S];
+    for (int q = 0; q < S; ++q) *(uint2*)(Ys + (q * TN + yc) * LD + yk) = yw[q];
+    double xv[2];
 #pragma unroll
-    for (int l = 0; l < S; ++l) c32[l] = {0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 2; ++j) {
+      const double g = src[xb * kSplitK + xk + j];
+      xv[j] = xok ? (xa >= 0 ? src[xa * kSplitK + xk + j] * g : g) : 0.0;
+    }
+    slice_values<LowT, S, 2>(xv, ex, Xs + xr * LD + xk, TM * LD);
+  };
+  f32x4 c32[2][S];
+  f64x4 acc[2];
 #pragma unroll
-    for (int kstep = 0; kstep < STG / 32; ++kstep) {
-      v8 av[S], bv[S];
+  for (int rb = 0; rb < 2; ++rb) {
+    acc[rb] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < S; ++q) {
-        av[q] = *(const v8*)&Xl[q][wm * 16 + (lane & 15)][32 * kstep + 8 * (lane >> 4)];
-        bv[q] = *(const v8*)&Yl[q][wn * 16 + (lane & 15)][32 * kstep + 8 * (lane >> 4)];
+    for (int l = 0; l < S; ++l) c32[rb][l] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  auto flush = [&]() {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int l = S - 1; l >= 0; --l) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[rb][r] = fma((double)c32[rb][l][r], ldexp(1.0, -beta * (l + 2)), acc[rb][r]);
+        c32[rb][l] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
-      // level l = qa + qb (0-based slices), l = 0..S-1; consecutive MFMAs
-      // feed different levels so that none waits on the previous result
+  };
+  load(kbeg);
+  store_src();
+  __syncthreads();
+  slice_step();
+  __syncthreads();
+  int step = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += kSplitK, ++step) {
+    const bool more = k0 + kSplitK < kend;
+    if (more) load(k0 + kSplitK);  // in flight during the MFMAs
+    {
+      v8 bv[S];
 #pragma unroll
-      for (int qa = 0; qa < S; ++qa)
+      for (int q = 0; q < S; ++q)
+        bv[q] = *(const v8*)(Ys + (q * TN + wn * 16 + (lane & 15)) * LD + 8 * (lane >> 4));
 #pragma unroll
-        for (int qb = 0; qa + qb < S; ++qb)
-          c32[qa + qb] = Vec8<LowT>::mfma(av[qa], bv[qb], c32[qa + qb]);
+      for (int rb = 0; rb < 2; ++rb) {
+        v8 av[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+          av[q] = *(const v8*)(Xs + (q * TM + wm * 32 + rb * 16 + (lane & 15)) * LD +
+                               8 * (lane >> 4));
+        // level l = qa + qb; consecutive MFMAs feed different accumulators
+#pragma unroll
+        for (int qa = 0; qa < S; ++qa)
+#pragma unroll
+          for (int qb = 0; qa + qb < S; ++qb)
+            c32[rb][qa + qb] = Vec8<LowT>::mfma(av[qa], bv[qb], c32[rb][qa + qb]);
+      }
     }
-#pragma unroll
-    for (int l = 0; l < S; ++l)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[l][r] += (double)c32[l][r];
-    __syncthreads();
-    if (more) commit();
-    __syncthreads();
+    if ((step & 1) || !more) flush();
+    if (more) store_src();
+    __syncthreads();  // every wave is done with this step's slices
+    if (more) {
+      slice_step();
+      __syncthreads();
+    }
   }
+  // f32 16x16x32 result layout: register r of lane l holds D[4 (l / 16) + r][l % 16]
   const int col = col0 + wn * 16 + (lane & 15);
-  const double ysc = col < p.N ? p.yscale[col / p.S] : 0.0;
+  if (col >= p.N) return;
+  const int ecol = p.eG[col / p.S];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    int row = row0 + wm * 16 + 4 * (lane >> 4) + r;
-    if (row < p.M && col < p.N) {
-      double v = 0.0;
+  for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int l = S - 1; l >= 0; --l) v += ldexp(acc[l][r], -(l + 2) * beta);
-      p.part[((int64_t)z * p.M + row) * p.N + col] = v * p.xscale[row] * ysc;
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + wm * 32 + rb * 16 + 4 * (lane >> 4) + r;
+      if (row >= p.M) continue;
+      const int t = row / m0, nu = row - t * m0;
+      const int erow = t < T ? p.eP[t] + p.eG[nu] : (t == T ? p.eA[nu] : p.eS[nu]);
+      p.part[((int64_t)z * p.M + row) * p.N + col] = ldexp(acc[rb][r], erow + ecol);
     }
-  }
+}
+
+__host__ __device__ inline size_t split_lds_bytes(int s, int nsrc_max) {
+  return sizeof(_Float16) * (size_t)s * (kSplitTile + kSplitTileN) * kSplitLd +
+         sizeof(double) * (size_t)nsrc_max * kSplitK;
 }
 
 struct ReduceArgs {

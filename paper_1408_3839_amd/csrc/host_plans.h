@@ -17,9 +17,11 @@ struct AssemblyPlan {
   tl_precision prec;
   int n_slices;
   dev::ContractArgs contract;
-  dev::SliceArgs slice;
+  dev::RowMaxArgs rowmax;  // split modes: exponents of the source rows' maxima
   dev::SplitArgs split;
-  int contract_blocks, slice_blocks;
+  int contract_blocks, rowmax_blocks;
+  size_t split_lds;        // split modes: dynamic LDS of the contraction
+  int split_spt;           // split modes: staged source rows per thread pass (8 or 16)
   dev::ReduceArgs reduce;
   int64_t reduce_total;
   dev::CombineArgs combine;
