@@ -610,6 +610,63 @@ __device__ inline void slice_values(const double (&x)[NV], int e, LowT* dst, int
   for (int q = 0; q < S; ++q) *(vN*)(dst + q * qstride) = out[q];
 }
 
+// Slices of two values (beta s <= 52): N' = N + bias is exact in FP64 and is
+// cut at a digit boundary into hi and lo 32-bit parts; every field is a
+// bit-field extract.  fp16 digits come from the bit pattern 0x6400 + field
+// (the half 1024 + field) minus 1024 + 2^(beta-1), two at a time in a
+// packed half add; bf16 digits from the float 2^23 + field minus 2^23 +
+// 2^(beta-1).  The pair is written as one 4-byte word per slice.
+template <typename LowT, int S>
+__device__ inline void slice_pair(double x0, double x1, int e, LowT* dst, int qstride) {
+  constexpr int beta = LowTraits<LowT>::beta;
+  static_assert(beta * S <= 52, "slice_pair needs beta s <= 52");
+  constexpr int m = S - 1 < 3 ? S - 1 : 3;  // low digits held in lo
+  constexpr int half = 1 << (beta - 1);
+  constexpr unsigned mask = (1u << beta) - 1;
+  constexpr double biasd = [] {
+    double b = 0.0, w = 1.0;
+    for (int k = 0; k < S - 1; ++k, w *= (double)(1 << beta)) b += (double)half * w;
+    return b;
+  }();
+  constexpr double lo_scale = (double)(1ull << (beta * m));
+  const double N0 = rint(ldexp(x0, beta * S - e)) + biasd;
+  const double N1 = rint(ldexp(x1, beta * S - e)) + biasd;
+  const double h0 = floor(N0 * (1.0 / lo_scale)), h1 = floor(N1 * (1.0 / lo_scale));
+  const unsigned l0 = (unsigned)fma(-h0, lo_scale, N0), l1 = (unsigned)fma(-h1, lo_scale, N1);
+  const int i0 = (int)h0, i1 = (int)h1;
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const int k = S - 1 - q;  // field from the bottom
+    unsigned f0, f1;
+    int off;                  // field value minus off = digit
+    if (q == 0) {             // top: signed, |d| <= 2^beta
+      f0 = (unsigned)((i0 >> (beta * (k - m))) + (1 << beta));
+      f1 = (unsigned)((i1 >> (beta * (k - m))) + (1 << beta));
+      off = 1 << beta;
+    } else if (k < m) {
+      f0 = (l0 >> (beta * k)) & mask;
+      f1 = (l1 >> (beta * k)) & mask;
+      off = half;
+    } else {
+      f0 = ((unsigned)i0 >> (beta * (k - m))) & mask;
+      f1 = ((unsigned)i1 >> (beta * (k - m))) & mask;
+      off = half;
+    }
+    if constexpr (sizeof(LowT) == 2 && LowTraits<LowT>::beta == 9) {  // fp16
+      typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+      const unsigned bits = (f0 | (f1 << 16)) + 0x64006400u;  // halves 1024 + f
+      const h2 v = __builtin_bit_cast(h2, bits);
+      const _Float16 c = (_Float16)(-(1024 + off));
+      *(h2*)(dst + q * qstride) = v + h2{c, c};
+    } else {  // bf16
+      typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+      const float v0 = __builtin_bit_cast(float, 0x4B000000u | f0) - (float)(8388608 + off);
+      const float v1 = __builtin_bit_cast(float, 0x4B000000u | f1) - (float)(8388608 + off);
+      *(b2*)(dst + q * qstride) = b2{(__bf16)v0, (__bf16)v1};
+    }
+  }
+}
+
 // One value's s slices, slice q at dst[q * qstride].
 template <typename LowT, int S>
 __device__ inline void slice_one(double x, int e, LowT* dst, int64_t qstride) {
@@ -750,7 +807,10 @@ __device__ inline void contract_split_src_body(const SplitArgs& a, int b) {
       const double g = src[xb * kSplitK + xk + j];
       xv[j] = xok ? (xa >= 0 ? src[xa * kSplitK + xk + j] * g : g) : 0.0;
     }
-    slice_values<LowT, S, 2>(xv, ex, Xs + xr * LD + xk, TM * LD);
+    if constexpr (LowTraits<LowT>::beta * S <= 52)
+      slice_pair<LowT, S>(xv[0], xv[1], ex, Xs + xr * LD + xk, TM * LD);
+    else
+      slice_values<LowT, S, 2>(xv, ex, Xs + xr * LD + xk, TM * LD);
   };
   f32x4 c32[2][S];
   f64x4 acc[2];
