@@ -206,6 +206,34 @@ def measure(sys_, precision, n_slices, steps, warmup):
     }
 
 
+def box_contraction_flops(s, tile: int = 32) -> float:
+    """MFMA work of the open chain's x contraction: per (mu <= nu) function
+    pair and 32 x 32 cell tile, two contractions (H and mass form) of
+    rows x cols entries over the tile's node range (where both tiles'
+    Gaussians are above exp(-46) of their peak), 2 flops per product."""
+    L0, m0, n, h = int(s.L[0]), s.m0, int(s.n[0]), float(s.h)
+    org, a0, x0 = float(s.cell_origin[0][0]), float(s.a[0]), float(s.x0[0])
+    cen = s.fn_center[:, 0]
+    rad = np.sqrt(46.0 / s.fn_alpha) + h
+    nt = -(-L0 // tile)
+    total = 0.0
+    for mu in range(m0):
+        for nu in range(mu, m0):
+            for tr in range(nt):
+                for tc in range(tr if mu == nu else 0, nt):
+                    r0, r1 = tr * tile, min(L0, tr * tile + tile) - 1
+                    c0, c1 = tc * tile, min(L0, tc * tile + tile) - 1
+                    lo = (max(org + r0 * a0 + cen[mu] - rad[mu], org + c0 * a0 + cen[nu] - rad[nu])
+                          - x0) / h
+                    hi = (min(org + r1 * a0 + cen[mu] + rad[mu], org + c1 * a0 + cen[nu] + rad[nu])
+                          - x0) / h
+                    klo = 0 if lo <= 0 else min(int(np.ceil(lo)), n)
+                    khi = 0 if hi < 0 else min(int(np.floor(hi)) + 1, n)
+                    if khi > klo:
+                        total += 4.0 * (r1 - r0 + 1) * (c1 - c0 + 1) * (khi - klo)
+    return total
+
+
 def box_chain_section(steps: int, warmup: int):
     """256-site open chain (N_b = 2048): GPU assembly of the full H, S and the
     dense lowest-64 generalized eigensolve, timed with HIP events (stage
@@ -250,6 +278,47 @@ def box_chain_section(steps: int, warmup: int):
     oracle.lowest_generalized_eigs(bp.H.cpu().numpy(), bp.S.cpu().numpy(), 64)
     cpu_eigh_s = time.perf_counter() - t0
     asm_ms, eig_ms = float(np.median(asm)), float(np.median(eig))
+    # the x contraction alone, in FP64 and the split modes; entries against
+    # the FP64 path, eigenvalues (FP64 eigensolver) against the oracle's
+    flops = box_contraction_flops(s)
+    H64, S64 = bp.H.clone(), bp.S.clone()
+    modes = {}
+    for prec, nsl in (("fp64", 0), ("split_fp16", 5), ("split_bf16", 6)):
+        bq = BoxPipeline(s, k=64, precision=prec, n_slices=nsl)
+        bq.run()
+        torch.cuda.synchronize()
+        con, tot = [], []
+        for _ in range(steps):
+            c0, c1, a0, a1 = ev(), ev(), ev(), ev()
+            for e in (c0, c1):
+                e.record(stream)
+            tl.tl_set_contraction_events(c0.cuda_event, c1.cuda_event)
+            a0.record(stream)
+            bq.assemble()
+            a1.record(stream)
+            tl.tl_set_contraction_events(None, None)
+            torch.cuda.synchronize()
+            con.append(c0.elapsed_time(c1))
+            tot.append(a0.elapsed_time(a1))
+        c_ms = float(np.median(con))
+        peak = 78.6 if prec == "fp64" else 2500.0
+        r = {"assembly_ms": float(np.median(tot)), "x_contraction_ms": c_ms,
+             "x_contraction_roofline": {
+                 "bound": "mfma", "achieved": flops / (c_ms * 1e-3) / 1e12, "peak": peak,
+                 "unit": "TFLOP/s", "frac": flops / (c_ms * 1e-3) / 1e12 / peak,
+                 "algorithmic_flops": flops,
+                 "note": "fp64 MFMA peak" if prec == "fp64" else
+                         "fp16/bf16 MFMA peak; flops of the FP64 problem, not of the slices"},
+             "max_abs_dH_rel_vs_fp64": float((bq.H - H64).abs().max() / H64.abs().max()),
+             "max_abs_dS_rel_vs_fp64": float((bq.S - S64).abs().max() / S64.abs().max())}
+        if prec != "fp64":
+            bq.eig.run(bq.H, bq.S)
+            torch.cuda.synchronize()
+            r["max_abs_dlambda_vs_oracle_Ha"] = float(np.abs(bq.eig.evals.cpu().numpy()
+                                                             - w_ref).max())
+            r["info"] = int(bq.eig.info.item())
+        modes[prec + (f"x{nsl}" if nsl else "")] = r
+        del bq
     return {
         "workload": "open (256,1,1) chain, 1.8 bohr, Z alternating 1/3, m0=8, grid 8500x256x256, "
                     "h=0.0625, R=32; N_b=2048; lowest 64 generalized eigenpairs",
@@ -267,6 +336,7 @@ def box_chain_section(steps: int, warmup: int):
         "max_abs_dlambda_vs_oracle_Ha": float(np.abs(ev_gpu - w_ref).max()),
         "info": int(bp.eig.info.item()),
         "oracle_eigh_on_host_s": cpu_eigh_s,
+        "x_contraction_modes": modes,
     }
 
 

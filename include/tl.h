@@ -189,7 +189,10 @@ tl_status tl_build_basis_and_potential(const tl_system* sys, double* G_dev, doub
  * Box mode: H_dev, S_dev = full (L0*m0)^2 matrices, row c*m0+mu.
  * prec selects the arithmetic of the 1D contractions; the combination over
  * terms and dimensions is FP64 in every mode.  n_slices is used by the split
- * modes (2..8 slices per operand), ignored otherwise.
+ * modes (2..6 slices per operand for TL_SPLIT_FP16, 2..7 for TL_SPLIT_BF16;
+ * 0 takes 5 and 6), ignored otherwise.
+ * Box mode runs the x contraction in FP64 or a split mode (TL_FP32 gives
+ * TL_EUNSUPPORTED); its y and z factors (m0 x m0 per term) are FP64.
  * Inputs: the arrays filled by tl_build_basis and tl_lattice_sum_potential.
  */
 tl_status tl_assemble_core_hamiltonian_block(const tl_system* sys, const double* G_dev,

@@ -130,7 +130,6 @@ SplitPlan make_split_plan(const Geometry& g, int s, size_t base) {
   return sp;
 }
 
-bool is_split(tl_precision prec) { return prec == TL_SPLIT_BF16 || prec == TL_SPLIT_FP16; }
 
 // Dynamic LDS budget of the source-row FP64 kernel: three workgroups per CU
 // with 32 x 32 tiles, two with 64 x 64 tiles.
@@ -196,9 +195,6 @@ int choose_kc(const Plan& plan, const Geometry& g, int d, int ypad, int tile, si
   return 0;
 }
 
-int default_slices(tl_precision prec) { return prec == TL_SPLIT_FP16 ? 5 : 6; }
-// beta s + 1 bits of the rounded integer and its bias must fit an int64
-int max_slices(tl_precision prec) { return prec == TL_SPLIT_FP16 ? 6 : 7; }
 
 // Source rows of the worst 64-row split tile: its P rows plus G, AG, SG rows.
 int split_src_rows(const Geometry& g) {
@@ -556,7 +552,7 @@ extern "C" tl_status tl_assemble_core_hamiltonian_block(const tl_system* sys, co
   if (g.mode == TL_MODE_PERIODIC)
     return tl::assemble_periodic(g, G_dev, AG_dev, SG_dev, P_dev, prec, n_slices, H_dev, S_dev,
                                  ws_dev, ws_bytes, (hipStream_t)stream);
-  return tl::assemble_box(g, sys, G_dev, AG_dev, SG_dev, P_dev, prec, H_dev, S_dev, ws_dev,
+  return tl::assemble_box(g, sys, G_dev, AG_dev, SG_dev, P_dev, prec, n_slices, H_dev, S_dev, ws_dev,
                          ws_bytes, (hipStream_t)stream);
 }
 
@@ -584,6 +580,6 @@ extern "C" tl_status tl_assemble_core_hamiltonian_block_noalloc(
   if (g.mode == TL_MODE_PERIODIC)
     return tl::assemble_periodic(g, G_dev, AG_dev, SG_dev, P_dev, prec, n_slices, H_dev, S_dev,
                                  ws, tl::kStaticScratchBytes, (hipStream_t)stream);
-  return tl::assemble_box(g, sys, G_dev, AG_dev, SG_dev, P_dev, prec, H_dev, S_dev, ws,
+  return tl::assemble_box(g, sys, G_dev, AG_dev, SG_dev, P_dev, prec, n_slices, H_dev, S_dev, ws,
                          tl::kStaticScratchBytes, (hipStream_t)stream);
 }

@@ -13,6 +13,11 @@ namespace tl {
 
 constexpr int kDefaultContractBlocks = 512;  // workgroups the contraction aims for
 
+inline bool is_split(tl_precision prec) { return prec == TL_SPLIT_BF16 || prec == TL_SPLIT_FP16; }
+inline int default_slices(tl_precision prec) { return prec == TL_SPLIT_FP16 ? 5 : 6; }
+// beta s + 1 bits of the rounded integer and its bias must fit an int64
+inline int max_slices(tl_precision prec) { return prec == TL_SPLIT_FP16 ? 6 : 7; }
+
 struct AssemblyPlan {
   tl_precision prec;
   int n_slices;
@@ -73,7 +78,7 @@ void set_fft_blue_tables(dev::FftArgs* a, void* ws);
 
 size_t box_workspace_bytes(const Geometry& g);
 tl_status assemble_box(const Geometry& g, const tl_system* s, const double* G, const double* AG,
-                       const double* SG, const double* P, tl_precision prec, double* H,
-                       double* S, void* ws, size_t ws_bytes, hipStream_t stream);
+                       const double* SG, const double* P, tl_precision prec, int n_slices,
+                       double* H, double* S, void* ws, size_t ws_bytes, hipStream_t stream);
 
 }  // namespace tl

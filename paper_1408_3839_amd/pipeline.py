@@ -193,11 +193,14 @@ class BoxPipeline:
     full N_b x N_b core Hamiltonian and mass matrix, and (k > 0) the lowest k
     generalized eigenpairs."""
 
-    def __init__(self, sys, k: int = 0, with_evecs: bool = True, device: str = "cuda:0"):
+    def __init__(self, sys, k: int = 0, with_evecs: bool = True, device: str = "cuda:0",
+                 precision: str = "fp64", n_slices: int = 0):
         if sys.mode != "box":
             raise ValueError("BoxPipeline needs a box-mode system")
         tl.load()
         self.sys = sys
+        self.prec = tl.PRECISIONS[precision]
+        self.n_slices = int(n_slices)
         self.handle = tl.SystemHandle(sys)
         self.device = torch.device(device)
         sz = tl.tl_query_sizes(self.handle)
@@ -209,7 +212,7 @@ class BoxPipeline:
         self.P = torch.empty(sz["pot_elems"], **f64)
         self.pot_ws_bytes = tl.tl_potential_workspace_bytes(self.handle)
         self.pot_ws = torch.empty(max(1, self.pot_ws_bytes), dtype=torch.uint8, device=self.device)
-        self.asm_ws_bytes = tl.tl_assemble_workspace_bytes(self.handle, tl.TL_FP64, 0)
+        self.asm_ws_bytes = tl.tl_assemble_workspace_bytes(self.handle, self.prec, self.n_slices)
         self.asm_ws = torch.empty(max(1, self.asm_ws_bytes), dtype=torch.uint8, device=self.device)
         self.Nb = int(sz["basis_rows"][0])
         self.H = torch.empty(self.Nb, self.Nb, **f64)
@@ -220,7 +223,7 @@ class BoxPipeline:
         tl.tl_build_basis_and_potential(self.handle, self.G, self.AG, self.SG, self.P,
                                         self.pot_ws, self.pot_ws_bytes, stream)
         tl.tl_assemble_core_hamiltonian_block(self.handle, self.G, self.AG, self.SG, self.P,
-                                              tl.TL_FP64, 0, self.H, self.S, self.asm_ws,
+                                              self.prec, self.n_slices, self.H, self.S, self.asm_ws,
                                               self.asm_ws_bytes, stream)
 
     def run(self, stream=None):

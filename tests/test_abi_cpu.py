@@ -117,9 +117,18 @@ def test_box_mode_queries_and_rejections():
     assert nb == 2048
     wb = tl.tl_assemble_workspace_bytes(s)
     assert wb > 0 and wb % 256 == 0
-    # the open-boundary assembly runs in FP64 only; the check precedes any launch
+    # the open-boundary assembly runs in FP64 or a split mode, with a valid
+    # slice count; the checks precede any launch
     _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EUNSUPPORTED, s, 8, 8, 8, 8,
-            tl.TL_SPLIT_BF16, 6, 8, 8, 8, wb, 0)
+            tl.TL_FP32, 0, 8, 8, 8, wb, 0)
+    _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EINVAL, s, 8, 8, 8, 8,
+            tl.TL_SPLIT_FP16, 7, 8, 8, 8, wb, 0)
+    _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EINVAL, s, 8, 8, 8, 8,
+            tl.TL_SPLIT_BF16, 1, 8, 8, 8, wb, 0)
+    # workspace: the transverse contraction, the factor tables and the
+    # weighted potentials Q[mu][nu] (m0^2 n_x doubles)
+    assert wb >= 8 * 8 * 8 * 8500
+    assert tl.tl_assemble_workspace_bytes(s, tl.TL_SPLIT_FP16, 5) == wb
     _expect(tl.tl_assemble_core_hamiltonian_block, tl.TL_EWORKSPACE, s, 8, 8, 8, 8,
             tl.TL_FP64, 0, 8, 8, 8, wb - 256, 0)
 

@@ -81,3 +81,61 @@ def test_box_chain_graph_replay():
         x = torch.randn(1024, device="cuda") @ torch.randn(1024, device="cuda")  # eager work
         torch.cuda.synchronize()
         del x
+
+
+# (precision, slices, bound on max|dH| / max|H| and max|dS| / max|S|)
+SPLIT_MODES = [("split_fp16", 3, 3e-7), ("split_fp16", 4, 1e-9), ("split_fp16", 5, 3e-12),
+               ("split_fp16", 6, 1e-14), ("split_bf16", 4, 1e-8), ("split_bf16", 6, 1e-13),
+               ("split_bf16", 7, 1e-14)]
+
+
+@pytest.mark.parametrize("mode", SPLIT_MODES, ids=lambda m: f"{m[0]}-{m[1]}")
+def test_box_small_split(mode):
+    """Split-precision x contraction of the 12-site chain: every entry of H
+    and S against the oracle, within a bound that shrinks as 2^(-beta s);
+    H and S exactly symmetric."""
+    from paper_1408_3839_amd.pipeline import BoxPipeline
+    prec, ns, bound = mode
+    s = _small_box()
+    bp = BoxPipeline(s, precision=prec, n_slices=ns)
+    bp.run()
+    torch.cuda.synchronize()
+    H = bp.H.cpu().numpy()
+    S = bp.S.cpu().numpy()
+    Hr, Sr = oracle.full_matrices(s)
+    eh = np.abs(H - Hr).max() / np.abs(Hr).max()
+    es = np.abs(S - Sr).max() / np.abs(Sr).max()
+    print(f"box12 {prec} s={ns}: max|dH|/max|H| = {eh:.3e}, max|dS|/max|S| = {es:.3e}")
+    assert np.array_equal(H, H.T) and np.array_equal(S, S.T)
+    assert eh <= bound and es <= bound
+
+
+@pytest.mark.parametrize("mode", [("split_fp16", 5), ("split_bf16", 6)],
+                         ids=lambda m: f"{m[0]}-{m[1]}")
+def test_box_chain_256_split_entries(mode):
+    """The 256-site chain with the split x contraction: the sampled entries
+    against the oracle, and every entry against the FP64 path."""
+    from paper_1408_3839_amd.pipeline import BoxPipeline
+    prec, ns = mode
+    s = wl.config(3)
+    bp = BoxPipeline(s, precision=prec, n_slices=ns)
+    bp.run()
+    b64 = BoxPipeline(s)
+    b64.run()
+    torch.cuda.synchronize()
+    assert torch.equal(bp.H, bp.H.T) and torch.equal(bp.S, bp.S.T)
+    dh = float((bp.H - b64.H).abs().max() / b64.H.abs().max())
+    ds = float((bp.S - b64.S).abs().max() / b64.S.abs().max())
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([np.arange(0, 8), np.arange(1020, 1028), np.arange(2040, 2048),
+                                     rng.integers(0, 2048, 8)]))
+    cols = np.unique(np.concatenate([rows, rng.integers(0, 2048, 16)]))
+    Hr, Sr = oracle.full_matrices(s, rows=rows, cols=cols)
+    Hg = bp.H.cpu().numpy()[np.ix_(rows, cols)]
+    Sg = bp.S.cpu().numpy()[np.ix_(rows, cols)]
+    eh = np.abs(Hg - Hr).max() / np.abs(Hr).max()
+    es = np.abs(Sg - Sr).max() / np.abs(Sr).max()
+    print(f"chain256 {prec} s={ns}: vs FP64 path {dh:.3e} / {ds:.3e}; "
+          f"sampled vs oracle {eh:.3e} / {es:.3e}")
+    assert dh <= 1e-12 and ds <= 1e-12
+    assert eh <= 1e-12 and es <= 1e-12

@@ -153,3 +153,32 @@ def test_box_chain_256_lowest64():
           f"{np.abs(G - np.eye(64)).max():.3e}")
     assert res.max() <= 1e-10
     assert np.abs(G - np.eye(64)).max() <= 1e-8
+
+
+def test_box_chain_256_lowest64_split_fp16():
+    """The 256-site chain assembled with the split-FP16 x contraction (five
+    slices), then the FP64 eigensolver: the lowest 64 eigenvalues against the
+    oracle's within 1e-6 Ha, and within the first-order bound of the measured
+    matrix perturbation (against the FP64 path) plus the eigensolver's own."""
+    from paper_1408_3839_amd import workloads as wl
+    from paper_1408_3839_amd.pipeline import BoxPipeline
+    rows = [l.split() for l in open(GOLDEN) if not l.startswith("#")]
+    meta = {l.split()[1]: float(l.split()[2]) for l in open(GOLDEN) if l.startswith("# norm2")}
+    w = np.array([float(r[1]) for r in rows])
+    un = np.array([float(r[2]) for r in rows])
+    bp = BoxPipeline(wl.config(3), k=64, precision="split_fp16", n_slices=5)
+    bp.run()
+    b64 = BoxPipeline(wl.config(3))
+    b64.assemble()
+    torch.cuda.synchronize()
+    assert int(bp.eig.info.item()) == 0
+    ev = bp.eig.evals.cpu().numpy()
+    dH = np.linalg.norm((bp.H - b64.H).cpu().numpy())  # Frobenius >= 2-norm
+    dS = np.linalg.norm((bp.S - b64.S).cpu().numpy())
+    tol = (1e-12 * np.abs(w) + 256 * EPS * (meta["norm2_H"] + np.abs(w) * meta["norm2_S"]) * un
+           + 2 * (dH + np.abs(w) * dS) * un)
+    err = np.abs(ev - w)
+    print(f"box chain split-fp16 x5: max |d lambda| = {err.max():.3e} Ha, max tol = "
+          f"{tol.max():.3e}; |dH|_F = {dH:.3e}, |dS|_F = {dS:.3e}")
+    assert np.all(err <= tol)
+    assert err.max() <= 1e-6
