@@ -202,6 +202,32 @@ tl_status tl_assemble_core_hamiltonian_block(const tl_system* sys, const double*
                                              void* ws_dev, size_t ws_bytes, void* stream);
 
 /*
+ * tl_assemble_kblocks - the k-blocks Hbar_k, Sbar_k of a periodic system
+ * straight from the 1D contractions, with the lattice DFT taken factor by
+ * factor (Theorem on the tensor-structured FFT diagonalisation, Sec. 2;
+ * Proposition on low-rank Fourier coefficients):
+ *   Chat_l[t][mu][nu](k) = sum_{d=0}^{L_l-1} C_l[t][mu][nu][d] w_l^(k d),
+ *   w_l = exp(-2 pi i / L_l), C_l[mu][nu][-s] = C_l[nu][mu][s] on the torus,
+ *   Vbar_k = sum_t prod_l Chat_l[t](k_l), Tbar_k and Sbar_k likewise from
+ *   the D and M factors, Hbar_k = Tbar_k - Vbar_k.
+ * The result equals tl_assemble_core_hamiltonian_block followed by
+ * tl_block_fft (up to rounding), without the real-space block column.
+ *   Hk_dev, Sk_dev: [L1][L2][L3][m0][m0] complex (interleaved re, im), the
+ *   layout tl_block_fft writes and tl_batched_heigh reads.
+ *   prec, n_slices, inputs: as tl_assemble_core_hamiltonian_block.
+ *   ws_dev: tl_assemble_kblocks_workspace_bytes bytes (the contraction's
+ *   workspace plus (T+2) m0^2 L_l complex values per transformed dim).
+ * Errors: TL_EUNSUPPORTED for box mode or a periodic L_l above 2048 (the
+ * block FFT route takes those), TL_EWORKSPACE, TL_EINVAL as for assembly.
+ */
+tl_status tl_assemble_kblocks_workspace_bytes(const tl_system* sys, tl_precision prec,
+                                              int n_slices, size_t* bytes);
+tl_status tl_assemble_kblocks(const tl_system* sys, const double* G_dev, const double* AG_dev,
+                              const double* SG_dev, const double* P_dev, tl_precision prec,
+                              int n_slices, double* Hk_dev, double* Sk_dev, void* ws_dev,
+                              size_t ws_bytes, void* stream);
+
+/*
  * tl_assemble_core_hamiltonian_block_noalloc - the same assembly for callers
  * that cannot allocate or pass device memory for scratch (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc).

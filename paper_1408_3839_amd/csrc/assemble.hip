@@ -57,6 +57,10 @@ __global__ __launch_bounds__(256) void combine_periodic_kernel(CombineArgs a, in
   combine_periodic_body(a, total, blockIdx.x);
 }
 
+__global__ __launch_bounds__(256) void combine_pair_kernel(CombineArgs a) {
+  combine_pair_body(a, blockIdx.x, blockIdx.y);
+}
+
 }  // namespace
 
 void contraction_events(hipEvent_t* start, hipEvent_t* stop) {
@@ -439,7 +443,7 @@ void launch_split_contraction(const AssemblyPlan& ap, hipStream_t stream, hipEve
 
 }  // namespace
 
-tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream) {
+tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream, bool combine) {
   if (is_split(ap.prec)) {
     launch_rowmax(ap, stream);
     TL_CHECK_LAUNCH();
@@ -466,8 +470,17 @@ tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream) {
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)ceil_div(ap.reduce_total, 256)),
                      dim3(256), 0, stream, ap.reduce, ap.reduce_total);
   TL_CHECK_LAUNCH();
-  hipLaunchKernelGGL(combine_periodic_kernel, dim3((unsigned)ceil_div(ap.combine_total, 4)),
-                     dim3(256), 0, stream, ap.combine, ap.combine_total);
+  if (!combine) return TL_OK;
+  const CombineArgs& c = ap.combine;
+  if (combine_pair_fits(c.T, c.L)) {
+    const int cells = c.L[0] * c.L[1] * c.L[2];
+    hipLaunchKernelGGL(combine_pair_kernel,
+                       dim3((unsigned)(c.m0 * c.m0), (unsigned)ceil_div(cells, 256)), dim3(256),
+                       0, stream, c);
+  } else {
+    hipLaunchKernelGGL(combine_periodic_kernel, dim3((unsigned)ceil_div(ap.combine_total, 4)),
+                       dim3(256), 0, stream, c, ap.combine_total);
+  }
   TL_CHECK_LAUNCH();
   return TL_OK;
 }

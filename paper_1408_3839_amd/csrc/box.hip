@@ -170,15 +170,17 @@ __device__ inline void box_store(const BoxPairArgs& a, const BoxTile& t, int c, 
   }
 }
 
-constexpr int kBoxKT = 16;  // FP64: nodes per LDS stage
-constexpr int kBoxLD = kBoxKT + 1;
-
 // FP64: 4 waves, each a 16 x 16 quarter of the 32 x 32 cell tile, two
-// accumulators (H and the mass form).
+// accumulators (H and the mass form); KT nodes per LDS stage, the next
+// stage's loads in flight during this stage's MFMAs.
+template <int KT>
 __global__ __launch_bounds__(256) void box_pair_f64_kernel(BoxPairArgs a) {
-  __shared__ double Xh[kBoxTile][kBoxLD];
-  __shared__ double Xm[kBoxTile][kBoxLD];
-  __shared__ double Yc[kBoxTile][kBoxLD];
+  constexpr int LDK = KT + 1;
+  constexpr int RSTEP = 256 / KT;          // rows apart of one thread's staged rows
+  constexpr int RPT = kBoxTile / RSTEP;    // staged rows per thread
+  __shared__ double Xh[kBoxTile][LDK];
+  __shared__ double Xm[kBoxTile][LDK];
+  __shared__ double Yc[kBoxTile][LDK];
   const BoxTile t = box_tile(a, blockIdx.x);
   const int m2 = a.m0 * a.m0;
   const double cD = a.coef[a.T * m2 + t.mu * a.m0 + t.nu];
@@ -186,48 +188,36 @@ __global__ __launch_bounds__(256) void box_pair_f64_kernel(BoxPairArgs a) {
   const double* Qp = a.Q + (int64_t)(t.mu * a.m0 + t.nu) * a.n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // staging: this thread's node kk of rows sr and sr + 16
-  const int kk = tid & 15, sr = tid >> 4;
-  const double* gr[2];
-  const double* ar[2];
-  const double* srow[2];
-  const double* yr[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int c = t.tr * kBoxTile + sr + 16 * u, cp = t.tc * kBoxTile + sr + 16 * u;
-    const int64_t f = (int64_t)min(c, a.L0 - 1) * a.m0 + t.mu;
-    const int64_t fp = (int64_t)min(cp, a.L0 - 1) * a.m0 + t.nu;
-    gr[u] = c < a.L0 ? a.G + f * a.n : nullptr;
-    ar[u] = a.AG + f * a.n;
-    srow[u] = a.SG + f * a.n;
-    yr[u] = cp < a.L0 ? a.G + fp * a.n : nullptr;
-  }
-  double vx[2], vm[2], vy[2];
+  // staging: this thread's node kk of rows sr, sr + RSTEP, ..
+  const int kk = tid % KT, sr = tid / KT;
+  double vx[RPT], vm[RPT], vy[RPT];
   auto load = [&](int k0) {
     const int i = k0 + kk;
     const bool ok = i < t.khi;
     const double q = ok ? Qp[i] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const bool rok = ok && gr[u] != nullptr;
-      vx[u] = rok ? box_x(gr[u][i], ar[u][i], srow[u][i], q, cD, cM) : 0.0;
-      vm[u] = rok ? srow[u][i] : 0.0;
-      vy[u] = ok && yr[u] != nullptr ? yr[u][i] : 0.0;
+    for (int u = 0; u < RPT; ++u) {
+      const int c = t.tr * kBoxTile + sr + RSTEP * u, cp = t.tc * kBoxTile + sr + RSTEP * u;
+      const int64_t o = ((int64_t)c * a.m0 + t.mu) * a.n + i;
+      const bool rok = ok && c < a.L0;
+      vx[u] = rok ? box_x(a.G[o], a.AG[o], a.SG[o], q, cD, cM) : 0.0;
+      vm[u] = rok ? a.SG[o] : 0.0;
+      vy[u] = ok && cp < a.L0 ? a.G[((int64_t)cp * a.m0 + t.nu) * a.n + i] : 0.0;
     }
   };
   f64x4 ah = {0.0, 0.0, 0.0, 0.0}, am = {0.0, 0.0, 0.0, 0.0};
   if (t.klo < t.khi) load(t.klo);
-  for (int k0 = t.klo; k0 < t.khi; k0 += kBoxKT) {
+  for (int k0 = t.klo; k0 < t.khi; k0 += KT) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      Xh[sr + 16 * u][kk] = vx[u];
-      Xm[sr + 16 * u][kk] = vm[u];
-      Yc[sr + 16 * u][kk] = vy[u];
+    for (int u = 0; u < RPT; ++u) {
+      Xh[sr + RSTEP * u][kk] = vx[u];
+      Xm[sr + RSTEP * u][kk] = vm[u];
+      Yc[sr + RSTEP * u][kk] = vy[u];
     }
     __syncthreads();
-    if (k0 + kBoxKT < t.khi) load(k0 + kBoxKT);  // in flight during the MFMAs
+    if (k0 + KT < t.khi) load(k0 + KT);  // in flight during the MFMAs
 #pragma unroll
-    for (int k = 0; k < kBoxKT; k += 4) {
+    for (int k = 0; k < KT; k += 4) {
       const int r = lane & 15, kq = k + (lane >> 4);
       const double bv = Yc[wn * 16 + r][kq];
       ah = __builtin_amdgcn_mfma_f64_16x16x4f64(Xh[wm * 16 + r][kq], bv, ah, 0, 0, 0);
@@ -241,6 +231,8 @@ __global__ __launch_bounds__(256) void box_pair_f64_kernel(BoxPairArgs a) {
   for (int r = 0; r < 4; ++r)
     box_store(a, t, t.tr * kBoxTile + wm * 16 + (lane >> 4) + 4 * r, cp, ah[r], am[r]);
 }
+
+constexpr int kBoxKT = 32;  // FP64: nodes per LDS stage
 
 // Split modes: the same tiles with the three operands (X, SG rows, G
 // columns) sliced in LDS per 32-node stage, relative to the power-of-two
@@ -532,8 +524,8 @@ tl_status assemble_box(const Geometry& g, const tl_system* s, const double* G, c
   hipEvent_t e0, e1;
   stage_events(TL_STAGE_CONTRACTION, &e0, &e1);
   if (prec == TL_FP64) {
-    launch_with_events(box_pair_f64_kernel, dim3((unsigned)pblocks), dim3(256), 0, stream, e0, e1,
-                       b);
+    launch_with_events(box_pair_f64_kernel<kBoxKT>, dim3((unsigned)pblocks), dim3(256), 0, stream,
+                       e0, e1, b);
     TL_CHECK_LAUNCH();
     return TL_OK;
   }

@@ -979,5 +979,50 @@ __device__ inline void combine_periodic_body(const CombineArgs& a, int64_t total
   }
 }
 
+// The same combination with a workgroup per (mu, nu) pair and chunk of 256
+// block cells: the factors of dims 1 and 2 for every term and shift staged
+// once in LDS, a thread per cell d = (d1, d2, d3) summing the products over
+// the terms in order (the dim-0 factor is one value per d1, read from the
+// compact C_0).  Needs (T+2)(L2 + L3) <= kPairLdsMax.
+constexpr int kPairLdsMax = 6144;  // doubles
+
+__host__ __device__ inline bool combine_pair_fits(int T, const int L[3]) {
+  return (int64_t)(T + 2) * (L[1] + L[2]) <= kPairLdsMax;
+}
+
+__device__ inline void combine_pair_body(const CombineArgs& a, int pair, int chunk) {
+  __shared__ double F[kPairLdsMax];
+  const int m0 = a.m0, T = a.T, TT = T + 2;
+  const int mu = pair / m0, nu = pair - mu * m0;
+  const int L1 = a.L[1], L2 = a.L[2];
+  double* F1 = F;                  // [T+2][L1]
+  double* F2 = F + TT * L1;        // [T+2][L2]
+  for (int e = threadIdx.x; e < TT * (L1 + L2); e += blockDim.x) {
+    if (e < TT * L1) {
+      const int t = e / L1, k = e - t * L1;
+      F1[e] = lookup(a, 1, t, mu, nu, k);
+    } else {
+      const int f = e - TT * L1, t = f / L2, k = f - t * L2;
+      F2[f] = lookup(a, 2, t, mu, nu, k);
+    }
+  }
+  __syncthreads();
+  const int cells = a.L[0] * L1 * L2;
+  const int d = chunk * blockDim.x + threadIdx.x;
+  if (d >= cells) return;
+  const int d12 = d / L2, d3 = d - d12 * L2;
+  const int d1 = d12 / L1, d2 = d12 - d1 * L1;
+  double V = 0.0;
+  for (int t = 0; t < T; ++t)
+    V = fma(lookup(a, 0, t, mu, nu, d1) * F1[t * L1 + d2], F2[t * L2 + d3], V);
+  const double D1 = lookup(a, 0, T, mu, nu, d1), M1 = lookup(a, 0, T + 1, mu, nu, d1);
+  const double D2 = F1[T * L1 + d2], M2 = F1[(T + 1) * L1 + d2];
+  const double D3 = F2[T * L2 + d3], M3 = F2[(T + 1) * L2 + d3];
+  const double Tk = 0.5 * (D1 * M2 * M3 + M1 * D2 * M3 + M1 * M2 * D3);
+  const int64_t o = (int64_t)d * m0 * m0 + pair;
+  a.H[o] = Tk - V;
+  a.Sm[o] = M1 * M2 * M3;
+}
+
 }  // namespace dev
 }  // namespace tl

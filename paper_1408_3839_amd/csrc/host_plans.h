@@ -43,7 +43,9 @@ tl_status plan_assembly(const Geometry& g, const double* G, const double* AG, co
                         const double* P, tl_precision prec, int n_slices, double* H, double* S,
                         void* ws, size_t ws_bytes, int want_blocks, AssemblyPlan* out,
                         int tile_hint = 32);
-tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream);
+// combine = false: contraction and partial-sum reduction only (compact C_l
+// left in the workspace for another combination).
+tl_status launch_assembly(const AssemblyPlan& ap, hipStream_t stream, bool combine = true);
 void contraction_events(hipEvent_t* start, hipEvent_t* stop);
 
 struct PotentialPlan {

@@ -15,9 +15,15 @@ from . import tl
 
 class PeriodicPipeline:
     def __init__(self, sys, precision: str = "fp64", n_slices: int = 0,
-                 device: str = "cuda:0", with_evecs: bool = False):
+                 device: str = "cuda:0", with_evecs: bool = False, route: str = "block_fft"):
+        """route: "block_fft" (block column, then the 3-level block FFT) or
+        "kspace" (tl_assemble_kblocks: the DFT taken factor by factor, no
+        block column)."""
         if sys.mode != "periodic":
             raise ValueError("PeriodicPipeline needs a periodic-mode system")
+        if route not in ("block_fft", "kspace"):
+            raise ValueError(f"unknown route {route!r}")
+        self.route = route
         tl.load()
         self.sys = sys
         self.handle = tl.SystemHandle(sys)
@@ -43,6 +49,10 @@ class PeriodicPipeline:
         self.HSbar = torch.empty(2, sz["block_elems"], 2, **f64)    # their transforms
         self.fft_ws_bytes = tl.tl_block_fft_workspace_bytes(L[0], L[1], L[2], self.m0, 2)
         self.fft_ws = torch.empty(max(1, self.fft_ws_bytes), dtype=torch.uint8, device=self.device)
+        if route == "kspace":
+            self.kws_bytes = tl.tl_assemble_kblocks_workspace_bytes(self.handle, self.prec,
+                                                                    self.n_slices)
+            self.kws = torch.empty(max(1, self.kws_bytes), dtype=torch.uint8, device=self.device)
         self.evals = torch.empty(self.nblocks, self.m0, **f64)
         self.evecs = torch.empty(self.nblocks, self.m0, self.m0, 2, **f64) if with_evecs else None
         self.info = torch.empty(self.nblocks, dtype=torch.int32, device=self.device)
@@ -66,6 +76,11 @@ class PeriodicPipeline:
                                               self.prec, self.n_slices, self.HS[0], self.HS[1],
                                               self.asm_ws, self.asm_ws_bytes, stream)
 
+    def assemble_kblocks(self, stream=None):
+        tl.tl_assemble_kblocks(self.handle, self.G, self.AG, self.SG, self.P, self.prec,
+                               self.n_slices, self.HSbar[0], self.HSbar[1], self.kws,
+                               self.kws_bytes, stream)
+
     def block_fft(self, stream=None):
         L = self.L
         tl.tl_block_fft(self.HS, L[0], L[1], L[2], self.m0, 2, self.HSbar, self.fft_ws,
@@ -81,8 +96,11 @@ class PeriodicPipeline:
 
     def run(self, stream=None):
         self.basis_and_potential(stream)
-        self.assemble(stream)
-        self.block_fft(stream)
+        if self.route == "kspace":
+            self.assemble_kblocks(stream)
+        else:
+            self.assemble(stream)
+            self.block_fft(stream)
         self.heigh(stream)
         return self.evals
 

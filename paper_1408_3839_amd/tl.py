@@ -109,6 +109,14 @@ SIGNATURES = {
         ctypes.c_int, [ctypes.POINTER(TlSystem), ctypes.c_void_p, ctypes.c_void_p,
                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tl_assemble_kblocks_workspace_bytes": (
+        ctypes.c_int, [ctypes.POINTER(TlSystem), ctypes.c_int, ctypes.c_int,
+                       ctypes.POINTER(ctypes.c_size_t)]),
+    "tl_assemble_kblocks": (
+        ctypes.c_int, [ctypes.POINTER(TlSystem), ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                       ctypes.c_void_p]),
     "tl_set_contraction_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "tl_set_stage_events": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "tl_block_fft": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 5
@@ -263,6 +271,15 @@ def tl_assemble_workspace_bytes(sys, precision=TL_FP64, n_slices=0) -> int:
     return v.value
 
 
+def tl_assemble_kblocks_workspace_bytes(sys, precision=TL_FP64, n_slices=0) -> int:
+    h = _handle(sys)
+    v = ctypes.c_size_t()
+    _check(load().tl_assemble_kblocks_workspace_bytes(h.ref, int(precision), int(n_slices),
+                                                      ctypes.byref(v)),
+           "tl_assemble_kblocks_workspace_bytes")
+    return v.value
+
+
 def tl_block_fft_workspace_bytes(L1, L2, L3, m0, batch) -> int:
     v = ctypes.c_size_t()
     _check(load().tl_block_fft_workspace_bytes(int(L1), int(L2), int(L3), int(m0), int(batch),
@@ -295,6 +312,14 @@ def tl_assemble_core_hamiltonian_block(sys, G, AG, SG, P, precision, n_slices, H
     _check(load().tl_assemble_core_hamiltonian_block(
         h.ref, _ptr(G), _ptr(AG), _ptr(SG), _ptr(P), int(precision), int(n_slices), _ptr(H),
         _ptr(S), _ptr(ws), int(ws_bytes), _stream(stream)), "tl_assemble_core_hamiltonian_block")
+
+
+def tl_assemble_kblocks(sys, G, AG, SG, P, precision, n_slices, Hk, Sk, ws, ws_bytes,
+                        stream=None):
+    h = _handle(sys)
+    _check(load().tl_assemble_kblocks(
+        h.ref, _ptr(G), _ptr(AG), _ptr(SG), _ptr(P), int(precision), int(n_slices), _ptr(Hk),
+        _ptr(Sk), _ptr(ws), int(ws_bytes), _stream(stream)), "tl_assemble_kblocks")
 
 
 def tl_assemble_core_hamiltonian_block_noalloc(sys, G, AG, SG, P, precision, n_slices, H, S,

@@ -156,3 +156,25 @@ def test_noalloc_assembly_rejects_oversize_before_enqueue():
     msg = _expect(tl.tl_assemble_core_hamiltonian_block_noalloc, tl.TL_EUNSUPPORTED, hb,
                   fake, fake, fake, fake, tl.TL_SPLIT_BF16, 8, fake, fake, 0)
     assert "static scratch" in msg
+
+
+def test_kblocks_queries_and_rejections():
+    s = wl.config(5)
+    b = tl.tl_assemble_kblocks_workspace_bytes(s)
+    base = tl.tl_assemble_workspace_bytes(s)
+    # (T + 2)(L1 + L2 + L3) = 66 * 24 factors fit the fused kernel's LDS
+    assert b == base
+    c2 = wl.config(2)
+    assert tl.tl_assemble_kblocks_workspace_bytes(c2) == tl.tl_assemble_workspace_bytes(c2)
+    # 42 * 130 factors do not: (T + 2) m0^2 L complex values per transformed dim
+    big = wl.tiny_periodic(L=(128, 1, 1), m0=2, c=4, h=0.5, R=40)
+    assert tl.tl_assemble_kblocks_workspace_bytes(big) == \
+        tl.tl_assemble_workspace_bytes(big) + 42 * 4 * 128 * 16
+    with pytest.raises(tl.TlError):
+        tl.tl_assemble_kblocks_workspace_bytes(wl.config(3))   # box mode
+    _expect(tl.tl_assemble_kblocks, tl.TL_EUNSUPPORTED, wl.config(3), 8, 8, 8, 8, tl.TL_FP64, 0,
+            8, 8, 8, 1 << 30, 0)
+    _expect(tl.tl_assemble_kblocks, tl.TL_EWORKSPACE, s, 8, 8, 8, 8, tl.TL_FP64, 0, 8, 8, 8,
+            b - 256, 0)
+    _expect(tl.tl_assemble_kblocks, tl.TL_EINVAL, s, 8, 8, 8, 8, tl.TL_SPLIT_FP16, 9, 8, 8, 8,
+            b, 0)
