@@ -157,14 +157,15 @@ def entry_errors(H, S, Hr, Sr, scale):
             "n_entries": int(H.size)}
 
 
-def measure(sys_, precision, n_slices, steps, warmup):
+def measure(sys_, precision, n_slices, steps, warmup, route="block_fft"):
     """Time K graph replays of the whole step and K eager steps with HIP
     events around the contraction kernel; return timings and outputs."""
     import torch
     from paper_1408_3839_amd import tl
     from paper_1408_3839_amd.pipeline import PeriodicPipeline
 
-    pl = PeriodicPipeline(sys_, precision=precision, n_slices=n_slices, device="cuda:0")
+    pl = PeriodicPipeline(sys_, precision=precision, n_slices=n_slices, device="cuda:0",
+                          route=route)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         pl.run()
@@ -200,7 +201,7 @@ def measure(sys_, precision, n_slices, steps, warmup):
     return {
         "ms_per_step": 1e3 * (t1 - t0) / steps,
         "contraction_ms": contr_ms,
-        "H": pl.H.cpu().numpy(), "S": pl.S.cpu().numpy(),
+        "H": pl.H.cpu().numpy(), "S": pl.S.cpu().numpy(), "HSbar": pl.HSbar.cpu().numpy(),
         "evals": pl.evals.cpu().numpy(), "info": pl.info.cpu().numpy(),
         "sizes": pl.sizes,
     }
@@ -370,6 +371,24 @@ def cubic_section(steps: int, warmup: int):
             fp64_ms = r["ms_per_step"]
         acc["speedup_vs_fp64"] = fp64_ms / r["ms_per_step"]
         out[prec + (f"x{nsl}" if nsl else "")] = acc
+    # the Fourier-side route: k-blocks from the 1D DFTs of the contraction
+    # factors (tl_assemble_kblocks), no block column and no block FFT
+    for prec, nsl in (("fp64", 0), ("split_fp16", 5)):
+        r = measure(s, prec, nsl, steps, warmup, route="kspace")
+        hs = r["HSbar"]
+        Hk = (hs[0, :, 0] + 1j * hs[0, :, 1]).reshape(Hb.shape)
+        Sk = (hs[1, :, 0] + 1j * hs[1, :, 1]).reshape(Sb.shape)
+        acc = {"ms_per_step": r["ms_per_step"],
+               "entries_per_s": entries / (r["ms_per_step"] * 1e-3),
+               "k_blocks_per_s": s.ncells / (r["ms_per_step"] * 1e-3),
+               "max_abs_dHbar_over_max": float(np.abs(Hk - Hb).max() / np.abs(Hb).max()),
+               "max_abs_dSbar_over_max": float(np.abs(Sk - Sb).max() / np.abs(Sb).max()),
+               "speedup_vs_block_fft_route": out[prec + (f"x{nsl}" if nsl else "")]["ms_per_step"]
+               / r["ms_per_step"]}
+        ok = r["info"].reshape(-1) == 0
+        if ok.any():
+            acc.update(eig_errors(r["evals"], Hb, Sb, s.m0, ok))
+        out["kspace_route_" + prec + (f"x{nsl}" if nsl else "")] = acc
     return out
 
 
@@ -388,7 +407,7 @@ def batch_section(steps: int, warmup: int):
     entries = sum(int(s.L[0]) * s.m0 * s.m0 for s in systems)
     flops = sum(contraction_flops(s, tl.tl_query_sizes(s)) for s in systems)
     results = {}
-    for prec, nsl in (("fp64", 0), ("split_bf16", 6)):
+    for prec, nsl in (("fp64", 0), ("split_fp16", 5), ("split_bf16", 6)):
         want, tuning = autotune.tune_batch(systems, precision=prec, n_slices=nsl, cache_path=None)
         bp = BatchPipeline(systems, precision=prec, n_slices=nsl, want_blocks=want)
         for _ in range(max(1, warmup)):
@@ -424,16 +443,25 @@ def batch_section(steps: int, warmup: int):
             "tuned_want_blocks": want,
             "tuning_contraction_ms": {str(k): round(v, 4) for k, v in tuning.items()},
         }
-        results[prec] = (bp.buf["evals"].cpu().numpy(), info, bp.buf["HSbar"].cpu().numpy(),
-                         bp.buf["HS"].cpu().numpy())
+        results[prec + (f"x{nsl}" if nsl else "")] = (
+            bp.buf["evals"].cpu().numpy(), info, bp.buf["HSbar"].cpu().numpy(),
+            bp.buf["HS"].cpu().numpy())
         del bp
         torch.cuda.synchronize()
     out["entries_per_step"] = entries
-    # split against the FP64 GPU path: entries, and eigenvalues of the blocks
-    # both solved, with each eigenvalue's condition in the FP64 pencil
+    for key in ("split_fp16x5", "split_bf16x6"):
+        r = split_vs_fp64(systems, results["fp64"], results[key])
+        r["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out[key]["ms_per_step"]
+        out[key + "_vs_fp64"] = r
+    return out
+
+
+def split_vs_fp64(systems, ref, got):
+    """A split mode against the FP64 GPU path: entries, and eigenvalues of the
+    blocks both solved, with each eigenvalue's condition in the FP64 pencil."""
     import scipy.linalg as sla
-    ev64, inf64, hsb64, hs64 = results["fp64"]
-    evs, infs, _, hss = results["split_bf16"]
+    ev64, inf64, hsb64, hs64 = ref
+    evs, infs, _, hss = got
     off = oe = ok_ = 0
     worst_all = worst_ok = 0.0
     n = n_in = n_ill = n_ok = n_ok_in = 0
@@ -466,13 +494,11 @@ def batch_section(steps: int, warmup: int):
         off += 2 * be
         oe += L * m0
         ok_ += L
-    out["split_bf16x6_vs_fp64"] = {
+    return {
         "max_abs_dHS_over_max": float(np.abs(hss - hs64).max() / np.abs(hs64).max()),
         "max_abs_dlambda_all_Ha": worst_all, "max_abs_dlambda_cond_le_1e6_Ha": worst_ok,
         "n_eigs_compared": n, "n_eigs_within_1e-6_Ha": n_in, "n_eigs_cond_gt_1e6": n_ill,
-        "n_eigs_cond_le_1e6": n_ok, "n_eigs_cond_le_1e6_within_1e-6_Ha": n_ok_in,
-        "speedup_vs_fp64": out["fp64"]["ms_per_step"] / out["split_bf16x6"]["ms_per_step"]}
-    return out
+        "n_eigs_cond_le_1e6": n_ok, "n_eigs_cond_le_1e6_within_1e-6_Ha": n_ok_in}
 
 
 def fft_bytes(systems) -> float:

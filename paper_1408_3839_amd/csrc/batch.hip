@@ -118,7 +118,13 @@ __global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchDesc* __re
 
 __global__ __launch_bounds__(256) void batch_combine_kernel(const BatchDesc* __restrict__ d) {
   TL_BATCH_LOCATE(kCombine)
-  dev::combine_periodic_body(J.asmb.combine, J.asmb.combine_total, lb);
+  const dev::CombineArgs& c = J.asmb.combine;
+  if (dev::combine_pair_fits(c.T, c.L)) {  // the single-system launch's choice
+    const int chunks = (c.L[0] * c.L[1] * c.L[2] + 255) / 256;
+    dev::combine_pair_body(c, (int)(lb / chunks), (int)(lb % chunks));
+  } else {
+    dev::combine_periodic_body(c, J.asmb.combine_total, lb);
+  }
 }
 
 __global__ __launch_bounds__(dev::kFftThreads) void batch_fft_tables_kernel(
@@ -294,7 +300,12 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
     blocks[kRowMax] = J.asmb.rowmax_blocks;
     blocks[kContract] = J.asmb.contract_blocks;
     blocks[kReduce] = ceil_div(J.asmb.reduce_total, 256);
-    blocks[kCombine] = ceil_div(J.asmb.combine_total, 4);
+    {
+      const dev::CombineArgs& c = J.asmb.combine;
+      blocks[kCombine] = dev::combine_pair_fits(c.T, c.L)
+                             ? (int64_t)c.m0 * c.m0 * ceil_div(c.L[0] * c.L[1] * c.L[2], 256)
+                             : ceil_div(J.asmb.combine_total, 4);
+    }
     blocks[kFftTables] = J.fft.blue ? 1 : 0;
     blocks[kDft] = ceil_div(J.fft.cols, J.fft.W);
     blocks[kHeigh] = g.L[0];
