@@ -152,6 +152,19 @@ __global__ __launch_bounds__(MAXM * MAXM < 64 ? 64 : MAXM * MAXM) void batch_hei
   dev::heigh_body<MAXM>(J.Hb, J.Sb, J.m0, J.evals, nullptr, J.info, lb);
 }
 
+// Eigenvalues of batches with 8 < max m0 <= 16: blocks with m0 <= 8 take the
+// one-wave route (the first wave), larger ones the 256-thread tridiagonal
+// route, as in the single-system launches.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void
+batch_heigh16_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kHeigh)
+  if (J.m0 <= 8) {  // uniform per workgroup
+    if (threadIdx.x < 64) dev::heigh_wave8_body(J.Hb, J.Sb, J.m0, J.evals, nullptr, J.info, lb);
+  } else {
+    dev::heigh_evals16_body(J.Hb, J.Sb, J.m0, J.evals, J.info, lb);
+  }
+}
+
 struct InstanceSizes {
   Geometry g;
   size_t pot_ws, asm_ws, fft_ws;
@@ -443,7 +456,7 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
   if (plan->max_m0 <= 8)
     hipLaunchKernelGGL(batch_heigh_kernel<8>, dim3(blocks(kHeigh)), dim3(64), 0, stream, d);
   else if (plan->max_m0 <= 16)
-    hipLaunchKernelGGL(batch_heigh_kernel<16>, dim3(blocks(kHeigh)), dim3(256), 0, stream, d);
+    hipLaunchKernelGGL(batch_heigh16_kernel, dim3(blocks(kHeigh)), dim3(256), 0, stream, d);
   else
     hipLaunchKernelGGL(batch_heigh_kernel<32>, dim3(blocks(kHeigh)), dim3(1024), 0, stream, d);
   TL_CHECK_LAUNCH();

@@ -158,6 +158,55 @@ __device__ __forceinline__ void sturm_count2_fast(const double (&d)[8], const do
   zero = z;
 }
 
+// The counts of sturm_count2 / sturm_count2_fast over a fixed 16 steps: the
+// caller pads the tridiagonal past m with d = 2 and e2 = 0, which adds no
+// sign change for any x below 2 (the scaled spectrum lies in (-1, 1)), so the
+// loops need no exit test and unroll completely.
+__device__ __forceinline__ void sturm_count16(const double (&d)[16], const double (&e2)[16],
+                                              double x0, double x1, int& c0, int& c1) {
+  constexpr double kTiny = 0x1p-500;
+  double p0 = d[0] - x0, p1 = d[0] - x1, r0 = 1.0, r1 = 1.0;
+  if (p0 == 0.0) p0 = -kTiny;
+  if (p1 == 0.0) p1 = -kTiny;
+  c0 = p0 < 0.0;
+  c1 = p1 < 0.0;
+#pragma unroll
+  for (int u = 1; u < 16; ++u) {
+    double n0 = fma(d[u] - x0, p0, -e2[u - 1] * r0);
+    double n1 = fma(d[u] - x1, p1, -e2[u - 1] * r1);
+    if (n0 == 0.0) n0 = -copysign(kTiny, p0);
+    if (n1 == 0.0) n1 = -copysign(kTiny, p1);
+    c0 += (n0 < 0.0) != (p0 < 0.0);
+    c1 += (n1 < 0.0) != (p1 < 0.0);
+    r0 = p0;
+    r1 = p1;
+    p0 = n0;
+    p1 = n1;
+  }
+}
+
+__device__ __forceinline__ void sturm_count16_fast(const double (&d)[16], const double (&e2)[16],
+                                                   double x0, double x1, int& c0, int& c1,
+                                                   bool& zero) {
+  double p0 = d[0] - x0, p1 = d[0] - x1, r0 = 1.0, r1 = 1.0;
+  bool z = p0 == 0.0 || p1 == 0.0;
+  c0 = signbit(p0);
+  c1 = signbit(p1);
+#pragma unroll
+  for (int u = 1; u < 16; ++u) {
+    const double n0 = fma(d[u] - x0, p0, -e2[u - 1] * r0);
+    const double n1 = fma(d[u] - x1, p1, -e2[u - 1] * r1);
+    z = z || n0 == 0.0 || n1 == 0.0;
+    c0 += signbit(n0) != signbit(p0);
+    c1 += signbit(n1) != signbit(p1);
+    r0 = p0;
+    r1 = p1;
+    p0 = n0;
+    p1 = n1;
+  }
+  zero = z;
+}
+
 // ---------------------------------------------------------------- m0 <= 8
 // One wave per k-block, lane 8 i + j holding entry (i, j) of every 8 x 8
 // (padded) matrix in registers: S, its Cholesky factor L, X = L^-1, C, V.
@@ -442,6 +491,211 @@ __device__ __forceinline__ void heigh_wave8_body(const double* __restrict__ H,
     const int rank_j = __shfl(rank_i, 8 * j);
     if (in) ((cx*)evecs)[blk * mm + i * m + rank_j] = u;
   }
+}
+
+// ---------------------------------------------------------------- 8 < m0 <= 16
+// Eigenvalues only, one 256-thread workgroup per block: thread 16 i + j holds
+// entry (i, j) of the 16 x 16 (padded) matrices, so a row is 16 consecutive
+// lanes of one wave (row sums are DPP reductions) and columns or single
+// entries pass through LDS.  The stages and conventions are those of the
+// m0 <= 8 wave (Cholesky, C = X H X^H with X = L^-1, Hermitian average,
+// zhetd2 reflectors, Sturm bisection of the power-of-two scaled tridiagonal),
+// with 16 lanes and 32 points per eigenvalue and bisection round.
+__device__ __forceinline__ double group16_sum(double v) {
+  v = group8_sum(v);
+  return v + dpp_d<0x140>(v, 0.0);  // row_mirror: the other half of the row of 16
+}
+__device__ __forceinline__ double group16_max(double v) {
+  v = group8_max(v);
+  return fmax(v, dpp_d<0x140>(v, v));
+}
+__device__ __forceinline__ double group16_min(double v) {
+  v = group8_min(v);
+  return fmin(v, dpp_d<0x140>(v, v));
+}
+
+__device__ __forceinline__ void heigh_evals16_body(const double* __restrict__ H,
+                                          const double* __restrict__ S, int m,
+                                          double* __restrict__ evals, int* __restrict__ info,
+                                          int64_t blk) {
+  constexpr int LD = 17;
+  __shared__ cx colbuf[16];
+  __shared__ cx wbuf[16];
+  __shared__ cx Ls[16 * LD];  // L, then W = X H
+  __shared__ cx Xs[16 * LD];  // X = L^-1
+  __shared__ cx Hs[16 * LD];  // H, then C
+  __shared__ double dsh[17];
+  const int t = threadIdx.x, i = t >> 4, j = t & 15;
+  const bool in = i < m && j < m;
+  const int mm = m * m;
+  const cx* Hb = (const cx*)H + blk * mm;
+  const cx* Sb = S ? (const cx*)S + blk * mm : nullptr;
+  const cx h = in ? Hb[i * m + j] : cx{0.0, 0.0};
+  cx s = (in && Sb) ? Sb[i * m + j] : cx{i == j ? 1.0 : 0.0, 0.0};
+  cx c = h;
+  if (Sb) {
+    // 1. Cholesky S = L L^H: column k of the updated S through LDS, one
+    // barrier per pivot (every read of step k precedes the barrier of k + 1)
+    int fail = 0;
+    for (int k = 0; k < m; ++k) {
+      if (j == k) colbuf[i] = s;
+      __syncthreads();
+      const double d = colbuf[k].re;
+      // pivots at or below 1e-300 (and non-finite ones) count as not positive
+      if (!(d > 1e-300) || !isfinite(d)) {  // uniform
+        fail = k + 1;
+        break;
+      }
+      const double inv = nrsq(d), lkk = d * inv;
+      const cx lik = i == k ? cx{lkk, 0.0} : cscale(colbuf[i], inv);
+      const cx ljk = j == k ? cx{lkk, 0.0} : cscale(colbuf[j], inv);
+      if (j == k && i >= k) s = lik;
+      if (j > k && i >= j) s = csub(s, cmul(lik, cconj(ljk)));
+      __syncthreads();  // colbuf is rewritten by the next pivot
+    }
+    if (fail) {
+      if (j == 0 && i < m) evals[blk * m + i] = NAN;
+      if (t == 0) info[blk] = fail;
+      return;
+    }
+    if (j > i) s = {0.0, 0.0};
+    // 2. X = L^-1 (column j by forward substitution in thread j), then
+    // W = X H and C = W X^H, each entry a 16-term sum from LDS
+    Ls[i * LD + j] = s;
+    Hs[i * LD + j] = h;
+    __syncthreads();
+    if (t < 16) {  // column t of X; each thread reads back only what it wrote
+      for (int r = 0; r < 16; ++r) {
+        cx acc = {r == t ? 1.0 : 0.0, 0.0};
+        for (int k = t; k < r; ++k) acc = csub(acc, cmul(Ls[r * LD + k], Xs[k * LD + t]));
+        Xs[r * LD + t] = r < t ? cx{0.0, 0.0} : cscale(acc, 1.0 / Ls[r * LD + r].re);
+      }
+    }
+    __syncthreads();
+    cx w = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) w = cadd(w, cmul(Xs[i * LD + k], Hs[k * LD + j]));
+    Ls[i * LD + j] = w;  // L is no longer read
+    __syncthreads();
+    c = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c = cadd(c, cmul(Ls[i * LD + k], cconj(Xs[j * LD + k])));
+  }
+  // Hermitian average
+  Hs[i * LD + j] = c;
+  __syncthreads();
+  {
+    const cx ct = Hs[j * LD + i];
+    c = i == j ? cx{c.re, 0.0} : cscale(cadd(c, cconj(ct)), 0.5);
+  }
+  // 3. Householder reduction to a real tridiagonal (zhetd2 convention, as
+  // in the m0 <= 8 wave): column k through LDS, w through LDS
+  double e2[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) e2[q] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 14; ++k) {
+    if (k > m - 3) break;  // uniform
+    if (j == k) colbuf[i] = c;
+    __syncthreads();
+    const cx alpha = colbuf[k + 1];
+    double sq = 0.0;
+    for (int q = k + 2; q < m; ++q) sq += cabs2(colbuf[q]);
+    if (sq == 0.0 && alpha.im == 0.0) {  // uniform: already reduced, H = I
+      e2[k] = alpha.re * alpha.re;
+      __syncthreads();  // colbuf is rewritten by the next step
+      continue;
+    }
+    const double s2 = alpha.re * alpha.re + alpha.im * alpha.im + sq;
+    const double rs = nrsq(s2);
+    const double beta = -copysign(s2 * rs, alpha.re), rbeta = -copysign(rs, alpha.re);
+    const cx tau = {(beta - alpha.re) * rbeta, -alpha.im * rbeta};
+    const cx den = {alpha.re - beta, alpha.im};
+    const double dd = nrcp(cabs2(den));
+    const cx rden = {den.re * dd, -den.im * dd};  // 1 / (alpha - beta)
+    const cx vi = i == k + 1 ? cx{1.0, 0.0} : (i > k + 1 ? cmul(colbuf[i], rden) : cx{0.0, 0.0});
+    const cx vj = j == k + 1 ? cx{1.0, 0.0} : (j > k + 1 ? cmul(colbuf[j], rden) : cx{0.0, 0.0});
+    // w_i = tau sum_j C[i][j] v_j over the trailing block (a row is 16 lanes)
+    cx tt = (i > k && j > k) ? cmul(c, vj) : cx{0.0, 0.0};
+    tt.re = group16_sum(tt.re);
+    tt.im = group16_sum(tt.im);
+    cx wi = cmul(tau, tt);
+    if (j == 0) wbuf[i] = wi;
+    __syncthreads();
+    cx wj = wbuf[j];
+    // K = -1/2 tau (w^H v), the same sum in every row
+    cx kk = j > k ? cmul(cconj(wj), vj) : cx{0.0, 0.0};
+    kk.re = group16_sum(kk.re);
+    kk.im = group16_sum(kk.im);
+    const cx K = cscale(cmul(tau, kk), -0.5);
+    wi = cadd(wi, cmul(K, vi));
+    wj = cadd(wj, cmul(K, vj));
+    if (i > k && j > k) c = csub(c, cadd(cmul(vi, cconj(wj)), cmul(wi, cconj(vj))));
+    e2[k] = beta * beta;
+    __syncthreads();  // colbuf and wbuf are rewritten by the next step
+  }
+  // diagonal and the last off-diagonal element (no reflector needed)
+  if (i == j) dsh[i] = c.re;
+  if (i == m - 1 && j == m - 2) dsh[16] = cabs2(c);
+  __syncthreads();
+  double d16[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) d16[q] = dsh[q];
+  if (m >= 2) {
+    const double el = dsh[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q == m - 2) e2[q] = el;
+  }
+  // Gershgorin interval and the power-of-two scaling into (-1, 1)
+  double lo = 1e308, hi = -1e308;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    if (q >= m) break;
+    const double el = q > 0 ? sqrt(e2[q - 1]) : 0.0, er = q < m - 1 ? sqrt(e2[q]) : 0.0;
+    lo = fmin(lo, d16[q] - el - er);
+    hi = fmax(hi, d16[q] + el + er);
+  }
+  const double tn = fmax(fabs(lo), fabs(hi));
+  int ex = 0;
+  if (tn > 0.0 && isfinite(tn)) frexp(tn, &ex);
+  ex += 1;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    d16[q] = ldexp(d16[q], -ex);
+    e2[q] = ldexp(e2[q], -2 * ex);
+  }
+  const double fudge = 2.1 * DBL_EPSILON * m * ldexp(tn, -ex);
+  lo = ldexp(lo, -ex) - fudge;
+  hi = ldexp(hi, -ex) + fudge;
+  const double atol = 2.0 * DBL_EPSILON * ldexp(tn, -ex);
+  // padding past m: d = 2, e2 = 0 (no sign change below x = 2)
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (q >= m) d16[q] = 2.0;
+  // 4. eigenvalue idx = row i; each lane counts at two points, so a round
+  // splits the bracket at 32 interior points per eigenvalue
+  const int idx = i, pt = j;
+  const double f0 = (double)(2 * pt + 1) / 33.0, f1 = (double)(2 * pt + 2) / 33.0;
+  for (int round = 0; round < 40; ++round) {
+    const bool done = hi - lo <= fmax(atol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)));
+    if (__all(done || idx >= m)) break;  // per wave: no barrier below
+    const double x0 = lo + (hi - lo) * f0, x1 = lo + (hi - lo) * f1;
+    int c0, c1;
+    bool zero;
+    sturm_count16_fast(d16, e2, x0, x1, c0, c1, zero);
+    if (__any(zero)) sturm_count16(d16, e2, x0, x1, c0, c1);  // rare
+    double nlo = c1 <= idx ? x1 : (c0 <= idx ? x0 : lo);
+    double nhi = c0 > idx ? x0 : (c1 > idx ? x1 : hi);
+    nlo = group16_max(nlo);
+    nhi = group16_min(nhi);
+    if (!done) {
+      lo = nlo;
+      hi = fmax(nhi, nlo);
+    }
+  }
+  if (pt == 0 && idx < m) evals[blk * m + idx] = ldexp(0.5 * (lo + hi), ex);
+  if (t == 0) info[blk] = 0;
 }
 
 // One k-block per workgroup; blk is the block index (H, S, evals, evecs and

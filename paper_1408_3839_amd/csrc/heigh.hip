@@ -3,11 +3,12 @@
 // on block-circulant diagonalisation, eq. (lambdAbc)).
 //
 // Per block: Cholesky Sbar = L L^H, C = L^-1 Hbar L^-H (Hermitian average),
-// then either eigenvalues only (m <= 8: Householder reduction of C to a real
+// then either eigenvalues only (m <= 16: Householder reduction of C to a real
 // tridiagonal and Sturm bisection) or complex Jacobi with the parallel
 // round-robin ordering and eigenvectors u = L^-H v.  m <= 8 runs in one wave
 // with the matrices in registers; larger m uses one workgroup per block and
-// LDS.  Eigenvalues ascending.
+// LDS (256 threads, one per entry, for the eigenvalues of m <= 16).
+// Eigenvalues ascending.
 #include <cmath>
 
 #include "common.h"
@@ -37,6 +38,14 @@ __global__ __launch_bounds__(64) void heigh_evals_kernel(const double* __restric
   dev::heigh_wave8_body(H, S, m, evals, nullptr, info, blk, w, m);
 }
 
+// Eigenvalues only, 8 < m <= 16: one 256-thread workgroup per block.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void heigh_evals16_kernel(const double* __restrict__ H,
+                                                            const double* __restrict__ S, int m,
+                                                            double* __restrict__ evals,
+                                                            int* __restrict__ info) {
+  dev::heigh_evals16_body(H, S, m, evals, info, blockIdx.x);
+}
+
 }  // namespace
 
 tl_status batched_heigh(const double* H, const double* S, int count, int m, double* evals,
@@ -48,6 +57,9 @@ tl_status batched_heigh(const double* H, const double* S, int count, int m, doub
   } else if (m <= 8) {
     hipLaunchKernelGGL(heigh_kernel<8>, dim3(count), dim3(threads), 0, stream, H, S, m, evals,
                        evecs, info);
+  } else if (m <= 16 && evecs == nullptr) {
+    hipLaunchKernelGGL(heigh_evals16_kernel, dim3(count), dim3(256), 0, stream, H, S, m, evals,
+                       info);
   } else if (m <= 16) {
     hipLaunchKernelGGL(heigh_kernel<16>, dim3(count), dim3(threads), 0, stream, H, S, m, evals,
                        evecs, info);

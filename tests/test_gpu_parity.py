@@ -329,12 +329,13 @@ def test_graph_replay_matches_eager():
         assert torch.equal(pl.evals, ev0), rep
 
 
-@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 7, 8])
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 7, 8, 9, 10, 12, 13, 15, 16])
 @pytest.mark.parametrize("standard", [False, True])
 def test_heigh_eigenvalues_only(m, standard):
-    """Without eigenvectors, m0 <= 8 blocks take the Householder-tridiagonal +
-    Sturm-bisection route; eigenvalues against LAPACK within the first-order
-    bound, ascending, info = 0."""
+    """Without eigenvectors, m0 <= 16 blocks take the Householder-tridiagonal +
+    Sturm-bisection route (one wave for m0 <= 8, 256 threads above);
+    eigenvalues against LAPACK within the first-order bound, ascending,
+    info = 0."""
     rng = np.random.default_rng(300 + m + 50 * standard)
     H, S = _random_pencils(rng, 41, m)
     if standard:
@@ -348,12 +349,12 @@ def test_heigh_eigenvalues_only(m, standard):
         assert np.all(np.diff(ev[j]) >= 0)
 
 
-def test_heigh_eigenvalues_only_degenerate_and_reduced():
+@pytest.mark.parametrize("m", [8, 16])
+def test_heigh_eigenvalues_only_degenerate_and_reduced(m):
     """Exactly repeated eigenvalues and an already diagonal block (every
     reflector is the identity) on the eigenvalue-only route."""
-    m = 8
     H = np.zeros((3, m, m), complex)
-    H[0] = np.diag([1.0, 1.0, 1.0, 2.0, 2.0, -3.0, 0.5, 0.5])
+    H[0] = np.diag(np.resize([1.0, 1.0, 1.0, 2.0, 2.0, -3.0, 0.5, 0.5], m))
     Q, _ = np.linalg.qr(np.random.default_rng(4).standard_normal((m, m))
                         + 1j * np.random.default_rng(5).standard_normal((m, m)))
     H[1] = Q @ H[0] @ Q.conj().T
@@ -361,6 +362,10 @@ def test_heigh_eigenvalues_only_degenerate_and_reduced():
     H[2] = np.diag(np.arange(m, dtype=float)) + np.diag(np.full(m - 1, 0.25), 1) + np.diag(np.full(m - 1, 0.25), -1)
     ev, _, info = _run_heigh(H, None, evecs=False)
     assert np.all(info == 0)
+    S = np.broadcast_to(np.eye(m), H.shape).astype(complex)
+    S[1][0, 0] = 0.0  # not definite at the first pivot: reported, the others unaffected
+    ev2, _, info2 = _run_heigh(H, S, evecs=False)
+    assert info2[1] == 1 and np.all(np.isnan(ev2[1])) and info2[0] == 0 and info2[2] == 0
     for j in range(3):
         lam = np.linalg.eigvalsh(H[j])
         assert np.abs(ev[j] - lam).max() <= 64 * 2.0 ** -52 * np.abs(lam).max(), (j, ev[j] - lam)
