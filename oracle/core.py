@@ -372,6 +372,35 @@ def kblock_eigvals(Hbar: np.ndarray, Sbar: np.ndarray = None) -> np.ndarray:
     return ev.reshape(shp + (m0,))
 
 
+def unitary_dft(L: int) -> np.ndarray:
+    """F_L = L^(-1/2) [omega^(jk)], omega = exp(-2 pi i / L) (Sec. 2, the
+    Fourier matrix that diagonalises the cyclic shift)."""
+    j = np.arange(L)
+    return np.exp(-2j * math.pi * (np.outer(j, j) % L) / L) / math.sqrt(L)
+
+
+def bloch_vectors(u: np.ndarray, L: Sequence[int], states: Sequence[int]) -> np.ndarray:
+    """Eigenvectors of the block-circulant pencil from those of its k-blocks,
+    eq. (eigvecA): U_(j,m) = (F^* x I_m0) Ubar_(j,m), Ubar_(j,m) =
+    E_[j] vec[u_(0,m), ..., u_(L-1,m)], i.e. u_(j,m) in block j and zeros
+    elsewhere; three levels with F = F_L1 x F_L2 x F_L3 (Kronecker products,
+    written out as dense matrices).
+    u: [L1 L2 L3][m0][m0] complex, column m = eigenvector m of block j;
+    states: flat indices j m0 + m.  Returns [len(states)][L1 L2 L3 m0]."""
+    L1, L2, L3 = (int(v) for v in L)
+    m0 = u.shape[-1]
+    nc = L1 * L2 * L3
+    F = np.kron(np.kron(unitary_dft(L1), unitary_dft(L2)), unitary_dft(L3))
+    W = np.kron(F.conj().T, np.eye(m0))
+    out = np.zeros((len(states), nc * m0), dtype=np.complex128)
+    for r, st in enumerate(states):
+        j, m = divmod(int(st), m0)
+        Ubar = np.zeros(nc * m0, dtype=np.complex128)
+        Ubar[j * m0:(j + 1) * m0] = u.reshape(nc, m0, m0)[j][:, m]
+        out[r] = W @ Ubar
+    return out
+
+
 def lowest_generalized_eigs(H: np.ndarray, S: np.ndarray, k: int):
     """Lowest k eigenpairs of the symmetric-definite pencil (H, S)."""
     w, v = sla.eigh(H, S, subset_by_index=[0, k - 1])
