@@ -308,6 +308,24 @@ tl_status tl_batched_heigh(const double* H_dev, const double* S_dev, int count, 
                            double* evals_dev, double* evecs_dev, int* info_dev, void* stream);
 
 /*
+ * tl_bloch_vectors - eigenvectors of the full block-circulant pencil from
+ * those of its k-blocks (Appendix, Proposition on block-circulant
+ * diagonalisation, eq. (eigvecA)): with F = F_L1 x F_L2 x F_L3 unitary,
+ *   U_(j,m) = (F^* x I_m0) (e_j x u_(j,m)),
+ *   U_(j,m)[c][mu] = L^(-1/2) exp(2 pi i sum_l j_l c_l / L_l) u_(j,m)[mu],
+ *   L = L1 L2 L3, j and c flat indices [j1][j2][j3], [c1][c2][c3].
+ *   evecs_dev: [L][m0][m0] complex, column m = eigenvector m of block j (the
+ *   layout tl_batched_heigh writes; S-normalised vectors there give
+ *   U^H S U = 1 for the full mass matrix).
+ *   states_dev: n_states int32 in device memory, flat state indices j*m0 + m;
+ *   an index outside [0, L*m0) yields a NaN vector.
+ *   out_dev: [n_states][L][m0] complex (interleaved re, im), row r = state r.
+ * Errors: TL_EINVAL for sizes out of range or a null array with n_states > 0.
+ */
+tl_status tl_bloch_vectors(const double* evecs_dev, int L1, int L2, int L3, int m0,
+                           const int* states_dev, int n_states, double* out_dev, void* stream);
+
+/*
  * tl_dense_gen_eigh_lowest - the k lowest eigenpairs of the full symmetric
  * pencil H u = lambda S u, S positive definite (the open-boundary chain's
  * core Hamiltonian and mass matrix, Sec. 5's full eigensolver; Sec. 2.1

@@ -90,6 +90,18 @@ class PeriodicPipeline:
         tl.tl_batched_heigh(self.HSbar[0], self.HSbar[1], self.nblocks, self.m0, self.evals,
                             self.evecs, self.info, stream)
 
+    def bloch_vectors(self, states, stream=None):
+        """Full-lattice eigenvectors of the given flat states j*m0 + m (needs
+        with_evecs): [len(states)][L1 L2 L3][m0] complex (last axis re, im)."""
+        if self.evecs is None:
+            raise ValueError("bloch_vectors needs a pipeline built with with_evecs=True")
+        st = torch.as_tensor(states, dtype=torch.int32).to(self.device)
+        out = torch.empty(st.numel(), self.nblocks, self.m0, 2, dtype=torch.float64,
+                          device=self.device)
+        L = self.L
+        tl.tl_bloch_vectors(self.evecs, L[0], L[1], L[2], self.m0, st, st.numel(), out, stream)
+        return out
+
     def basis_and_potential(self, stream=None):
         tl.tl_build_basis_and_potential(self.handle, self.G, self.AG, self.SG, self.P,
                                         self.pot_ws, self.pot_ws_bytes, stream)

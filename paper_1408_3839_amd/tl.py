@@ -124,6 +124,8 @@ SIGNATURES = {
     "tl_batched_heigh": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "tl_bloch_vectors": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 4
+                         + [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "tl_dense_gen_eigh_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int,
                                                          ctypes.POINTER(ctypes.c_size_t)]),
     "tl_set_dense_eigh_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -352,6 +354,11 @@ def tl_block_fft(inp, L1, L2, L3, m0, batch, out, ws=None, ws_bytes=0, stream=No
 def tl_batched_heigh(H, S, count, m0, evals, evecs, info, stream=None):
     _check(load().tl_batched_heigh(_ptr(H), _ptr(S), int(count), int(m0), _ptr(evals),
                                    _ptr(evecs), _ptr(info), _stream(stream)), "tl_batched_heigh")
+
+
+def tl_bloch_vectors(evecs, L1, L2, L3, m0, states, n_states, out, stream=None):
+    _check(load().tl_bloch_vectors(_ptr(evecs), int(L1), int(L2), int(L3), int(m0), _ptr(states),
+                                   int(n_states), _ptr(out), _stream(stream)), "tl_bloch_vectors")
 
 
 def tl_dense_gen_eigh_workspace_bytes(N, k) -> int:

@@ -178,3 +178,11 @@ def test_kblocks_queries_and_rejections():
             b - 256, 0)
     _expect(tl.tl_assemble_kblocks, tl.TL_EINVAL, s, 8, 8, 8, 8, tl.TL_SPLIT_FP16, 9, 8, 8, 8,
             b, 0)
+
+
+def test_bloch_vectors_validation():
+    _expect(tl.tl_bloch_vectors, tl.TL_EINVAL, 8, 0, 1, 1, 4, 8, 3, 8, 0)
+    _expect(tl.tl_bloch_vectors, tl.TL_EINVAL, 8, 4, 1, 1, 33, 8, 3, 8, 0)
+    _expect(tl.tl_bloch_vectors, tl.TL_EINVAL, 8, 4, 1, 1, 4, 8, -1, 8, 0)
+    _expect(tl.tl_bloch_vectors, tl.TL_EINVAL, 0, 4, 1, 1, 4, 8, 3, 8, 0)
+    tl.tl_bloch_vectors(0, 4, 1, 1, 4, 0, 0, 0, 0)  # no states: nothing to do, no launch
