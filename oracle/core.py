@@ -283,11 +283,15 @@ def cell_origins(sys) -> np.ndarray:
     return np.array(out, dtype=np.float64)
 
 
-def full_matrices(sys, rows: Sequence[int] = None, cols: Sequence[int] = None):
+def full_matrices(sys, rows: Sequence[int] = None, cols: Sequence[int] = None,
+                  absolute: bool = False):
     """H and S over all N_b = ncells*m0 functions (cell-major, function-minor),
     every entry from the 1D inner products of explicitly sampled functions:
     H_fg = 1/2 sum_d <A_d g_f, g_g> prod_{e!=d} <S_e g_f, g_g> - sum_t prod_d <g_f p_t g_g>.
-    Optional `rows`/`cols` restrict the computation to a sub-block."""
+    Optional `rows`/`cols` restrict the computation to a sub-block.
+    absolute=True returns the entry scales instead (the same formula, every 1D
+    sum over absolute values of its products, |A| = (1/h) tridiag(1,2,1), the
+    terms of H added in magnitude), as core_hamiltonian_blocks' `scale`."""
     origins = cell_origins(sys)
     P = potential_vectors(sys)
     Nb = origins.shape[0] * sys.m0
@@ -298,11 +302,19 @@ def full_matrices(sys, rows: Sequence[int] = None, cols: Sequence[int] = None):
         Gall = _all_function_samples(sys, d, origins)
         per = bool(sys.periodic[d])
         Gr, Gc = Gall[rows], Gall[cols]
-        Cs.append(np.stack([(Gr * P[d][t]) @ Gc.T for t in range(P[d].shape[0])]))
-        Ds.append(fem_stiffness(Gr, per, sys.h) @ Gc.T)
+        Pd = P[d]
+        if absolute:
+            Gr, Gc, Pd = np.abs(Gr), np.abs(Gc), np.abs(Pd)
+        Cs.append(np.stack([(Gr * Pd[t]) @ Gc.T for t in range(Pd.shape[0])]))
+        if absolute:
+            Ds.append((4.0 * Gr / sys.h - fem_stiffness(Gr, per, sys.h)) @ Gc.T)
+        else:
+            Ds.append(fem_stiffness(Gr, per, sys.h) @ Gc.T)
         Ms.append(fem_mass(Gr, per, sys.h) @ Gc.T)
     V = np.sum(Cs[0] * Cs[1] * Cs[2], axis=0)
     T = 0.5 * (Ds[0] * Ms[1] * Ms[2] + Ms[0] * Ds[1] * Ms[2] + Ms[0] * Ms[1] * Ds[2])
+    if absolute:
+        return T + V, Ms[0] * Ms[1] * Ms[2]
     return T - V, Ms[0] * Ms[1] * Ms[2]
 
 

@@ -359,6 +359,28 @@ def test_bloch_vectors_are_eigenvectors_of_the_full_pencil(L):
     np.testing.assert_allclose(U[cf * m0:(cf + 1) * m0, jf * m0], ph * u[jf][:, 0], atol=1e-14)
 
 
+def test_full_matrix_scales():
+    """The entry scales of the explicit full matrices: on a torus they equal
+    the block-circulant matrix of the shift-structured scales (two separate
+    constructions); they bound |H| and |S| entry by entry (triangle
+    inequality); for an open chain of s functions (positive samples) the
+    mass-matrix scale is S itself (no product changes sign)."""
+    s = wl.tiny_periodic(L=(3, 2, 1), m0=3, c=6, h=0.3, R=8, alpha_range=(0.25, 2.0))
+    H, S, scale = oracle.core_hamiltonian_blocks(s)
+    Ha, Sa = oracle.full_matrices(s, absolute=True)
+    Hf, Sf = oracle.full_matrices(s)
+    np.testing.assert_allclose(Ha, oracle.bcirc_full(scale), rtol=1e-12, atol=1e-15 * Ha.max())
+    assert np.all(np.abs(Hf) <= Ha * (1 + 1e-12) + 1e-300)
+    assert np.all(np.abs(Sf) <= Sa * (1 + 1e-12) + 1e-300)
+    b = wl.box_chain_system("b3", 3, 1.5, [1.0, 2.0], 0.2, [60, 40, 40], 3, (0.4, 2.0), 10,
+                            seed=9)
+    assert np.all(b.fn_l == 0)
+    Hb, Sb = oracle.full_matrices(b)
+    Hba, Sba = oracle.full_matrices(b, absolute=True)
+    np.testing.assert_allclose(Sba, Sb, rtol=1e-14)
+    assert np.all(np.abs(Hb) <= Hba * (1 + 1e-12))
+
+
 def test_fourier_blocks_hermitian_and_conjugate_pairs():
     """Symmetric block-circulant => Hermitian Fourier blocks,
     Abar_{L-j} = conj(Abar_j), real blocks for a mirror-symmetric s basis."""
