@@ -207,32 +207,43 @@ def measure(sys_, precision, n_slices, steps, warmup, route="block_fft"):
     }
 
 
-def box_contraction_flops(s, tile: int = 32) -> float:
-    """MFMA work of the open chain's x contraction: per (mu <= nu) function
-    pair and 32 x 32 cell tile, two contractions (H and mass form) of
-    rows x cols entries over the tile's node range (where both tiles'
-    Gaussians are above exp(-46) of their peak), 2 flops per product."""
+def box_contraction_work(s, tile: int = 32):
+    """Flops of the open chain's x contraction (two contractions per entry, H
+    and the mass form, 2 flops per product).  `algorithmic`: every entry over
+    the nodes where both of its own Gaussians are above exp(-46) of their
+    peak, each unordered pair of functions once.  `executed`: what the
+    kernel's MFMA tiles run, 32 x 32 cells (partial tiles padded) over the
+    node range where the two tiles' supports meet, per function pair mu <= nu
+    (mu = nu: the upper triangle of tiles)."""
     L0, m0, n, h = int(s.L[0]), s.m0, int(s.n[0]), float(s.h)
     org, a0, x0 = float(s.cell_origin[0][0]), float(s.a[0]), float(s.x0[0])
     cen = s.fn_center[:, 0]
     rad = np.sqrt(46.0 / s.fn_alpha) + h
+    cells = np.arange(L0)
+
+    def node_range(lo, hi):
+        lo, hi = (lo - x0) / h, (hi - x0) / h
+        klo = np.where(lo <= 0, 0, np.minimum(np.ceil(lo), n))
+        khi = np.where(hi < 0, 0, np.minimum(np.floor(hi) + 1, n))
+        return np.maximum(khi - klo, 0)
+
+    alg = exe = 0.0
     nt = -(-L0 // tile)
-    total = 0.0
     for mu in range(m0):
         for nu in range(mu, m0):
+            xm = org + cells * a0 + cen[mu]
+            xn = org + cells * a0 + cen[nu]
+            K = node_range(np.maximum.outer(xm - rad[mu], xn - rad[nu]),
+                           np.minimum.outer(xm + rad[mu], xn + rad[nu]))
+            alg += 4.0 * (np.triu(K).sum() if mu == nu else K.sum())
             for tr in range(nt):
                 for tc in range(tr if mu == nu else 0, nt):
                     r0, r1 = tr * tile, min(L0, tr * tile + tile) - 1
                     c0, c1 = tc * tile, min(L0, tc * tile + tile) - 1
-                    lo = (max(org + r0 * a0 + cen[mu] - rad[mu], org + c0 * a0 + cen[nu] - rad[nu])
-                          - x0) / h
-                    hi = (min(org + r1 * a0 + cen[mu] + rad[mu], org + c1 * a0 + cen[nu] + rad[nu])
-                          - x0) / h
-                    klo = 0 if lo <= 0 else min(int(np.ceil(lo)), n)
-                    khi = 0 if hi < 0 else min(int(np.floor(hi)) + 1, n)
-                    if khi > klo:
-                        total += 4.0 * (r1 - r0 + 1) * (c1 - c0 + 1) * (khi - klo)
-    return total
+                    k = node_range(max(xm[r0] - rad[mu], xn[c0] - rad[nu]),
+                                   min(xm[r1] + rad[mu], xn[c1] + rad[nu]))
+                    exe += 4.0 * tile * tile * float(k)
+    return {"algorithmic": float(alg), "executed": float(exe)}
 
 
 def box_chain_section(steps: int, warmup: int):
@@ -281,7 +292,8 @@ def box_chain_section(steps: int, warmup: int):
     asm_ms, eig_ms = float(np.median(asm)), float(np.median(eig))
     # the x contraction alone, in FP64 and the split modes; entries against
     # the FP64 path, eigenvalues (FP64 eigensolver) against the oracle's
-    flops = box_contraction_flops(s)
+    work = box_contraction_work(s)
+    flops = work["algorithmic"]
     H64, S64 = bp.H.clone(), bp.S.clone()
     modes = {}
     for prec, nsl in (("fp64", 0), ("split_fp16", 5), ("split_bf16", 6)):
@@ -307,7 +319,7 @@ def box_chain_section(steps: int, warmup: int):
              "x_contraction_roofline": {
                  "bound": "mfma", "achieved": flops / (c_ms * 1e-3) / 1e12, "peak": peak,
                  "unit": "TFLOP/s", "frac": flops / (c_ms * 1e-3) / 1e12 / peak,
-                 "algorithmic_flops": flops,
+                 "algorithmic_flops": flops, "executed_flops": work["executed"],
                  "note": "fp64 MFMA peak" if prec == "fp64" else
                          "fp16/bf16 MFMA peak; flops of the FP64 problem, not of the slices"},
              "max_abs_dH_rel_vs_fp64": float((bq.H - H64).abs().max() / H64.abs().max()),
@@ -389,6 +401,51 @@ def cubic_section(steps: int, warmup: int):
         if ok.any():
             acc.update(eig_errors(r["evals"], Hb, Sb, s.m0, ok))
         out["kspace_route_" + prec + (f"x{nsl}" if nsl else "")] = acc
+    return out
+
+
+def energy_per_cell(evals, L: int) -> float:
+    """Average energy per unit cell: the sum of the L lowest eigenvalues (one
+    state per cell) divided by L."""
+    ev = np.sort(np.asarray(evals, dtype=np.float64).ravel())
+    return float(ev[:L].sum() / L)
+
+
+def spectra_section():
+    """Periodic versus open (L,1,1) chains of the same cell (a = 2.0 bohr,
+    Z = 1, m0 = 4 s functions, h = 0.125, R = 20, 16-bohr transverse box):
+    the periodic bands (range of each band over the L k-points), the lowest
+    eigenvalues of both, and the average energy per cell, for L = 16, 32, 64."""
+    import torch
+    from paper_1408_3839_amd import workloads
+    from paper_1408_3839_amd.pipeline import BoxPipeline, PeriodicPipeline
+    out = {"workload": "(L,1,1) chains, a=2.0 bohr, Z=1, m0=4 s (alpha log-uniform "
+                       "[0.1,20], seed 1), h=0.125, R=20; periodic torus vs open box "
+                       "with 16-bohr margins"}
+    for L in (16, 32, 64):
+        per = workloads.periodic_system(f"chain{L}", [L, 1, 1], [2.0, 0, 0], 0.125,
+                                        [0, 16.0, 16.0], [[0, 0, 0]], [1.0], 4, (0.1, 20.0), 20,
+                                        seed=1)
+        box = workloads.box_chain_system(f"box{L}", L, 2.0, [1.0], 0.125,
+                                         [16 * L + 256, 128, 128], 4, (0.1, 20.0), 20, seed=1)
+        pl = PeriodicPipeline(per)
+        pl.run()
+        k = min(64, 4 * L)
+        bp = BoxPipeline(box, k=k, with_evecs=False)
+        bp.run()
+        torch.cuda.synchronize()
+        ev_p = pl.evals.cpu().numpy()          # [L][4], k-point j, band m
+        ev_b = bp.eig.evals.cpu().numpy()      # lowest k of the open chain
+        out[f"L{L}"] = {
+            "bands_min_Ha": [float(v) for v in ev_p.min(axis=0)],
+            "bands_max_Ha": [float(v) for v in ev_p.max(axis=0)],
+            "periodic_lowest_Ha": float(ev_p.min()),
+            "box_lowest_Ha": float(ev_b[0]),
+            "box_info": int(bp.eig.info.item()),
+            "energy_per_cell_periodic_Ha": energy_per_cell(ev_p, L),
+            "energy_per_cell_box_Ha": energy_per_cell(ev_b, L),
+        }
+        del pl, bp
     return out
 
 
@@ -593,6 +650,8 @@ def main():
     ap.add_argument("--no-box", action="store_true", help="skip the open-chain section")
     ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch section")
     ap.add_argument("--no-cubic", action="store_true", help="skip the (8,8,8) lattice section")
+    ap.add_argument("--no-spectra", action="store_true",
+                    help="skip the periodic-vs-open chain spectra section")
     ap.add_argument("--no-stages", action="store_true",
                     help="skip the lattice-sum / FFT HBM section")
     ap.add_argument("--stages-only", action="store_true",
@@ -717,6 +776,8 @@ def main():
         out["batch"] = batch_section(min(args.steps, 10), 2)
     if not args.no_stages:
         out["stage_rooflines"] = stage_section()
+    if not args.no_spectra:
+        out["spectra"] = spectra_section()
     print(json.dumps(out))
 
 

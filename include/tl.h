@@ -299,10 +299,11 @@ tl_status tl_block_fft(const double* in_dev, int L1, int L2, int L3, int m0, int
  *   complex, column m = eigenvector of evals[m], normalised u^H Sbar u = 1.
  *   info_dev: [count] int, 0 = converged, k > 0 = Sbar not positive definite
  *   at pivot k (evals set to NaN), -1 = Jacobi iteration did not converge.
- * Method: Cholesky Sbar = L L^H, C = L^-1 Hbar L^-H, then for m0 <= 8
+ * Method: Cholesky Sbar = L L^H, C = L^-1 Hbar L^-H, then for m0 <= 16
  * without eigenvectors (evecs_dev NULL) a complex Householder reduction of C
- * to a real tridiagonal and Sturm bisection, otherwise cyclic parallel
- * complex Jacobi with u = L^-H v.  1 <= m0 <= TL_MAX_M0.
+ * to a real tridiagonal and Sturm bisection (one wave per block for m0 <= 8,
+ * 256 threads above), otherwise cyclic parallel complex Jacobi with
+ * u = L^-H v.  1 <= m0 <= TL_MAX_M0.
  */
 tl_status tl_batched_heigh(const double* H_dev, const double* S_dev, int count, int m0,
                            double* evals_dev, double* evecs_dev, int* info_dev, void* stream);

@@ -15,6 +15,16 @@ def _small_box():
                                10, seed=21)
 
 
+def _per_entry(A, Ar, scale, dr, dc):
+    """|A - Ar| per entry against its no-cancellation scale, with the floor of
+    the support cutoff: the dropped products are below exp(-46) ~ 1e-20 of
+    either function's peak, so an entry moves by at most ~1e-18 of the
+    geometric mean of the two functions' own diagonal scales.  A value <= 1e-10
+    means |dA| <= 1e-10 scale + 1e-18 sqrt(scale_ff scale_gg)."""
+    floor = 1e-8 * np.sqrt(np.outer(dr, dc))
+    return np.abs(A - Ar) / (scale + floor)
+
+
 def test_box_small_full_matrices():
     from paper_1408_3839_amd.pipeline import BoxPipeline
     s = _small_box()
@@ -24,11 +34,16 @@ def test_box_small_full_matrices():
     H = bp.H.cpu().numpy()
     S = bp.S.cpu().numpy()
     Hr, Sr = oracle.full_matrices(s)
+    Ha, Sa = oracle.full_matrices(s, absolute=True)
     eh = np.abs(H - Hr).max() / np.abs(Hr).max()
     es = np.abs(S - Sr).max() / np.abs(Sr).max()
-    print(f"box12: max|dH|/max|H| = {eh:.3e}, max|dS|/max|S| = {es:.3e}")
+    ph = _per_entry(H, Hr, Ha, np.diag(Ha), np.diag(Ha))
+    ps = _per_entry(S, Sr, Sa, np.diag(Sa), np.diag(Sa))
+    print(f"box12: max|dH|/max|H| = {eh:.3e}, max|dS|/max|S| = {es:.3e}; per entry "
+          f"{ph.max():.3e} / {ps.max():.3e}")
     assert np.array_equal(H, H.T) and np.array_equal(S, S.T)
     assert eh <= 1e-12 and es <= 1e-12
+    assert ph.max() <= 1e-10 and ps.max() <= 1e-10
 
 
 def test_box_chain_256_sampled_entries():
@@ -49,12 +64,25 @@ def test_box_chain_256_sampled_entries():
                                      rng.integers(0, 2048, 16)]))
     cols = np.unique(np.concatenate([rows, rng.integers(0, 2048, 24)]))
     Hr, Sr = oracle.full_matrices(s, rows=rows, cols=cols)
+    Ha, Sa = oracle.full_matrices(s, rows=rows, cols=cols, absolute=True)
+    both = np.union1d(rows, cols)
+    Hd, Sd = oracle.full_matrices(s, rows=both, cols=both, absolute=True)
+    pos = {f: i for i, f in enumerate(both)}
+    ir, ic = [pos[f] for f in rows], [pos[f] for f in cols]
     Hg = H.cpu().numpy()[np.ix_(rows, cols)]
     Sg = S.cpu().numpy()[np.ix_(rows, cols)]
     eh = np.abs(Hg - Hr).max() / np.abs(Hr).max()
     es = np.abs(Sg - Sr).max() / np.abs(Sr).max()
-    print(f"chain256: max|dH|/max|H| = {eh:.3e}, max|dS|/max|S| = {es:.3e}")
+    ph = _per_entry(Hg, Hr, Ha, np.diag(Hd)[ir], np.diag(Hd)[ic])
+    ps = _per_entry(Sg, Sr, Sa, np.diag(Sd)[ir], np.diag(Sd)[ic])
+    print(f"chain256: max|dH|/max|H| = {eh:.3e}, max|dS|/max|S| = {es:.3e}; per entry "
+          f"{ph.max():.3e} / {ps.max():.3e}")
+    for name, p_, A, Ar, Aa in (("H", ph, Hg, Hr, Ha), ("S", ps, Sg, Sr, Sa)):
+        r_, c_ = np.unravel_index(np.argmax(p_), p_.shape)
+        print(f"  worst {name}: f={rows[r_]} f'={cols[c_]} gpu={A[r_, c_]:.6e} oracle={Ar[r_, c_]:.6e} "
+              f"scale={Aa[r_, c_]:.3e} max scale={Aa.max():.3e}")
     assert eh <= 1e-12 and es <= 1e-12
+    assert ph.max() <= 1e-10 and ps.max() <= 1e-10
 
 
 def test_box_chain_graph_replay():
