@@ -465,8 +465,10 @@ def batch_section(steps: int, warmup: int):
     flops = sum(contraction_flops(s, tl.tl_query_sizes(s)) for s in systems)
     results = {}
     for prec, nsl in (("fp64", 0), ("split_fp16", 5), ("split_bf16", 6)):
-        want, tuning = autotune.tune_batch(systems, precision=prec, n_slices=nsl, cache_path=None)
-        bp = BatchPipeline(systems, precision=prec, n_slices=nsl, want_blocks=want)
+        (want, edge), tuning = autotune.tune_batch(systems, precision=prec, n_slices=nsl,
+                                                   cache_path=None)
+        bp = BatchPipeline(systems, precision=prec, n_slices=nsl, want_blocks=want,
+                           tile_edge=edge)
         for _ in range(max(1, warmup)):
             bp.run()
         bp.capture()
@@ -497,7 +499,7 @@ def batch_section(steps: int, warmup: int):
             "k_blocks": nkb,
             "contraction_ms": cms,
             "contraction_tflops": flops * mult / (cms * 1e-3) / 1e12,
-            "tuned_want_blocks": want,
+            "tuned_want_blocks": want, "tuned_tile_edge": edge,
             "tuning_contraction_ms": {str(k): round(v, 4) for k, v in tuning.items()},
         }
         results[prec + (f"x{nsl}" if nsl else "")] = (

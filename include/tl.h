@@ -385,7 +385,10 @@ tl_status tl_dense_gen_eigh_lowest(const double* H_dev, const double* S_dev, int
  *       the descriptor (launch geometry) and its device copy (arguments).
  *       Allocates nothing and copies nothing: capturable in a HIP graph.
  * want_blocks is the tiling target of the contraction (workgroups per
- * instance; 0 = library default), the parameter the autotuner chooses.
+ * instance; 0 = library default) and plan.tile_edge the largest tile edge of
+ * the FP64 contraction (64 or 32; an instance whose tiles do not fit the LDS
+ * budget takes the smaller edge): the parameters the autotuner chooses.
+ * tl_batch_write_descriptor returns TL_EINVAL for another tile_edge.
  * Same arithmetic per instance as the single-system calls (bitwise equal
  * for equal want_blocks).
  */
@@ -395,6 +398,8 @@ typedef struct {
   int max_m0, max_len;
   int64_t basis_elems, pot_elems, hs_elems, eval_elems, kblocks;
   size_t ws_bytes, desc_bytes;
+  int tile_edge;  /* FP64 contraction tile edge, 64 (default) or 32; may be
+                     changed between plan creation and descriptor writing */
 } tl_batch_plan;
 
 typedef struct {

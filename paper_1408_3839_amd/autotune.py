@@ -1,10 +1,13 @@
 """Tile autotuner of the batched path.
 
-The contraction's tiling target (workgroups per instance the node chunks are
-split for) is the free parameter: fewer, longer chunks mean fewer partial
-sums to reduce; more chunks fill the chip.  For a given batch the candidates
-are timed on the device with HIP events around the contraction launch and the
-fastest is kept in a JSON cache keyed by the batch's shape and precision.
+Two parameters of the contraction are tuned: the tiling target (workgroups
+per instance the node chunks are split for: fewer, longer chunks mean fewer
+partial sums to reduce, more chunks fill the chip) and, for FP64, the tile
+edge (64 x 64 tiles with four 16 x 16 MFMA blocks per wave, or 32 x 32 tiles:
+4x more, smaller workgroups over the same chunks).  For a given batch every
+candidate pair is timed on the device with HIP events around the contraction
+launch and the fastest is kept in a JSON cache keyed by the batch's shape
+and precision.
 """
 from __future__ import annotations
 
@@ -17,6 +20,7 @@ import numpy as np
 from . import tl
 
 CANDIDATES = (128, 256, 512, 1024, 2048, 4096)
+TILE_EDGES = (64, 32)   # FP64 only; the split kernels have one tile shape
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "tl_tuning.json")
 
 
@@ -46,8 +50,8 @@ def _time_contraction(bp, reps: int) -> float:
 
 
 def tune_batch(systems, precision: str = "fp64", n_slices: int = 0, candidates=CANDIDATES,
-               reps: int = 3, cache_path: str | None = DEFAULT_CACHE):
-    """Return (best want_blocks, {candidate: contraction ms})."""
+               reps: int = 3, cache_path: str | None = DEFAULT_CACHE, tile_edges=TILE_EDGES):
+    """Return ((best want_blocks, best tile edge), {"edge x want": contraction ms})."""
     from .pipeline import BatchPipeline
     key = batch_key(systems, precision, n_slices)
     cache = {}
@@ -57,17 +61,22 @@ def tune_batch(systems, precision: str = "fp64", n_slices: int = 0, candidates=C
                 cache = json.load(f)
         except (OSError, ValueError):
             cache = {}
-    if key in cache:
-        return int(cache[key]["want_blocks"]), {int(k): v for k, v in cache[key]["ms"].items()}
+    if key in cache and "tile_edge" in cache[key]:
+        c = cache[key]
+        return (int(c["want_blocks"]), int(c["tile_edge"])), dict(c["ms"])
+    edges = tile_edges if precision == "fp64" else (64,)
     times = {}
-    for c in candidates:
-        bp = BatchPipeline(systems, precision=precision, n_slices=n_slices, want_blocks=c)
-        times[int(c)] = _time_contraction(bp, reps)
-        del bp
+    for e in edges:
+        for c in candidates:
+            bp = BatchPipeline(systems, precision=precision, n_slices=n_slices, want_blocks=c,
+                               tile_edge=e)
+            times[f"{e}x{int(c)}"] = _time_contraction(bp, reps)
+            del bp
     best = min(times, key=times.get)
+    be, bw = (int(v) for v in best.split("x"))
     if cache_path:
-        cache[key] = {"want_blocks": best, "ms": times}
+        cache[key] = {"want_blocks": bw, "tile_edge": be, "ms": times}
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1)
-    return best, times
+    return (bw, be), times

@@ -233,6 +233,7 @@ extern "C" tl_status tl_batch_plan_create(const tl_system* systems, int count, t
     TL_REQUIRE(out->n_slices >= 2 && out->n_slices <= (prec == TL_SPLIT_FP16 ? 6 : 7),
                "n_slices = %d outside [2, %d]", out->n_slices, prec == TL_SPLIT_FP16 ? 6 : 7);
   out->want_blocks = want_blocks;
+  out->tile_edge = 64;
   out->desc_bytes = sizeof(BatchDesc);
   for (int i = 0; i < count; ++i) {
     InstanceSizes is;
@@ -268,6 +269,8 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
   TL_REQUIRE(buf->G && buf->AG && buf->SG && buf->P && buf->HS && buf->HSbar && buf->evals &&
                  buf->info && buf->ws,
              "null device buffer");
+  TL_REQUIRE(plan->tile_edge == 64 || plan->tile_edge == 32, "tile_edge = %d is not 64 or 32",
+             plan->tile_edge);
   const tl_precision prec = (tl_precision)plan->precision;
   std::vector<char> storage(sizeof(BatchDesc));
   BatchDesc* d = (BatchDesc*)storage.data();
@@ -292,7 +295,7 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
     double* H = buf->HS + ohs;
     double* S = H + g.block_elems;
     TL_TRY(plan_assembly(g, J.G, J.AG, J.SG, P, prec, plan->n_slices, H, S, ws + is.pot_ws,
-                         is.asm_ws, plan->want_blocks, &J.asmb, 64));
+                         is.asm_ws, plan->want_blocks, &J.asmb, plan->tile_edge));
     // one lattice axis: transform H and S (outer = 2) along L
     double* Hbar = buf->HSbar + 2 * ohs;
     const int Ls[3] = {g.L[0], 1, 1};

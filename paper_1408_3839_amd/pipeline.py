@@ -139,7 +139,7 @@ class BatchPipeline:
     run() enqueues the whole chain with one launch per stage."""
 
     def __init__(self, systems, precision: str = "fp64", n_slices: int = 0,
-                 want_blocks: int = 0, device: str = "cuda:0"):
+                 want_blocks: int = 0, device: str = "cuda:0", tile_edge: int = 64):
         import numpy as np
         tl.load()
         self.systems = list(systems)
@@ -147,6 +147,7 @@ class BatchPipeline:
         self.device = torch.device(device)
         self.plan = tl.tl_batch_plan_create(self.sarr, tl.PRECISIONS[precision], n_slices,
                                             want_blocks)
+        self.plan.tile_edge = int(tile_edge)
         p = self.plan
         f64 = dict(dtype=torch.float64, device=self.device)
         self.buf = {

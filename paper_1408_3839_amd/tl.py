@@ -72,6 +72,7 @@ class TlBatchPlan(ctypes.Structure):
         ("basis_elems", ctypes.c_int64), ("pot_elems", ctypes.c_int64),
         ("hs_elems", ctypes.c_int64), ("eval_elems", ctypes.c_int64), ("kblocks", ctypes.c_int64),
         ("ws_bytes", ctypes.c_size_t), ("desc_bytes", ctypes.c_size_t),
+        ("tile_edge", ctypes.c_int),
     ]
 
 

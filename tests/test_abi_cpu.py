@@ -186,3 +186,18 @@ def test_bloch_vectors_validation():
     _expect(tl.tl_bloch_vectors, tl.TL_EINVAL, 8, 4, 1, 1, 4, 8, -1, 8, 0)
     _expect(tl.tl_bloch_vectors, tl.TL_EINVAL, 0, 4, 1, 1, 4, 8, 3, 8, 0)
     tl.tl_bloch_vectors(0, 4, 1, 1, 4, 0, 0, 0, 0)  # no states: nothing to do, no launch
+
+
+def test_batch_plan_tile_edge():
+    """The plan carries the FP64 tile edge (64 by default); a descriptor is
+    only written for 64 or 32 (host check, before any device address is
+    used)."""
+    systems = [wl.tiny_periodic(L=(4, 1, 1)), wl.tiny_periodic(L=(5, 1, 1), m0=2)]
+    plan = tl.tl_batch_plan_create(systems)
+    assert plan.tile_edge == 64
+    plan.tile_edge = 48
+    fake = {n: 8 for n in ("G", "AG", "SG", "P", "HS", "HSbar", "evals", "info", "ws")}
+    host = np.zeros(plan.desc_bytes, dtype=np.uint8)
+    with pytest.raises(tl.TlError) as ei:
+        tl.tl_batch_write_descriptor(systems, plan, fake, host)
+    assert "tile_edge" in str(ei.value)

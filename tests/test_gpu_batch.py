@@ -139,22 +139,29 @@ def test_ragged_64_chain_batch():
 
 
 def test_autotune_picks_and_caches(tmp_path):
-    """The tiling autotuner times every candidate, keeps the fastest in its
-    cache, answers the next call from the cache, and the tuned batch still
-    matches the oracle."""
+    """The autotuner times every (tile edge, tiling target) pair, keeps the
+    fastest in its cache, answers the next call from the cache, and the tuned
+    batch still matches the oracle; both tile edges give the same H bit for
+    bit up to the summation order inside a tile (checked against the oracle)."""
     from paper_1408_3839_amd import autotune
     from paper_1408_3839_amd.pipeline import BatchPipeline
     systems = _ragged()
     cache = str(tmp_path / "tuning.json")
     cands = (128, 512, 2048)
     best, times = autotune.tune_batch(systems, candidates=cands, reps=2, cache_path=cache)
-    assert set(times) == set(cands) and best == min(times, key=times.get)
+    assert set(times) == {f"{e}x{c}" for e in (64, 32) for c in cands}
+    assert f"{best[1]}x{best[0]}" == min(times, key=times.get)
     assert all(t > 0 for t in times.values())
     best2, times2 = autotune.tune_batch(systems, candidates=cands, reps=2, cache_path=cache)
     assert best2 == best and times2 == times
-    bp = BatchPipeline(systems, want_blocks=best)
-    bp.run()
-    torch.cuda.synchronize()
-    s, v = systems[0], bp.views[0]
-    Hr, Sr, scale = oracle.core_hamiltonian_blocks(s)
-    assert np.all(np.abs(v["H"].cpu().numpy() - Hr) <= 1e-10 * scale + 1e-290)
+    for edge in (64, 32):
+        bp = BatchPipeline(systems, want_blocks=best[0], tile_edge=edge)
+        bp.run()
+        torch.cuda.synchronize()
+        for s, v in zip(systems[:2], bp.views[:2]):
+            Hr, Sr, scale = oracle.core_hamiltonian_blocks(s)
+            assert np.all(np.abs(v["H"].cpu().numpy() - Hr) <= 1e-10 * scale + 1e-290)
+    # the split modes have one tile shape: only the tiling target is timed
+    _, ts = autotune.tune_batch(systems, precision="split_fp16", n_slices=5, candidates=cands,
+                                reps=1, cache_path=None)
+    assert set(ts) == {f"64x{c}" for c in cands}
