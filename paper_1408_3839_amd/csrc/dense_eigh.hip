@@ -369,6 +369,10 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 constexpr int kPU = 8;   // prologue elements per thread held in registers (n <= 2048)
 constexpr int kPP = 2;   // partial sums per thread held in registers (nparts <= 512)
 
+// NP > 0: the trailing rows' column pairs (at most 2 kTT NP columns) are all
+// loaded into registers before the reflector is formed, so that the reads of
+// the step overlap its reductions; NP = 0 streams the columns one pair ahead.
+template <int NP>
 __global__ __launch_bounds__(kTT) void tridiag_step_kernel(TridArgs t, int j, int nparts) {
   extern __shared__ double vs[];  // N + 1 entries: x, then v_j
   __shared__ double red[kTT / 64];
@@ -410,15 +414,19 @@ __global__ __launch_bounds__(kTT) void tridiag_step_kernel(TridArgs t, int j, in
   }
   const int cb = (j + 1) & ~1;
   const bool rows = j < N - 1;
-  // first column pair of the trailing rows (consumed after the reflector)
+  // column pairs of the trailing rows (consumed after the reflector): all of
+  // them for NP > 0, else the first
   int c = cb + 2 * tid;
-  f64x2 a[kTR], pv2 = {0.0, 0.0}, py2 = {0.0, 0.0};
+  constexpr int NA = NP > 0 ? NP : 1;
+  f64x2 a[NA][kTR], pv2[NA], py2[NA];
 #pragma unroll
-  for (int q = 0; q < kTR; ++q)
-    a[q] = (rows && c < N && r0 + q < N) ? *(const f64x2*)(row[q] + c) : f64x2{0.0, 0.0};
-  if (rows && corr && c < N) {
-    pv2 = *(const f64x2*)(vp + c);
-    py2 = *(const f64x2*)(yp + c);
+  for (int u = 0; u < NA; ++u) {
+    const int cu = c + 2 * kTT * u;
+#pragma unroll
+    for (int q = 0; q < kTR; ++q)
+      a[u][q] = (rows && cu < N && r0 + q < N) ? *(const f64x2*)(row[q] + cu) : f64x2{0.0, 0.0};
+    pv2[u] = (rows && corr && cu < N) ? *(const f64x2*)(vp + cu) : f64x2{0.0, 0.0};
+    py2[u] = (rows && corr && cu < N) ? *(const f64x2*)(yp + cu) : f64x2{0.0, 0.0};
   }
   // ---- reflector of column j
   double cw = 0.0;
@@ -476,39 +484,52 @@ __global__ __launch_bounds__(kTT) void tridiag_step_kernel(TridArgs t, int j, in
     wr[q] = yr_[q] - cw * vr[q];
     acc[q] = 0.0;
   }
-  // N <= ld and ld is even, so the pair (c, c+1) with c < N is in the row
-  for (; c < N; c += 2 * kTT) {
-    const int cn = c + 2 * kTT;
-    f64x2 an[kTR], pvn = {0.0, 0.0}, pyn = {0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < kTR; ++q)
-      an[q] = (cn < N && r0 + q < N) ? *(const f64x2*)(row[q] + cn) : f64x2{0.0, 0.0};
-    if (corr && cn < N) {
-      pvn = *(const f64x2*)(vp + cn);
-      pyn = *(const f64x2*)(yp + cn);
-    }
-    const bool ok0 = c >= j + 1, ok1 = c + 1 < N;
+  // one column pair (cc, cc+1) of the trailing rows: step j-1's update, the
+  // write-back, and the products with v_j.  N <= ld and ld is even, so the
+  // pair with cc < N is in the row.
+  auto pair = [&](int cc, f64x2 (&ar)[kTR], f64x2 pvc, f64x2 pyc) {
+    const bool ok0 = cc >= j + 1, ok1 = cc + 1 < N;
     const double m0 = ok0 ? 1.0 : 0.0, m1 = ok1 ? 1.0 : 0.0;
-    const double v0 = vs[c], v1 = vs[c + 1];
-    const f64x2 pw = py2 - cw * pv2;
+    const double v0 = vs[cc], v1 = vs[cc + 1];
+    const f64x2 pw = pyc - cw * pvc;
 #pragma unroll
     for (int q = 0; q < kTR; ++q) {
       if (r0 + q >= N) continue;
       if (corr) {
-        a[q] -= vr[q] * pw + wr[q] * pv2;
+        ar[q] -= vr[q] * pw + wr[q] * pvc;
         if (ok0 && ok1)
-          *(f64x2*)(row[q] + c) = a[q];
+          *(f64x2*)(row[q] + cc) = ar[q];
         else if (ok1)
-          row[q][c + 1] = a[q].y;
+          row[q][cc + 1] = ar[q].y;
         else if (ok0)
-          row[q][c] = a[q].x;
+          row[q][cc] = ar[q].x;
       }
-      acc[q] += m0 * a[q].x * v0 + m1 * a[q].y * v1;
+      acc[q] += m0 * ar[q].x * v0 + m1 * ar[q].y * v1;
     }
+  };
+  if constexpr (NP > 0) {
 #pragma unroll
-    for (int q = 0; q < kTR; ++q) a[q] = an[q];
-    pv2 = pvn;
-    py2 = pyn;
+    for (int u = 0; u < NP; ++u) {
+      const int cu = c + 2 * kTT * u;
+      if (cu < N) pair(cu, a[u], pv2[u], py2[u]);
+    }
+  } else {
+    for (; c < N; c += 2 * kTT) {
+      const int cn = c + 2 * kTT;
+      f64x2 an[kTR], pvn = {0.0, 0.0}, pyn = {0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < kTR; ++q)
+        an[q] = (cn < N && r0 + q < N) ? *(const f64x2*)(row[q] + cn) : f64x2{0.0, 0.0};
+      if (corr && cn < N) {
+        pvn = *(const f64x2*)(vp + cn);
+        pyn = *(const f64x2*)(yp + cn);
+      }
+      pair(c, a[0], pv2[0], py2[0]);
+#pragma unroll
+      for (int q = 0; q < kTR; ++q) a[0][q] = an[q];
+      pv2[0] = pvn;
+      py2[0] = pyn;
+    }
   }
 #pragma unroll
   for (int q = 0; q < kTR; ++q) {
@@ -1362,8 +1383,18 @@ tl_status dense_gen_eigh_lowest(const double* H, const double* S, int N, int k, 
     const size_t lds = sizeof(double) * ((size_t)N + 1);
     for (int j = 0; j < N; ++j) {
       const int grid = std::max(1, (int)ceil_div(N - j - 1, kTR));
-      hipLaunchKernelGGL(tridiag_step_kernel, dim3((unsigned)grid), dim3(kTT), lds, stream, t, j,
-                         nparts);
+      // column pairs per thread for the trailing columns cb .. N-1
+      const int np = (int)ceil_div(N - ((j + 1) & ~1), 2 * kTT);
+      const dim3 gd((unsigned)grid), bd(kTT);
+      switch (np) {
+        case 0:
+        case 1: hipLaunchKernelGGL(tridiag_step_kernel<1>, gd, bd, lds, stream, t, j, nparts); break;
+        case 2: hipLaunchKernelGGL(tridiag_step_kernel<2>, gd, bd, lds, stream, t, j, nparts); break;
+        case 3: hipLaunchKernelGGL(tridiag_step_kernel<3>, gd, bd, lds, stream, t, j, nparts); break;
+        case 4: hipLaunchKernelGGL(tridiag_step_kernel<4>, gd, bd, lds, stream, t, j, nparts); break;
+        default:
+          hipLaunchKernelGGL(tridiag_step_kernel<0>, gd, bd, lds, stream, t, j, nparts);
+      }
       TL_CHECK_LAUNCH();
       nparts = grid;
     }
