@@ -99,3 +99,27 @@ def test_kspace_reduced_precision(mode):
     d = max(np.abs(Hk - Hf).max() / np.abs(Hf).max(), np.abs(Sk - Sf).max() / np.abs(Sf).max())
     print(f"\nc5 {prec} s={ns}: k-space vs block-FFT route {d:.2e}")
     assert d <= 1e-12
+
+
+def test_kspace_route_graph_replay():
+    """The k-space route captured in one HIP graph (basis and potential,
+    contraction, reduction, fused factor DFTs and combination, k-block
+    eigensolves) and replayed three times with eager work and
+    synchronisations between the replays: every replay equals the eager run
+    bit for bit."""
+    from paper_1408_3839_amd.pipeline import PeriodicPipeline
+    pl = PeriodicPipeline(wl.config(5), route="kspace")
+    pl.run()
+    torch.cuda.synchronize()
+    ref = (pl.HSbar.clone(), pl.evals.clone(), pl.info.clone())
+    pl.capture()
+    for rep in range(3):
+        pl.HSbar.fill_(float("nan"))
+        pl.evals.fill_(float("nan"))
+        torch.cuda.synchronize()
+        pl.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(pl.HSbar, ref[0]) and torch.equal(pl.evals, ref[1]), rep
+        assert torch.equal(pl.info, ref[2]), rep
+        pl.run()
+        torch.cuda.synchronize()

@@ -70,11 +70,12 @@ def test_noalloc_two_calls_second_smaller(prec):
         _bitwise(S0, S1)
 
 
-def test_noalloc_open_chain_then_periodic():
+@pytest.mark.parametrize("prec", [tl.TL_FP64, tl.TL_SPLIT_FP16])
+def test_noalloc_open_chain_then_periodic(prec):
     chain = wl.box_chain_system("box12", 12, 1.5, [1.0, 2.0], 0.1, [400, 64, 72], 5,
                                 (0.3, 4.0), 10, seed=21)
     for sys in (chain, wl.config(1)):
-        H0, S0, H1, S1 = _both(sys, tl.TL_FP64)
+        H0, S0, H1, S1 = _both(sys, prec)
         assert np.all(np.isfinite(H1))
         _bitwise(H0, H1)
         _bitwise(S0, S1)
