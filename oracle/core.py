@@ -336,6 +336,19 @@ def bcirc_full(blocks: np.ndarray) -> np.ndarray:
     return A
 
 
+def btoepl_full(blocks: np.ndarray) -> np.ndarray:
+    """The symmetric one-level block Toeplitz matrix of the Appendix, eq.
+    (block_SToepl): block (r, c) = A_(r-c) for r >= c and A_(c-r)^T for
+    r < c.  blocks: [L][m0][m0]."""
+    L, m0, _ = blocks.shape
+    A = np.zeros((L * m0, L * m0), dtype=blocks.dtype)
+    for r in range(L):
+        for c in range(L):
+            B = blocks[r - c] if r >= c else blocks[c - r].T
+            A[r * m0:(r + 1) * m0, c * m0:(c + 1) * m0] = B
+    return A
+
+
 def block_dft(blocks: np.ndarray) -> np.ndarray:
     """Abar_j = sum_k omega_1^(j1 k1) omega_2^(j2 k2) omega_3^(j3 k3) A_k with
     omega_l = exp(-2 pi i / L_l), by explicit O(|L|^2) sums (Proposition on

@@ -381,6 +381,29 @@ def test_full_matrix_scales():
     assert np.all(np.abs(Hb) <= Hba * (1 + 1e-12))
 
 
+def test_btoepl_full_structure_and_embedding():
+    """Eq. (block_SToepl) written out: symmetric when A_0 is; constant along
+    block diagonals; the leading L x L block part of the 2L-block circulant
+    with first block column [A_0..A_(L-1), 0, A_(L-1)^T..A_1^T] (the Remark on
+    block Toeplitz matrices, with the circulant assembled by its own
+    definition); L = 1 gives A_0."""
+    rng = np.random.default_rng(2)
+    L, m0 = 6, 3
+    A = rng.standard_normal((L, m0, m0))
+    A[0] = A[0] + A[0].T
+    T = oracle.btoepl_full(A)
+    np.testing.assert_array_equal(T, T.T)
+    for r in range(1, L):
+        np.testing.assert_array_equal(T[r * m0:(r + 1) * m0, (r - 1) * m0:r * m0], A[1])
+    C = np.zeros((2 * L, 1, 1, m0, m0))
+    for k in range(L):
+        C[k, 0, 0] = A[k]
+    for k in range(1, L):
+        C[2 * L - k, 0, 0] = A[k].T
+    np.testing.assert_array_equal(oracle.bcirc_full(C)[:L * m0, :L * m0], T)
+    np.testing.assert_array_equal(oracle.btoepl_full(A[:1]), A[0])
+
+
 def test_fourier_blocks_hermitian_and_conjugate_pairs():
     """Symmetric block-circulant => Hermitian Fourier blocks,
     Abar_{L-j} = conj(Abar_j), real blocks for a mirror-symmetric s basis."""
