@@ -327,6 +327,39 @@ tl_status tl_bloch_vectors(const double* evecs_dev, int L1, int L2, int L3, int 
                            const int* states_dev, int n_states, double* out_dev, void* stream);
 
 /*
+ * Symmetric block-Toeplitz matrices (Sec. 2, Definition of the block
+ * Toeplitz class; Appendix eq. (block_SToepl)), as the open chain's matrices
+ * are up to a boundary defect (Sec. 3.3): A = BToepl_s{A_0..A_{L-1}}, block
+ * (r, c) = A_{r-c} (r >= c), A_{c-r}^T (r < c).  Products with A go through
+ * the double-size block-circulant embedding (Remark on block Toeplitz
+ * matrices): C_k = A_k (k < L), C_L = 0, C_{2L-k} = A_k^T, diagonalised by the
+ * block DFT over 2L cells, O(m0^2 L log L + m0^2 nvec L) per product instead
+ * of (L m0)^2 nvec.
+ *   tl_btoepl_workspace_bytes  workspace for (L, m0, nvec): the 2L k-blocks
+ *       of C and the transforms of one block of nvec vectors.
+ *   tl_btoepl_setup   A_dev: [L][m0][m0] (A_0 symmetric); forms the k-blocks
+ *       of C in the workspace (once per matrix; the workspace then serves
+ *       every product with that matrix and nvec).
+ *   tl_btoepl_matvec  Y = A X, X_dev and Y_dev [L][m0][nvec] (cell, function,
+ *       vector), FP64.
+ *   tl_btoepl_power   the power method for the senior eigenvalue (largest in
+ *       magnitude), the Remark's use: iters times y = A x,
+ *       lambda[it] = (x . y) / (x . x), x = y / |y|.  x_dev: start vector in,
+ *       last iterate out; y_dev: scratch; both L*m0 doubles; lambda_dev:
+ *       iters doubles.  Workspace and setup as for nvec = 1.
+ * Limits: 1 <= L <= 2048 (2L on the block FFT; lengths 2L with a prime factor
+ * above 7 use Bluestein and need 4L - 1 <= 4096), 1 <= m0 <= TL_MAX_M0,
+ * 1 <= nvec <= 1024.  Errors: TL_EINVAL, TL_EUNSUPPORTED (no transform plan).
+ */
+tl_status tl_btoepl_workspace_bytes(int L, int m0, int nvec, size_t* bytes);
+tl_status tl_btoepl_setup(const double* A_dev, int L, int m0, int nvec, void* ws_dev,
+                          size_t ws_bytes, void* stream);
+tl_status tl_btoepl_matvec(const double* X_dev, double* Y_dev, int L, int m0, int nvec,
+                           void* ws_dev, size_t ws_bytes, void* stream);
+tl_status tl_btoepl_power(int L, int m0, int iters, double* x_dev, double* y_dev,
+                          double* lambda_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/*
  * tl_dense_gen_eigh_lowest - the k lowest eigenpairs of the full symmetric
  * pencil H u = lambda S u, S positive definite (the open-boundary chain's
  * core Hamiltonian and mass matrix, Sec. 5's full eigensolver; Sec. 2.1

@@ -87,10 +87,15 @@ bool factor_axis(int n, dev::FftAxis* ax) {
 
 bool plan_fft(const double* in, double* out, const int L[3], int m0, int64_t batch,
               dev::FftArgs* a, int min_groups) {
+  return plan_fft_cols(in, out, L, (int64_t)m0 * m0, batch, a, min_groups);
+}
+
+bool plan_fft_cols(const double* in, double* out, const int L[3], int64_t E, int64_t batch,
+                   dev::FftArgs* a, int min_groups) {
   std::memset(a, 0, sizeof(*a));
   a->in = in;
   a->out = out;
-  a->E = (int64_t)m0 * m0;
+  a->E = E;
   a->cols = batch * a->E;
   a->P = 1;
   for (int d = 0; d < 3; ++d) {

@@ -74,9 +74,13 @@ tl_status build_basis(const Geometry& g, const tl_system* s, double* G, double* 
 constexpr int kFftSingleGroups = 256;
 bool plan_fft(const double* in, double* out, const int L[3], int m0, int64_t batch,
               dev::FftArgs* a, int min_groups = 1);
+// the same for E real entries per lattice point (any column count, not m0^2)
+bool plan_fft_cols(const double* in, double* out, const int L[3], int64_t E, int64_t batch,
+                   dev::FftArgs* a, int min_groups = 1);
 // workspace of the Bluestein tables (0 for 7-smooth lattices) and their place in it
 size_t fft_blue_table_bytes(const dev::FftArgs& a);
 void set_fft_blue_tables(dev::FftArgs* a, void* ws);
+tl_status launch_fft(const dev::FftArgs& a, hipStream_t stream);
 
 size_t box_workspace_bytes(const Geometry& g);
 tl_status assemble_box(const Geometry& g, const tl_system* s, const double* G, const double* AG,

@@ -127,6 +127,14 @@ SIGNATURES = {
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "tl_bloch_vectors": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 4
                          + [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "tl_btoepl_workspace_bytes": (ctypes.c_int, [ctypes.c_int] * 3
+                                  + [ctypes.POINTER(ctypes.c_size_t)]),
+    "tl_btoepl_setup": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 3
+                        + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "tl_btoepl_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 3
+                         + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "tl_btoepl_power": (ctypes.c_int, [ctypes.c_int] * 3 + [ctypes.c_void_p] * 4
+                        + [ctypes.c_size_t, ctypes.c_void_p]),
     "tl_dense_gen_eigh_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int,
                                                          ctypes.POINTER(ctypes.c_size_t)]),
     "tl_set_dense_eigh_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -360,6 +368,28 @@ def tl_batched_heigh(H, S, count, m0, evals, evecs, info, stream=None):
 def tl_bloch_vectors(evecs, L1, L2, L3, m0, states, n_states, out, stream=None):
     _check(load().tl_bloch_vectors(_ptr(evecs), int(L1), int(L2), int(L3), int(m0), _ptr(states),
                                    int(n_states), _ptr(out), _stream(stream)), "tl_bloch_vectors")
+
+
+def tl_btoepl_workspace_bytes(L, m0, nvec) -> int:
+    v = ctypes.c_size_t()
+    _check(load().tl_btoepl_workspace_bytes(int(L), int(m0), int(nvec), ctypes.byref(v)),
+           "tl_btoepl_workspace_bytes")
+    return v.value
+
+
+def tl_btoepl_setup(A, L, m0, nvec, ws, ws_bytes, stream=None):
+    _check(load().tl_btoepl_setup(_ptr(A), int(L), int(m0), int(nvec), _ptr(ws), int(ws_bytes),
+                                  _stream(stream)), "tl_btoepl_setup")
+
+
+def tl_btoepl_matvec(X, Y, L, m0, nvec, ws, ws_bytes, stream=None):
+    _check(load().tl_btoepl_matvec(_ptr(X), _ptr(Y), int(L), int(m0), int(nvec), _ptr(ws),
+                                   int(ws_bytes), _stream(stream)), "tl_btoepl_matvec")
+
+
+def tl_btoepl_power(L, m0, iters, x, y, lam, ws, ws_bytes, stream=None):
+    _check(load().tl_btoepl_power(int(L), int(m0), int(iters), _ptr(x), _ptr(y), _ptr(lam),
+                                  _ptr(ws), int(ws_bytes), _stream(stream)), "tl_btoepl_power")
 
 
 def tl_dense_gen_eigh_workspace_bytes(N, k) -> int:

@@ -201,3 +201,19 @@ def test_batch_plan_tile_edge():
     with pytest.raises(tl.TlError) as ei:
         tl.tl_batch_write_descriptor(systems, plan, fake, host)
     assert "tile_edge" in str(ei.value)
+
+
+def test_btoepl_sizes_and_validation():
+    b = tl.tl_btoepl_workspace_bytes(256, 8, 64)
+    # k-blocks 2L m0^2 complex; padded X, its transform, [R; I] and their transforms
+    assert b >= 8 * (2 * 512 * 64 + 512 * 512 + 2 * 512 * 512 + 2 * 512 * 512 + 4 * 512 * 512)
+    with pytest.raises(tl.TlError):
+        tl.tl_btoepl_workspace_bytes(0, 8, 1)
+    with pytest.raises(tl.TlError):
+        tl.tl_btoepl_workspace_bytes(2049, 8, 1)
+    with pytest.raises(tl.TlError):
+        tl.tl_btoepl_workspace_bytes(16, 33, 1)
+    with pytest.raises(tl.TlError):
+        tl.tl_btoepl_workspace_bytes(16, 4, 0)
+    _expect(tl.tl_btoepl_matvec, tl.TL_EINVAL, 8, 8, 16, 4, 2, 8, 8, 0)   # workspace too small
+    _expect(tl.tl_btoepl_power, tl.TL_EINVAL, 16, 4, 0, 8, 8, 8, 8, 1 << 30, 0)
