@@ -360,6 +360,42 @@ tl_status tl_btoepl_power(int L, int m0, int iters, double* x_dev, double* y_dev
                           double* lambda_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
 /*
+ * tl_btoepl_lowest - the nev lowest eigenpairs of the symmetric-definite
+ * pencil T_H u = lambda T_S u of two symmetric block-Toeplitz matrices given
+ * by their first block columns (the iterative route for boxes too large for
+ * the full eigensolver, Sec. 3.3's closing remark, on the embedded product of
+ * the Remark on block Toeplitz matrices).  LOBPCG with a block of nb vectors,
+ * preconditioned by the inverse of the shifted Strang block circulant of the
+ * pencil (its k-blocks Hhat_j - sigma Shat_j, sigma = the circulant pencil's
+ * lowest eigenvalue minus `shift`, through the block DFT over L cells).
+ *   H_dev, S_dev: [L][m0][m0] doubles, device (A_0 symmetric); T_S must be
+ *     positive definite, and so must every k-block Shat_j of its circulant.
+ *   nev <= nb <= 21, 3 nb <= L m0.  A few guard vectors (nb > nev) speed up
+ *     the convergence of the highest wanted pairs.
+ *   max_iter: iteration limit; tol: relative residual target
+ *     |T_H x - lambda T_S x| / ((|T_H| + |lambda| |T_S|) |x|), the norms
+ *     bounded by the sums over k of the largest row and column sums of |A_k|.
+ *   shift: sigma below the circulant minimum (<= 0: 0.02 max(1, |lambda_min|)).
+ *   x0_dev (nullable): start block [L m0][nb]; NULL draws it from a fixed seed.
+ *   evals_dev: nev doubles, ascending; evecs_dev (nullable): [L][m0][nev],
+ *     T_S-normalised; resid_dev (nullable): the nev relative residuals,
+ *     recomputed from fresh products at the end.
+ *   iters, nconv (host): iterations run, and how many of the nev pairs meet
+ *     tol (nconv < nev: not converged within max_iter; the outputs are the
+ *     last iterate).
+ * The call synchronises `stream` (the iteration is steered by residual norms
+ * read back every step).  Limits: 1 <= L <= 2048 as for the product, m0 <=
+ * TL_MAX_M0.  Errors: TL_EINVAL (arguments; a circulant k-block that is not
+ * definite; a Rayleigh-Ritz basis that lost rank), TL_EWORKSPACE,
+ * TL_EUNSUPPORTED (no transform plan for L).
+ */
+tl_status tl_btoepl_lowest_workspace_bytes(int L, int m0, int nb, size_t* bytes);
+tl_status tl_btoepl_lowest(const double* H_dev, const double* S_dev, int L, int m0, int nev,
+                           int nb, int max_iter, double tol, double shift, const double* x0_dev,
+                           double* evals_dev, double* evecs_dev, double* resid_dev, int* iters,
+                           int* nconv, void* ws_dev, size_t ws_bytes, void* stream);
+
+/*
  * tl_dense_gen_eigh_lowest - the k lowest eigenpairs of the full symmetric
  * pencil H u = lambda S u, S positive definite (the open-boundary chain's
  * core Hamiltonian and mass matrix, Sec. 5's full eigensolver; Sec. 2.1

@@ -12,8 +12,10 @@
 // data: with Yhat = R + i I, Y_c = (Re DFT(R)_c + Im DFT(I)_c) / 2L.  The
 // power method for the largest eigenvalue in magnitude (the senior one) runs
 // on this product.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "common.h"
 #include "host_plans.h"
@@ -193,6 +195,970 @@ tl_status matvec(const ToeplitzLayout& t, char* ws, const double* X, double* Y,
   return TL_OK;
 }
 
+// ===========================================================================
+// Lowest eigenpairs of the symmetric-definite block-Toeplitz pencil
+// (T_H, T_S): the iterative route the paper points to for open boxes whose
+// full matrices are too large to diagonalise (Sec. 3.3, closing remark), on
+// the fast product above.  The solver is LOBPCG (Knyazev, SIAM J. Sci.
+// Comput. 23 (2001)): a block of nb vectors X, the preconditioned residuals
+// W and the previous search directions P span the Rayleigh-Ritz basis of
+// each step.  Choices of this implementation:
+//   * preconditioner: the Strang block circulant of each matrix (first block
+//     column A_0, ..., A_{L/2}, A_{L/2}^T..., A_1^T: the periodic matrix with
+//     the same blocks, Lemma 2.2), shifted below the circulant pencil's
+//     lowest eigenvalue and inverted through the block DFT over L cells:
+//     W = F^-1 diag_j (Hhat_j - sigma Shat_j)^-1 F R;
+//   * W is made T_S-orthogonal to X before its products are taken; the basis
+//     [X, W, P] is orthonormalised in the T_S metric by SVQB (Stathopoulos
+//     and Wu, SIAM J. Sci. Comput. 23 (2002)): columns scaled to unit norm,
+//     the Gram matrix diagonalised, directions with eigenvalue below 1e-12 of
+//     the largest dropped;
+//   * the small eigenproblems (order <= 3 nb <= 64) are solved by cyclic
+//     Jacobi in one workgroup's LDS;
+//   * T_H X and T_S X are recomputed from X every 10 steps (the recurrences
+//     that update them drift);
+//   * soft locking: a wanted pair whose residual meets the tolerance keeps
+//     its place in X but contributes no preconditioned residual.
+
+constexpr int kLobMaxBasis = 64;  // 3 nb, padded
+constexpr int kLobMaxNb = 21;
+constexpr int kLobLd = kLobMaxBasis + 1;
+constexpr double kLobDrop = 1e-12;
+constexpr int kLobRefresh = 10;
+
+// Strang circulant blocks of A (first block column), H and S stacked.
+struct StrangArgs {
+  const double* A[2];  // [L][m0][m0]
+  double* out;         // [2][L][m0][m0]
+  int L, m0;
+};
+
+__global__ __launch_bounds__(256) void strang_kernel(StrangArgs a) {
+  const int64_t m2 = (int64_t)a.m0 * a.m0;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * a.L * m2) return;
+  const int w = (int)(idx / (a.L * m2));
+  const int64_t rest = idx - w * a.L * m2;
+  const int k = (int)(rest / m2);
+  const int e = (int)(rest - k * m2), mu = e / a.m0, nu = e - mu * a.m0;
+  const double* A = a.A[w];
+  double v;
+  if (2 * k < a.L)
+    v = A[(int64_t)k * m2 + e];
+  else if (2 * k == a.L)
+    v = 0.5 * (A[(int64_t)k * m2 + e] + A[(int64_t)k * m2 + (int64_t)nu * a.m0 + mu]);
+  else
+    v = A[(int64_t)(a.L - k) * m2 + (int64_t)nu * a.m0 + mu];  // A_{L-k}^T
+  a.out[idx] = v;
+}
+
+// scal[0] = lowest eigenvalue over the k-blocks, scal[3] = 1 if a block
+// failed (not definite or not converged).
+__global__ __launch_bounds__(256) void lmin_kernel(const double* evals, const int* info, int L,
+                                                   int m0, double* scal) {
+  __shared__ double red[4];
+  __shared__ int bad[4];
+  double v = INFINITY;
+  int b = 0;
+  for (int j = threadIdx.x; j < L; j += blockDim.x) {
+    if (info[j] != 0) b = 1;
+    for (int i = 0; i < m0; ++i) {
+      const double e = evals[(int64_t)j * m0 + i];
+      if (e != e) b = 1;
+      else v = fmin(v, e);
+    }
+  }
+  v = wave_min_dpp(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int any = __any(b) ? 1 : 0;
+  if (lane == 0) {
+    red[wave] = v;
+    bad[wave] = any;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    scal[0] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+    scal[3] = (bad[0] | bad[1] | bad[2] | bad[3]) ? 1.0 : 0.0;
+  }
+}
+
+// scal[1], scal[2]: sum over k of (largest row sum + largest column sum of
+// |A_k|) for H and S, a bound on the infinity norm of each Toeplitz matrix.
+__global__ __launch_bounds__(256) void tnorm_kernel(const double* H, const double* S, int L,
+                                                    int m0, double* scal) {
+  __shared__ double red[2][4];
+  double acc[2] = {0.0, 0.0};
+  const int64_t m2 = (int64_t)m0 * m0;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    for (int w = 0; w < 2; ++w) {
+      const double* A = (w ? S : H) + k * m2;
+      double rmax = 0.0, cmax = 0.0;
+      for (int i = 0; i < m0; ++i) {
+        double r = 0.0, c = 0.0;
+        for (int j = 0; j < m0; ++j) {
+          r += fabs(A[i * m0 + j]);
+          c += fabs(A[j * m0 + i]);
+        }
+        rmax = fmax(rmax, r);
+        cmax = fmax(cmax, c);
+      }
+      acc[w] += rmax + cmax;
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int w = 0; w < 2; ++w) {
+    const double t = wave_sum_dpp(acc[w]);
+    if (lane == 0) red[w][wave] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int w = threadIdx.x;
+    scal[1 + w] = red[w][0] + red[w][1] + red[w][2] + red[w][3];
+  }
+}
+
+// Minv_j = (Hhat_j - sigma Shat_j)^-1 by complex Cholesky, one thread per j
+// (Lf: the factor, workspace).  info[j] = 1 + the failing pivot, else 0.
+__global__ __launch_bounds__(64) void minv_kernel(const double* hat, int L, int m0, double sigma,
+                                                  double* Lf, double* Minv, int* info) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= L) return;
+  const int64_t m2 = (int64_t)m0 * m0;
+  const double* Hh = hat + 2 * j * m2;
+  const double* Sh = hat + 2 * ((int64_t)L + j) * m2;
+  double* F = Lf + 2 * j * m2;
+  double* X = Minv + 2 * j * m2;
+  for (int64_t e = 0; e < m2; ++e) {
+    F[2 * e] = Hh[2 * e] - sigma * Sh[2 * e];
+    F[2 * e + 1] = Hh[2 * e + 1] - sigma * Sh[2 * e + 1];
+  }
+  // lower factor in place: F = L L^H
+  for (int c = 0; c < m0; ++c) {
+    double d = F[2 * (c * m0 + c)];
+    for (int k = 0; k < c; ++k) {
+      const double re = F[2 * (c * m0 + k)], im = F[2 * (c * m0 + k) + 1];
+      d -= re * re + im * im;
+    }
+    if (!(d > 0.0)) {
+      info[j] = 1 + c;
+      return;
+    }
+    d = sqrt(d);
+    F[2 * (c * m0 + c)] = d;
+    F[2 * (c * m0 + c) + 1] = 0.0;
+    for (int r = c + 1; r < m0; ++r) {
+      double re = F[2 * (r * m0 + c)], im = F[2 * (r * m0 + c) + 1];
+      for (int k = 0; k < c; ++k) {  // -= L[r][k] conj(L[c][k])
+        const double ar = F[2 * (r * m0 + k)], ai = F[2 * (r * m0 + k) + 1];
+        const double br = F[2 * (c * m0 + k)], bi = F[2 * (c * m0 + k) + 1];
+        re -= ar * br + ai * bi;
+        im -= ai * br - ar * bi;
+      }
+      F[2 * (r * m0 + c)] = re / d;
+      F[2 * (r * m0 + c) + 1] = im / d;
+    }
+  }
+  // column e of the inverse: L y = e_e, then L^H x = y (x stored in place)
+  for (int e = 0; e < m0; ++e) {
+    for (int r = 0; r < m0; ++r) {
+      double re = r == e ? 1.0 : 0.0, im = 0.0;
+      for (int k = 0; k < r; ++k) {
+        const double ar = F[2 * (r * m0 + k)], ai = F[2 * (r * m0 + k) + 1];
+        const double yr = X[2 * (k * m0 + e)], yi = X[2 * (k * m0 + e) + 1];
+        re -= ar * yr - ai * yi;
+        im -= ar * yi + ai * yr;
+      }
+      const double d = F[2 * (r * m0 + r)];
+      X[2 * (r * m0 + e)] = re / d;
+      X[2 * (r * m0 + e) + 1] = im / d;
+    }
+    for (int r = m0 - 1; r >= 0; --r) {
+      double re = X[2 * (r * m0 + e)], im = X[2 * (r * m0 + e) + 1];
+      for (int k = r + 1; k < m0; ++k) {  // -= conj(L[k][r]) x_k
+        const double ar = F[2 * (k * m0 + r)], ai = -F[2 * (k * m0 + r) + 1];
+        const double xr = X[2 * (k * m0 + e)], xi = X[2 * (k * m0 + e) + 1];
+        re -= ar * xr - ai * xi;
+        im -= ar * xi + ai * xr;
+      }
+      const double d = F[2 * (r * m0 + r)];
+      X[2 * (r * m0 + e)] = re / d;
+      X[2 * (r * m0 + e) + 1] = im / d;
+    }
+  }
+  info[j] = 0;
+}
+
+// Start block: entries uniform in (-1, 1) from splitmix64 of (seed, index).
+__global__ __launch_bounds__(256) void lob_rand_kernel(double* X, int64_t n, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  X[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// Partial Gram matrices over a chunk of rows: part[chunk][s][a][b] =
+// sum_rows V[row][a] U_s[row][b], with V = [V_0 | V_1 | V_2] (nb columns each)
+// and U_s likewise, a, b < nblk nb <= 64.
+struct GramArgs {
+  const double* V[3];
+  const double* U[2][3];
+  int nblk, nsets, nb;
+  int64_t N;
+  int chunk_rows;
+  double* part;
+};
+
+__global__ __launch_bounds__(256) void lob_gram_kernel(GramArgs g) {
+  __shared__ double Vs[32][kLobLd];
+  __shared__ double Us[2][32][kLobLd];
+  const int tid = threadIdx.x, a0 = (tid >> 4) * 4, b0 = (tid & 15) * 4;
+  const int n = g.nblk * g.nb;
+  const int64_t r0 = (int64_t)blockIdx.x * g.chunk_rows;
+  const int64_t r1 = min(g.N, r0 + g.chunk_rows);
+  double acc[2][4][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[s][i][j] = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += 32) {
+    for (int e = tid; e < 32 * kLobMaxBasis; e += 256) {
+      const int rr = e >> 6, c = e & 63;
+      const int64_t row = rb + rr;
+      const bool ok = row < r1 && c < n;
+      const int blk = ok ? c / g.nb : 0, cc = c - blk * g.nb;
+      const int64_t off = row * g.nb + cc;
+      Vs[rr][c] = ok ? g.V[blk][off] : 0.0;
+      Us[0][rr][c] = ok ? g.U[0][blk][off] : 0.0;
+      Us[1][rr][c] = ok && g.nsets > 1 ? g.U[1][blk][off] : 0.0;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < 32; ++rr) {
+      double va[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) va[i] = Vs[rr][a0 + i];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double ub = Us[s][rr][b0 + j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[s][i][j] = fma(va[i], ub, acc[s][i][j]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (s >= g.nsets) break;
+    double* P = g.part + ((int64_t)blockIdx.x * 2 + s) * kLobMaxBasis * kLobMaxBasis;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) P[(a0 + i) * kLobMaxBasis + b0 + j] = acc[s][i][j];
+  }
+}
+
+// gram[s][a][b] = sum over chunks, in chunk order.
+__global__ __launch_bounds__(256) void lob_gram_reduce_kernel(const double* part, int chunks,
+                                                              int nsets, double* gram) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = kLobMaxBasis * kLobMaxBasis;
+  if (e >= nsets * per) return;
+  const int s = e / per, r = e - s * per;
+  double v = 0.0;
+  for (int c = 0; c < chunks; ++c) v += part[((int64_t)c * 2 + s) * per + r];
+  gram[e] = v;
+}
+
+// Cyclic Jacobi on the symmetric n x n matrix A (LDS, row stride kLobLd),
+// eigenvectors accumulated into V (columns); parallel round-robin ordering,
+// n / 2 disjoint rotations per step.  On return A's diagonal holds the
+// eigenvalues.
+__device__ void jacobi_lds(double (*A)[kLobLd], double (*V)[kLobLd], int n, double* rot,
+                           double* red, int* rotated) {
+  const int tid = threadIdx.x;
+  const int ne = n + (n & 1);
+  const int npair = ne / 2;
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e - i * n;
+    V[i][j] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    // off-diagonal and total squared norms
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e - i * n;
+      const double v = A[i][j] * A[i][j];
+      tot += v;
+      if (i != j) off += v;
+    }
+    off = wave_sum_dpp(off);
+    tot = wave_sum_dpp(tot);
+    const int lane = tid & 63, wave = tid >> 6;
+    if (lane == 0) {
+      red[wave] = off;
+      red[4 + wave] = tot;
+    }
+    __syncthreads();
+    const double offs = red[0] + red[1] + red[2] + red[3];
+    const double tots = red[4] + red[5] + red[6] + red[7];
+    const bool any_rot = sweep == 0 || *rotated != 0;
+    __syncthreads();
+    // stop once a sweep rotated nothing (every |a_pq| below 1e-18 of
+    // sqrt|a_pp a_qq|), or the off-diagonal part is below 1e-18 of the norm
+    if (!any_rot || !(offs > 1e-36 * tots) || ne < 2) break;
+    if (tid == 0) *rotated = 0;
+    __syncthreads();
+    for (int step = 0; step < ne - 1; ++step) {
+      if (tid < npair) {
+        const int i = tid;
+        const int p = i == 0 ? 0 : ((i + step - 1) % (ne - 1)) + 1;
+        const int q = ((ne - 1 - i + step - 1) % (ne - 1)) + 1;
+        double c = 1.0, sn = 0.0;
+        if (p < n && q < n) {
+          const double apq = A[p][q];
+          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(A[p][p] * A[q][q]))) {
+            const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+            *rotated = 1;
+          }
+        }
+        rot[4 * i] = (double)p;
+        rot[4 * i + 1] = (double)q;
+        rot[4 * i + 2] = c;
+        rot[4 * i + 3] = sn;
+      }
+      __syncthreads();
+      // rows p, q of J^T A
+      for (int e = tid; e < npair * n; e += blockDim.x) {
+        const int i = e / n, k = e - i * n;
+        const int p = (int)rot[4 * i], q = (int)rot[4 * i + 1];
+        const double c = rot[4 * i + 2], sn = rot[4 * i + 3];
+        if (p >= n || q >= n || sn == 0.0) continue;
+        const double ap = A[p][k], aq = A[q][k];
+        A[p][k] = c * ap - sn * aq;
+        A[q][k] = sn * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q of (J^T A) J and of V J
+      for (int e = tid; e < npair * n; e += blockDim.x) {
+        const int i = e / n, k = e - i * n;
+        const int p = (int)rot[4 * i], q = (int)rot[4 * i + 1];
+        const double c = rot[4 * i + 2], sn = rot[4 * i + 3];
+        if (p >= n || q >= n || sn == 0.0) continue;
+        const double ap = A[k][p], aq = A[k][q];
+        A[k][p] = c * ap - sn * aq;
+        A[k][q] = sn * ap + c * aq;
+        const double vp = V[k][p], vq = V[k][q];
+        V[k][p] = c * vp - sn * vq;
+        V[k][q] = sn * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Rayleigh-Ritz on the basis of n columns: gram[0] = V^T T_H V, gram[1] =
+// V^T T_S V.  SVQB of gram[1], then the lowest nb eigenpairs of the projected
+// T_H.  Out: Y (n x nb, row stride nb) with X_new = V Y, lam (nb, ascending),
+// info[0] = kept rank r (r < nb: failure).
+__global__ __launch_bounds__(256) void lob_small_kernel(const double* gram, int n, int nb,
+                                                        double* Y, double* lam, int* info) {
+  extern __shared__ double lds[];
+  double(*GA)[kLobLd] = (double(*)[kLobLd])lds;
+  double(*GB)[kLobLd] = GA + kLobMaxBasis;
+  double(*Q)[kLobLd] = GB + kLobMaxBasis;
+  double(*T)[kLobLd] = Q + kLobMaxBasis;
+  __shared__ double D[kLobMaxBasis], th[kLobMaxBasis], rot[4 * kLobMaxBasis / 2], red[8];
+  __shared__ int keep_idx[kLobMaxBasis], perm[kLobMaxBasis];
+  __shared__ int r_sh, rotated;
+  const int tid = threadIdx.x;
+  const double* gA = gram;
+  const double* gB = gram + kLobMaxBasis * kLobMaxBasis;
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e - i * n;
+    GA[i][j] = 0.5 * (gA[i * kLobMaxBasis + j] + gA[j * kLobMaxBasis + i]);
+    GB[i][j] = 0.5 * (gB[i * kLobMaxBasis + j] + gB[j * kLobMaxBasis + i]);
+  }
+  __syncthreads();
+  if (tid < n) D[tid] = GB[tid][tid] > 0.0 ? 1.0 / sqrt(GB[tid][tid]) : 0.0;
+  __syncthreads();
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e - i * n;
+    T[i][j] = D[i] * GB[i][j] * D[j];
+  }
+  __syncthreads();
+  jacobi_lds(T, Q, n, rot, red, &rotated);
+  if (tid < n) th[tid] = T[tid][tid];
+  __syncthreads();
+  double tmax = 0.0;
+  for (int i = 0; i < n; ++i) tmax = fmax(tmax, th[i]);
+  if (tid < n) {
+    int pos = 0;
+    const bool kp = th[tid] > kLobDrop * tmax;
+    for (int i = 0; i < tid; ++i) pos += th[i] > kLobDrop * tmax;
+    keep_idx[tid] = kp ? pos : -1;
+  }
+  if (tid == 0) {
+    int r = 0;
+    for (int i = 0; i < n; ++i) r += th[i] > kLobDrop * tmax;
+    r_sh = r;
+  }
+  __syncthreads();
+  const int r = r_sh;
+  // M = D Q_keep theta^-1/2 (n x r) into T
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    const int i = e / n, k = e - i * n;
+    const int c = keep_idx[k];
+    if (c >= 0) T[i][c] = D[i] * Q[i][k] / sqrt(th[k]);
+  }
+  __syncthreads();
+  // Q = GA M (n x r)
+  for (int e = tid; e < n * r; e += blockDim.x) {
+    const int i = e / r, c = e - i * r;
+    double v = 0.0;
+    for (int k = 0; k < n; ++k) v = fma(GA[i][k], T[k][c], v);
+    Q[i][c] = v;
+  }
+  __syncthreads();
+  // GB = M^T GA M (r x r), symmetrised
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    const int a = e / r, b = e - a * r;
+    double v = 0.0, w = 0.0;
+    for (int k = 0; k < n; ++k) {
+      v = fma(T[k][a], Q[k][b], v);
+      w = fma(T[k][b], Q[k][a], w);
+    }
+    GB[a][b] = 0.5 * (v + w);
+  }
+  __syncthreads();
+  jacobi_lds(GB, GA, r, rot, red, &rotated);  // eigenvectors into GA
+  if (tid < r) {
+    const double v = GB[tid][tid];
+    int rank = 0;
+    for (int i = 0; i < r; ++i) {
+      const double u = GB[i][i];
+      rank += (u < v) || (u == v && i < tid);
+    }
+    perm[rank] = tid;
+  }
+  __syncthreads();
+  if (tid < nb && tid < r) lam[tid] = GB[perm[tid]][perm[tid]];
+  // Y = M C[:, perm[:nb]]
+  for (int e = tid; e < n * nb; e += blockDim.x) {
+    const int i = e / nb, j = e - i * nb;
+    double v = 0.0;
+    if (j < r) {
+      const int c = perm[j];
+      for (int k = 0; k < r; ++k) v = fma(T[i][k], GA[k][c], v);
+    }
+    Y[i * nb + j] = v;
+  }
+  if (tid == 0) info[0] = r;
+}
+
+// out_f = beta out_f + alpha sum_b in_f[b] Y_b (+ add_f), f = blockIdx.y:
+// N x nb tall-skinny blocks times nb x nb pieces of Y (row stride ldy).
+struct TsArgs {
+  const double* in[3][3];
+  const double* Y[3];
+  const double* add[3];
+  double* out[3];
+  int nin, nb, ldy;
+  int64_t N;
+  double alpha, beta;
+};
+
+__global__ __launch_bounds__(256) void lob_ts_kernel(TsArgs a) {
+  const int f = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.N * a.nb) return;
+  const int64_t row = e / a.nb;
+  const int j = (int)(e - row * a.nb);
+  double v = 0.0;
+  for (int b = 0; b < a.nin; ++b) {
+    const double* x = a.in[f][b] + row * a.nb;
+    const double* y = a.Y[b] + j;
+    for (int i = 0; i < a.nb; ++i) v = fma(x[i], y[(int64_t)i * a.ldy], v);
+  }
+  v *= a.alpha;
+  if (a.add[f]) v += a.add[f][e];
+  double* o = a.out[f];
+  o[e] = a.beta != 0.0 ? fma(a.beta, o[e], v) : v;
+}
+
+// R = AX - BX diag(lam)
+__global__ __launch_bounds__(256) void lob_resid_kernel(const double* AX, const double* BX,
+                                                        const double* lam, double* R, int64_t N,
+                                                        int nb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * nb) return;
+  const int j = (int)(e % nb);
+  R[e] = fma(-lam[j], BX[e], AX[e]);
+}
+
+// norms[j] = |R_j|^2, norms[nb + j] = |X_j|^2, one workgroup per column.
+__global__ __launch_bounds__(256) void lob_colnorm_kernel(const double* R, const double* X,
+                                                          int64_t N, int nb, double* norms) {
+  __shared__ double red[2][4];
+  const int j = blockIdx.x;
+  double r = 0.0, x = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    const double a = R[i * nb + j], b = X[i * nb + j];
+    r = fma(a, a, r);
+    x = fma(b, b, x);
+  }
+  r = wave_sum_dpp(r);
+  x = wave_sum_dpp(x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = r;
+    red[1][wave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    norms[j] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    norms[nb + j] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// W[row][j] *= mask[j]: the residuals of locked columns are not expanded
+__global__ __launch_bounds__(256) void lob_mask_kernel(double* W, const double* mask, int64_t N,
+                                                       int nb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * nb) return;
+  W[e] *= mask[e % nb];
+}
+
+// dst[row][j] = src[row][j] for j < nev (row strides nev and nb)
+__global__ __launch_bounds__(256) void lob_cols_kernel(const double* src, double* dst, int64_t N,
+                                                       int nb, int nev) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * nev) return;
+  const int64_t row = e / nev;
+  dst[e] = src[row * nb + (e - row * nev)];
+}
+
+enum LobVec {
+  kX, kAX, kBX, kW, kAW, kBW, kP, kAP, kBP, kX2, kAX2, kBX2, kP2, kAP2, kBP2, kBest, kNVec
+};
+
+struct LobLayout {
+  int L, m0, nb;
+  int64_t N, Ev;
+  ToeplitzLayout tH, tS;
+  size_t off_tH, off_tS;
+  FftArgs fblk, fr, fz;
+  size_t off_strang, off_hat, off_evals, off_info, off_lf, off_minv, off_rhat, off_z, off_f;
+  size_t off_tab[3];
+  size_t off_vec[kNVec];
+  size_t off_part, off_gram, off_y, off_lam, off_sinfo, off_norms, off_scal, off_mask;
+  size_t off_lambest;
+  int chunks, chunk_rows;
+  size_t bytes;
+};
+
+tl_status lob_layout(int L, int m0, int nb, LobLayout* t, char* ws) {
+  TL_REQUIRE(nb >= 1 && nb <= kLobMaxNb, "nb = %d outside [1, %d]", nb, kLobMaxNb);
+  TL_REQUIRE(L >= 1 && L <= kFftPoints / 2, "L = %d outside [1, %d]", L, kFftPoints / 2);
+  TL_REQUIRE(m0 >= 1 && m0 <= TL_MAX_M0, "m0 = %d outside [1, %d]", m0, TL_MAX_M0);
+  t->L = L;
+  t->m0 = m0;
+  t->nb = nb;
+  t->N = (int64_t)L * m0;
+  t->Ev = (int64_t)m0 * nb;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t r = o;
+    o += align_up(b, 256);
+    return r;
+  };
+  TL_TRY(layout(L, m0, nb, &t->tH, nullptr));
+  t->off_tH = take(t->tH.bytes);
+  t->off_tS = take(t->tH.bytes);
+  if (ws) {
+    TL_TRY(layout(L, m0, nb, &t->tH, ws + t->off_tH));
+    TL_TRY(layout(L, m0, nb, &t->tS, ws + t->off_tS));
+  } else {
+    t->tS = t->tH;
+  }
+  const int64_t m2 = (int64_t)m0 * m0;
+  t->off_strang = take(sizeof(double) * 2 * L * m2);
+  t->off_hat = take(sizeof(double) * 4 * L * m2);
+  t->off_evals = take(sizeof(double) * L * m0);
+  t->off_info = take(sizeof(int) * L);
+  t->off_lf = take(sizeof(double) * 2 * L * m2);
+  t->off_minv = take(sizeof(double) * 2 * L * m2);
+  t->off_rhat = take(sizeof(double) * 2 * L * t->Ev);
+  t->off_z = take(sizeof(double) * 2 * L * t->Ev);
+  t->off_f = take(sizeof(double) * 4 * L * t->Ev);
+  for (int v = 0; v < kNVec; ++v) t->off_vec[v] = take(sizeof(double) * t->N * nb);
+  t->chunk_rows = (int)std::max<int64_t>(32, align_up((size_t)ceil_div(t->N, 256), 32));
+  t->chunks = (int)ceil_div(t->N, t->chunk_rows);
+  t->off_part = take(sizeof(double) * t->chunks * 2 * kLobMaxBasis * kLobMaxBasis);
+  t->off_gram = take(sizeof(double) * 2 * kLobMaxBasis * kLobMaxBasis);
+  t->off_y = take(sizeof(double) * kLobMaxBasis * kLobMaxNb);
+  t->off_lam = take(sizeof(double) * kLobMaxNb);
+  t->off_sinfo = take(sizeof(int) * 4);
+  t->off_norms = take(sizeof(double) * 2 * kLobMaxNb);
+  t->off_scal = take(sizeof(double) * 4);
+  t->off_mask = take(sizeof(double) * kLobMaxNb);
+  t->off_lambest = take(sizeof(double) * kLobMaxNb);
+  const int Ls[3] = {L, 1, 1};
+  auto ptr = [&](size_t off) { return (double*)(ws ? ws + off : nullptr); };
+  if (!plan_fft_cols(ptr(t->off_strang), ptr(t->off_hat), Ls, m2, 2, &t->fblk, 64) ||
+      !plan_fft_cols(ptr(t->off_vec[kW]), ptr(t->off_rhat), Ls, t->Ev, 1, &t->fr, 64) ||
+      !plan_fft_cols(ptr(t->off_z), ptr(t->off_f), Ls, t->Ev, 2, &t->fz, 64)) {
+    set_error("no FFT plan for L = %d", L);
+    return TL_EUNSUPPORTED;
+  }
+  FftArgs* plans[3] = {&t->fblk, &t->fr, &t->fz};
+  for (int q = 0; q < 3; ++q) {
+    t->off_tab[q] = take(fft_blue_table_bytes(*plans[q]));
+    if (ws) set_fft_blue_tables(plans[q], ws + t->off_tab[q]);
+  }
+  t->bytes = o;
+  return TL_OK;
+}
+
+}  // namespace
+
+tl_status batched_heigh(const double* H, const double* S, int count, int m, double* evals,
+                        double* evecs, int* info, hipStream_t stream);
+
+namespace {
+
+tl_status lob_read(const void* dev, void* host, size_t bytes, hipStream_t st) {
+  TL_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st));
+  TL_HIP(hipStreamSynchronize(st));
+  return TL_OK;
+}
+
+// Host driver of the solver; every step is a kernel, the host only reads the
+// residual norms, the Ritz values and the basis rank to steer the iteration.
+class Lobpcg {
+ public:
+  Lobpcg(const LobLayout& t, char* ws, hipStream_t st) : t_(t), ws_(ws), st_(st) {
+    for (int i = 0; i < kNVec; ++i) cur_[i] = i;
+  }
+  double* v(int logical) const { return (double*)(ws_ + t_.off_vec[cur_[logical]]); }
+  double* at(size_t off) const { return (double*)(ws_ + off); }
+
+  tl_status products(int src, int dA, int dB) {
+    TL_TRY(matvec(t_.tH, ws_ + t_.off_tH, v(src), v(dA), st_));
+    return matvec(t_.tS, ws_ + t_.off_tS, v(src), v(dB), st_);
+  }
+  // gram[s] = [V_0 | ...]^T [U_s0 | ...]; us1 null: one set
+  tl_status gram(const int* vb, const int* us0, const int* us1, int nblk) {
+    GramArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.nblk = nblk;
+    g.nsets = us1 ? 2 : 1;
+    g.nb = t_.nb;
+    g.N = t_.N;
+    g.chunk_rows = t_.chunk_rows;
+    g.part = at(t_.off_part);
+    for (int b = 0; b < nblk; ++b) {
+      g.V[b] = v(vb[b]);
+      g.U[0][b] = v(us0[b]);
+      if (us1) g.U[1][b] = v(us1[b]);
+    }
+    hipLaunchKernelGGL(lob_gram_kernel, dim3((unsigned)t_.chunks), dim3(256), 0, st_, g);
+    TL_CHECK_LAUNCH();
+    const int tot = g.nsets * kLobMaxBasis * kLobMaxBasis;
+    hipLaunchKernelGGL(lob_gram_reduce_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0,
+                       st_, (const double*)at(t_.off_part), t_.chunks, g.nsets, at(t_.off_gram));
+    TL_CHECK_LAUNCH();
+    return TL_OK;
+  }
+  // Rayleigh-Ritz on [X | W | P][0..nblk): Y, lam, rank check
+  tl_status rayleigh_ritz(int nblk) {
+    const int vb[3] = {kX, kW, kP}, ua[3] = {kAX, kAW, kAP}, ub[3] = {kBX, kBW, kBP};
+    TL_TRY(gram(vb, ua, ub, nblk));
+    const size_t lds = sizeof(double) * 4 * kLobMaxBasis * kLobLd;
+    hipLaunchKernelGGL(lob_small_kernel, dim3(1), dim3(256), lds, st_,
+                       (const double*)at(t_.off_gram), nblk * t_.nb, t_.nb, at(t_.off_y),
+                       at(t_.off_lam), (int*)(ws_ + t_.off_sinfo));
+    TL_CHECK_LAUNCH();
+    int si[4];
+    TL_TRY(lob_read(ws_ + t_.off_sinfo, si, sizeof(si), st_));
+    if (si[0] < t_.nb) {
+      set_error("Rayleigh-Ritz basis of rank %d below the block size %d", si[0], t_.nb);
+      return TL_EINVAL;
+    }
+    return TL_OK;
+  }
+  // X <- X Y_x + P_new, P_new = W Y_w + P Y_p (all three families)
+  tl_status update(int nblk) {
+    const double* Y = at(t_.off_y);
+    const int64_t nb = t_.nb;
+    const int xs[3] = {kX, kAX, kBX}, ws[3] = {kW, kAW, kBW}, ps[3] = {kP, kAP, kBP};
+    const int x2[3] = {kX2, kAX2, kBX2}, p2[3] = {kP2, kAP2, kBP2};
+    if (nblk > 1) {
+      TsArgs a = base();
+      for (int f = 0; f < 3; ++f) {
+        a.in[f][0] = v(ws[f]);
+        a.in[f][1] = v(ps[f]);
+        a.out[f] = v(p2[f]);
+      }
+      a.Y[0] = Y + nb * nb;
+      a.Y[1] = Y + 2 * nb * nb;
+      a.nin = nblk - 1;
+      TL_TRY(launch_ts(a));
+    }
+    TsArgs a = base();
+    for (int f = 0; f < 3; ++f) {
+      a.in[f][0] = v(xs[f]);
+      a.out[f] = v(x2[f]);
+      a.add[f] = nblk > 1 ? v(p2[f]) : nullptr;
+    }
+    a.Y[0] = Y;
+    a.nin = 1;
+    TL_TRY(launch_ts(a));
+    for (int f = 0; f < 3; ++f) {
+      std::swap(cur_[xs[f]], cur_[x2[f]]);
+      if (nblk > 1) std::swap(cur_[ps[f]], cur_[p2[f]]);
+    }
+    return TL_OK;
+  }
+  // W <- W - X (BX^T W)
+  tl_status project_w() {
+    const int vb[1] = {kBX}, ub[1] = {kW};
+    TL_TRY(gram(vb, ub, nullptr, 1));
+    TsArgs a = base();
+    a.in[0][0] = v(kX);
+    a.out[0] = v(kW);
+    a.Y[0] = at(t_.off_gram);
+    a.ldy = kLobMaxBasis;
+    a.nin = 1;
+    a.alpha = -1.0;
+    a.beta = 1.0;
+    hipLaunchKernelGGL(lob_ts_kernel, dim3((unsigned)ceil_div(t_.N * t_.nb, 256), 1), dim3(256),
+                       0, st_, a);
+    TL_CHECK_LAUNCH();
+    return TL_OK;
+  }
+  // keep (X, lam) as the best iterate so far, or return to it
+  tl_status keep_best(bool restore) {
+    const size_t bx = sizeof(double) * t_.N * t_.nb, bl = sizeof(double) * t_.nb;
+    double* best = (double*)(ws_ + t_.off_vec[kBest]);
+    if (restore) {
+      TL_HIP(hipMemcpyAsync(v(kX), best, bx, hipMemcpyDeviceToDevice, st_));
+      TL_HIP(hipMemcpyAsync(at(t_.off_lam), at(t_.off_lambest), bl, hipMemcpyDeviceToDevice, st_));
+    } else {
+      TL_HIP(hipMemcpyAsync(best, v(kX), bx, hipMemcpyDeviceToDevice, st_));
+      TL_HIP(hipMemcpyAsync(at(t_.off_lambest), at(t_.off_lam), bl, hipMemcpyDeviceToDevice, st_));
+    }
+    return TL_OK;
+  }
+  // zero the residual columns whose mask entry is 0 (soft locking)
+  tl_status mask(const double* mask_h) {
+    TL_HIP(hipMemcpyAsync(at(t_.off_mask), mask_h, sizeof(double) * t_.nb, hipMemcpyHostToDevice,
+                          st_));
+    hipLaunchKernelGGL(lob_mask_kernel, dim3((unsigned)ceil_div(t_.N * t_.nb, 256)), dim3(256), 0,
+                       st_, v(kW), (const double*)at(t_.off_mask), t_.N, t_.nb);
+    TL_CHECK_LAUNCH();
+    return TL_OK;
+  }
+  // W <- Strang shift-inverse of W (through the block DFT over L cells)
+  tl_status precondition() {
+    TL_TRY(launch_fft(t_.fr, st_));
+    const int64_t nx = (int64_t)t_.L * t_.Ev;
+    hipLaunchKernelGGL(mul_kernel, dim3((unsigned)ceil_div(nx, 256)), dim3(256), 0, st_,
+                       MulArgs{(const double*)at(t_.off_minv), (const double*)at(t_.off_rhat),
+                               at(t_.off_z), t_.L, t_.m0, t_.nb});
+    TL_CHECK_LAUNCH();
+    TL_TRY(launch_fft(t_.fz, st_));
+    hipLaunchKernelGGL(comb_kernel, dim3((unsigned)ceil_div(nx, 256)), dim3(256), 0, st_,
+                       CombArgs{(const double*)at(t_.off_f), v(kW), t_.L, t_.L, t_.Ev});
+    TL_CHECK_LAUNCH();
+    return TL_OK;
+  }
+  // R = AX - BX lam into W; column norms of R and X read back with lam
+  tl_status residuals(double* lam_h, double* norms_h) {
+    const int64_t n = t_.N * t_.nb;
+    hipLaunchKernelGGL(lob_resid_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st_,
+                       (const double*)v(kAX), (const double*)v(kBX),
+                       (const double*)at(t_.off_lam), v(kW), t_.N, t_.nb);
+    TL_CHECK_LAUNCH();
+    hipLaunchKernelGGL(lob_colnorm_kernel, dim3((unsigned)t_.nb), dim3(256), 0, st_,
+                       (const double*)v(kW), (const double*)v(kX), t_.N, t_.nb,
+                       at(t_.off_norms));
+    TL_CHECK_LAUNCH();
+    TL_HIP(hipMemcpyAsync(lam_h, at(t_.off_lam), sizeof(double) * t_.nb, hipMemcpyDeviceToHost,
+                          st_));
+    return lob_read(at(t_.off_norms), norms_h, sizeof(double) * 2 * t_.nb, st_);
+  }
+
+ private:
+  TsArgs base() const {
+    TsArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nb = t_.nb;
+    a.ldy = t_.nb;
+    a.N = t_.N;
+    a.alpha = 1.0;
+    a.beta = 0.0;
+    return a;
+  }
+  tl_status launch_ts(const TsArgs& a) {
+    hipLaunchKernelGGL(lob_ts_kernel, dim3((unsigned)ceil_div(t_.N * t_.nb, 256), 3), dim3(256),
+                       0, st_, a);
+    TL_CHECK_LAUNCH();
+    return TL_OK;
+  }
+  const LobLayout& t_;
+  char* ws_;
+  hipStream_t st_;
+  int cur_[kNVec];
+};
+
+tl_status btoepl_lowest(const double* Hb, const double* Sb, int L, int m0, int nev, int nb,
+                        int max_iter, double tol, double shift, const double* x0, double* evals,
+                        double* evecs, double* resid, int* iters, int* nconv, char* ws,
+                        size_t ws_bytes, hipStream_t st) {
+  LobLayout t;
+  TL_TRY(lob_layout(L, m0, nb, &t, ws));
+  if (ws_bytes < t.bytes) {
+    set_error("workspace: need %zu bytes, got %zu", t.bytes, ws_bytes);
+    return TL_EWORKSPACE;
+  }
+  const size_t lds = sizeof(double) * 4 * kLobMaxBasis * kLobLd;
+  TL_HIP(hipFuncSetAttribute((const void*)lob_small_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  Lobpcg lob(t, ws, st);
+  const int64_t m2 = (int64_t)m0 * m0;
+  // the two Toeplitz operators
+  for (int w = 0; w < 2; ++w) {
+    const ToeplitzLayout& tw = w ? t.tS : t.tH;
+    char* base = ws + (w ? t.off_tS : t.off_tH);
+    const int64_t nbk = 2 * (int64_t)L * m2;
+    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)ceil_div(nbk, 256)), dim3(256), 0, st,
+                       EmbedArgs{w ? Sb : Hb, (double*)(base + tw.off_xt), L, m0});
+    TL_CHECK_LAUNCH();
+    TL_TRY(launch_fft(tw.fb, st));
+  }
+  // preconditioner: Strang k-blocks, their lowest eigenvalue, the shifted inverses
+  StrangArgs sa{{Hb, Sb}, lob.at(t.off_strang), L, m0};
+  hipLaunchKernelGGL(strang_kernel, dim3((unsigned)ceil_div(2 * L * m2, 256)), dim3(256), 0, st,
+                     sa);
+  TL_CHECK_LAUNCH();
+  TL_TRY(launch_fft(t.fblk, st));
+  const double* hat = lob.at(t.off_hat);
+  int* kinfo = (int*)(ws + t.off_info);
+  TL_TRY(batched_heigh(hat, hat + 2 * (int64_t)L * m2, L, m0, lob.at(t.off_evals), nullptr,
+                       kinfo, st));
+  double* scal = lob.at(t.off_scal);
+  hipLaunchKernelGGL(lmin_kernel, dim3(1), dim3(256), 0, st, (const double*)lob.at(t.off_evals),
+                     (const int*)kinfo, L, m0, scal);
+  TL_CHECK_LAUNCH();
+  hipLaunchKernelGGL(tnorm_kernel, dim3(1), dim3(256), 0, st, Hb, Sb, L, m0, scal);
+  TL_CHECK_LAUNCH();
+  double sc[4];
+  TL_TRY(lob_read(scal, sc, sizeof(sc), st));
+  if (sc[3] != 0.0) {
+    set_error("a k-block of the circulant preconditioner is not definite");
+    return TL_EINVAL;
+  }
+  const double lmin = sc[0], nA = sc[1], nB = sc[2];
+  const double sigma = lmin - (shift > 0.0 ? shift : 0.02 * std::max(1.0, std::fabs(lmin)));
+  hipLaunchKernelGGL(minv_kernel, dim3((unsigned)ceil_div(L, 64)), dim3(64), 0, st, hat, L, m0,
+                     sigma, lob.at(t.off_lf), lob.at(t.off_minv), kinfo);
+  TL_CHECK_LAUNCH();
+  hipLaunchKernelGGL(lmin_kernel, dim3(1), dim3(256), 0, st, (const double*)lob.at(t.off_evals),
+                     (const int*)kinfo, L, m0, scal);
+  TL_CHECK_LAUNCH();
+  TL_TRY(lob_read(scal, sc, sizeof(sc), st));
+  if (sc[3] != 0.0) {
+    set_error("shifted circulant block not positive definite");
+    return TL_EINVAL;
+  }
+
+  // start block and its Rayleigh-Ritz
+  const int64_t nx = t.N * nb;
+  if (x0) {
+    TL_HIP(hipMemcpyAsync(lob.v(kX), x0, sizeof(double) * nx, hipMemcpyDeviceToDevice, st));
+  } else {
+    hipLaunchKernelGGL(lob_rand_kernel, dim3((unsigned)ceil_div(nx, 256)), dim3(256), 0, st,
+                       lob.v(kX), nx, (uint64_t)0x5EEDull);
+    TL_CHECK_LAUNCH();
+  }
+  TL_TRY(lob.products(kX, kAX, kBX));
+  TL_TRY(lob.rayleigh_ritz(1));
+  TL_TRY(lob.update(1));
+
+  std::vector<double> lam_h(nb), norms_h(2 * nb), rel(nb), mask_h(nb);
+  double worst = 0.0;  // largest relative residual of the wanted pairs
+  auto count_converged = [&]() {
+    int c = 0;
+    worst = 0.0;
+    for (int j = 0; j < nb; ++j) {
+      rel[j] = std::sqrt(norms_h[j]) /
+               ((nA + std::fabs(lam_h[j]) * nB) * std::sqrt(norms_h[nb + j]));
+      if (j < nev && rel[j] <= tol) ++c;
+      if (j < nev) worst = std::max(worst, rel[j]);
+    }
+    return c;
+  };
+  // near the rounding floor the iteration can lose accuracy again; the best
+  // iterate (most converged pairs, then smallest worst residual) is kept
+  int nblk = 2, it = 0, conv = 0, best_conv = -1;
+  double best_worst = INFINITY;
+  for (it = 1; it <= max_iter; ++it) {
+    if (it % kLobRefresh == 0) TL_TRY(lob.products(kX, kAX, kBX));
+    TL_TRY(lob.residuals(lam_h.data(), norms_h.data()));
+    conv = count_converged();
+    if (conv > best_conv || (conv == best_conv && worst < best_worst)) {
+      best_conv = conv;
+      best_worst = worst;
+      TL_TRY(lob.keep_best(false));
+    }
+    if (conv == nev) break;
+    // soft locking: converged wanted pairs stay in the basis through X but
+    // add no new direction (their residuals are rounding noise)
+    for (int j = 0; j < nb; ++j) mask_h[j] = (j < nev && rel[j] <= tol) ? 0.0 : 1.0;
+    TL_TRY(lob.mask(mask_h.data()));
+    TL_TRY(lob.precondition());
+    TL_TRY(lob.project_w());
+    TL_TRY(lob.products(kW, kAW, kBW));
+    TL_TRY(lob.rayleigh_ritz(nblk));
+    TL_TRY(lob.update(nblk));
+    nblk = 3;
+  }
+  // final residuals from fresh products; the best iterate if the last is worse
+  TL_TRY(lob.products(kX, kAX, kBX));
+  TL_TRY(lob.residuals(lam_h.data(), norms_h.data()));
+  conv = count_converged();
+  if (conv < best_conv || (conv == best_conv && worst > best_worst)) {
+    TL_TRY(lob.keep_best(true));
+    TL_TRY(lob.products(kX, kAX, kBX));
+    TL_TRY(lob.residuals(lam_h.data(), norms_h.data()));
+    conv = count_converged();
+  }
+  *iters = std::min(it, max_iter);
+  *nconv = conv;
+  TL_HIP(hipMemcpyAsync(evals, lob.at(t.off_lam), sizeof(double) * nev, hipMemcpyDeviceToDevice,
+                        st));
+  if (resid)
+    TL_HIP(hipMemcpyAsync(resid, rel.data(), sizeof(double) * nev, hipMemcpyHostToDevice, st));
+  if (evecs) {
+    hipLaunchKernelGGL(lob_cols_kernel, dim3((unsigned)ceil_div(t.N * nev, 256)), dim3(256), 0,
+                       st, (const double*)lob.v(kX), evecs, t.N, nb, nev);
+    TL_CHECK_LAUNCH();
+  }
+  TL_HIP(hipStreamSynchronize(st));  // rel is a host buffer of this call
+  return TL_OK;
+}
+
 }  // namespace
 }  // namespace tl
 
@@ -249,4 +1215,31 @@ extern "C" tl_status tl_btoepl_power(int L, int m0, int iters, double* x_dev, do
     TL_CHECK_LAUNCH();
   }
   return TL_OK;
+}
+
+extern "C" tl_status tl_btoepl_lowest_workspace_bytes(int L, int m0, int nb, size_t* bytes) {
+  clear_error();
+  TL_REQUIRE(bytes != nullptr, "null output");
+  LobLayout t;
+  TL_TRY(lob_layout(L, m0, nb, &t, nullptr));
+  *bytes = t.bytes;
+  return TL_OK;
+}
+
+extern "C" tl_status tl_btoepl_lowest(const double* H_dev, const double* S_dev, int L, int m0,
+                                      int nev, int nb, int max_iter, double tol, double shift,
+                                      const double* x0_dev, double* evals_dev, double* evecs_dev,
+                                      double* resid_dev, int* iters, int* nconv, void* ws_dev,
+                                      size_t ws_bytes, void* stream) {
+  clear_error();
+  TL_REQUIRE(H_dev && S_dev && evals_dev && iters && nconv && ws_dev, "null argument");
+  TL_REQUIRE(nb >= 1 && nb <= kLobMaxNb, "nb = %d outside [1, %d]", nb, kLobMaxNb);
+  TL_REQUIRE(nev >= 1 && nev <= nb, "nev = %d outside [1, nb = %d]", nev, nb);
+  TL_REQUIRE((int64_t)L * m0 >= 3 * (int64_t)nb, "L m0 = %lld below 3 nb = %d",
+             (long long)L * m0, 3 * nb);
+  TL_REQUIRE(max_iter >= 1, "max_iter = %d < 1", max_iter);
+  TL_REQUIRE(tol > 0.0, "tol must be positive");
+  return btoepl_lowest(H_dev, S_dev, L, m0, nev, nb, max_iter, tol, shift, x0_dev, evals_dev,
+                       evecs_dev, resid_dev, iters, nconv, (char*)ws_dev, ws_bytes,
+                       (hipStream_t)stream);
 }

@@ -217,3 +217,25 @@ def test_btoepl_sizes_and_validation():
         tl.tl_btoepl_workspace_bytes(16, 4, 0)
     _expect(tl.tl_btoepl_matvec, tl.TL_EINVAL, 8, 8, 16, 4, 2, 8, 8, 0)   # workspace too small
     _expect(tl.tl_btoepl_power, tl.TL_EINVAL, 16, 4, 0, 8, 8, 8, 8, 1 << 30, 0)
+
+
+def test_btoepl_lowest_sizes_and_validation():
+    b = tl.tl_btoepl_lowest_workspace_bytes(256, 4, 12)
+    # two embedded operators, 15 blocks of N nb vectors, the preconditioner's k-blocks
+    assert b >= 2 * tl.tl_btoepl_workspace_bytes(256, 4, 12) + 8 * 15 * 1024 * 12
+    with pytest.raises(tl.TlError):
+        tl.tl_btoepl_lowest_workspace_bytes(256, 4, 22)
+    with pytest.raises(tl.TlError):
+        tl.tl_btoepl_lowest_workspace_bytes(2049, 4, 8)
+    args = dict(H=8, S=8, L=64, m0=4, nev=4, nb=8, max_iter=10, tol=1e-9, shift=0.0, x0=None,
+                evals=8, evecs=None, resid=None, ws=8, ws_bytes=8, stream=0)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return tl.tl_btoepl_lowest(a["H"], a["S"], a["L"], a["m0"], a["nev"], a["nb"],
+                                   a["max_iter"], a["tol"], a["shift"], a["x0"], a["evals"],
+                                   a["evecs"], a["resid"], a["ws"], a["ws_bytes"], a["stream"])
+    for bad in [dict(nev=9), dict(nev=0), dict(nb=22), dict(L=5, m0=1), dict(max_iter=0),
+                dict(tol=0.0), dict(H=None), dict(evals=None)]:
+        _expect(lambda: call(**bad), tl.TL_EINVAL)
+    _expect(call, tl.TL_EWORKSPACE)  # 8 bytes of workspace

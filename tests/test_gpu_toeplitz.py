@@ -124,3 +124,120 @@ def test_btoepl_power_senior_eigenvalue():
     assert ratio < 0.9
     assert err <= 1e-13
     assert 1.0 - abs(np.dot(V[:, i], x)) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# lowest eigenpairs of the block-Toeplitz pencil (tl_btoepl_lowest)
+
+
+def _chain_pencil(L, nd=4):
+    """The infinite s-chain's pencil restricted to L cells: the first nd
+    generating blocks (shifts 0..nd-1) of the periodic (8,1,1) chain, m0 = 4,
+    zero beyond."""
+    H, S, _ = oracle.core_hamiltonian_blocks(wl.config(1))
+    m0 = H.shape[-1]
+    H = H.reshape(-1, m0, m0)
+    S = S.reshape(-1, m0, m0)
+    Hb = np.zeros((L, m0, m0))
+    Sb = np.zeros_like(Hb)
+    Hb[:nd] = H[:nd]
+    Sb[:nd] = S[:nd]
+    Hb[0] = 0.5 * (Hb[0] + Hb[0].T)
+    Sb[0] = 0.5 * (Sb[0] + Sb[0].T)
+    return Hb, Sb
+
+
+def _lowest(Hb, Sb, nev, nb, max_iter=400, tol=1e-10, shift=0.0, x0=None):
+    L, m0, _ = Hb.shape
+    ws_bytes = tl.tl_btoepl_lowest_workspace_bytes(L, m0, nb)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    Hd = torch.from_numpy(np.ascontiguousarray(Hb)).cuda()
+    Sd = torch.from_numpy(np.ascontiguousarray(Sb)).cuda()
+    f64 = dict(dtype=torch.float64, device="cuda")
+    ev = torch.full((nev,), float("nan"), **f64)
+    U = torch.full((L * m0, nev), float("nan"), **f64)
+    res = torch.full((nev,), float("nan"), **f64)
+    xd = None if x0 is None else torch.from_numpy(np.ascontiguousarray(x0)).cuda()
+    it, nc = tl.tl_btoepl_lowest(Hd, Sd, L, m0, nev, nb, max_iter, tol, shift, xd, ev, U, res, ws,
+                                 ws_bytes)
+    torch.cuda.synchronize()
+    return it, nc, ev.cpu().numpy(), U.cpu().numpy(), res.cpu().numpy()
+
+
+def _check_pairs(Hb, Sb, lam, U, tol, label):
+    """Against the oracle: eigenvalues of the explicit pencil within the
+    residual bound |lambda - mu| <= |r|_2 / sqrt(lambda_min(T_S)) for a
+    T_S-normalised Ritz pair, residuals recomputed with the explicit
+    matrices, T_S-normalisation."""
+    T = oracle.btoepl_full(Hb)
+    S = oracle.btoepl_full(Sb)
+    nev = lam.size
+    w, _ = oracle.lowest_generalized_eigs(T, S, nev)
+    smin = np.linalg.eigvalsh(S)[0]
+    R = T @ U - (S @ U) * lam
+    rn = np.linalg.norm(R, axis=0)
+    nT = np.abs(T).sum(axis=1).max()
+    nS = np.abs(S).sum(axis=1).max()
+    rel = rn / ((nT + np.abs(lam) * nS) * np.linalg.norm(U, axis=0))
+    bound = rn / np.sqrt(smin) + 1e-13 * nT
+    err = np.abs(lam - w)
+    gram = U.T @ S @ U
+    print(f"\n{label}: max |dlambda| = {err.max():.2e} (bound {bound.min():.2e}..{bound.max():.2e}),"
+          f" max rel residual {rel.max():.2e}, |U^T S U - I| = {np.abs(gram - np.eye(nev)).max():.2e}")
+    assert np.all(err <= bound)
+    assert rel.max() <= 10 * tol
+    assert np.abs(np.diag(gram) - 1.0).max() <= 1e-9
+
+
+@pytest.mark.parametrize("L", [256, 600])
+def test_btoepl_lowest_chain(L):
+    """Lowest 8 states of the s-chain pencil (band bottom, eigenvalue spacing
+    ~1e-5 Ha at L = 600) with 4 guard vectors, to a relative residual of 1e-9
+    (the pencil's rounding floor is near 1e-10: kappa(T_S) ~ 4e5)."""
+    Hb, Sb = _chain_pencil(L)
+    it, nc, lam, U, res = _lowest(Hb, Sb, 8, 12, tol=1e-9)
+    print(f"\nL = {L}: {it} iterations, {nc} converged, residuals {res.max():.2e}")
+    assert nc == 8 and np.all(res <= 1e-9)
+    assert np.all(np.diff(lam) >= 0)
+    _check_pairs(Hb, Sb, lam, U, 1e-9, f"chain L={L}")
+
+
+def test_btoepl_lowest_random_pencil():
+    """Random banded pencil, L = 61 (prime: Bluestein transforms of lengths
+    L and 2L), m0 = 3, T_S diagonally dominant."""
+    rng = np.random.default_rng(61)
+    L, m0 = 61, 3
+    Hb = np.zeros((L, m0, m0))
+    Sb = np.zeros_like(Hb)
+    h0 = rng.standard_normal((m0, m0))
+    s0 = rng.standard_normal((m0, m0))
+    Hb[0] = h0 + h0.T
+    Sb[0] = np.eye(m0) + 0.025 * (s0 + s0.T)
+    for k, (hs, ss) in enumerate([(0.5, 0.05), (0.2, 0.01)], start=1):
+        Hb[k] = hs * rng.standard_normal((m0, m0))
+        Sb[k] = ss * rng.standard_normal((m0, m0))
+    it, nc, lam, U, res = _lowest(Hb, Sb, 4, 6, tol=1e-11)
+    print(f"\nrandom pencil: {it} iterations, {nc} converged")
+    assert nc == 4
+    _check_pairs(Hb, Sb, lam, U, 1e-11, "random L=61")
+
+
+def test_btoepl_lowest_start_block():
+    """A start block spanning the wanted eigenvectors (the oracle's, plus
+    others) converges at the first check; a start block is used as given."""
+    Hb, Sb = _chain_pencil(128)
+    T = oracle.btoepl_full(Hb)
+    S = oracle.btoepl_full(Sb)
+    _, V = oracle.lowest_generalized_eigs(T, S, 10)
+    it, nc, lam, U, res = _lowest(Hb, Sb, 6, 10, tol=1e-9, x0=V)
+    print(f"\nexact start block: {it} iterations, residuals {res.max():.2e}")
+    assert it <= 2 and nc == 6
+    _check_pairs(Hb, Sb, lam, U, 1e-9, "start block")
+
+
+def test_btoepl_lowest_iteration_limit():
+    """max_iter reached: no error, nconv < nev, finite last iterate."""
+    Hb, Sb = _chain_pencil(600)
+    it, nc, lam, U, res = _lowest(Hb, Sb, 8, 12, max_iter=2, tol=1e-12)
+    assert it == 2 and nc < 8
+    assert np.all(np.isfinite(lam)) and np.all(np.isfinite(U)) and np.all(np.isfinite(res))
