@@ -451,13 +451,93 @@ def spectra_section():
     return out
 
 
+def _btoepl_dense(A):
+    """The explicit symmetric block-Toeplitz matrix of the blocks A [L][m0][m0]
+    (a torch tensor on the GPU): block (r, c) = A_(r-c) for r >= c, A_(c-r)^T
+    above; input marshalling for the checks against dense products."""
+    import torch
+    L, m0, _ = A.shape
+    idx = torch.arange(L, device=A.device)
+    d = idx[:, None] - idx[None, :]
+    low = A[d.clamp(min=0)]
+    up = A[(-d).clamp(min=0)].transpose(-1, -2)
+    T = torch.where((d >= 0)[:, :, None, None], low, up)
+    return T.permute(0, 2, 1, 3).reshape(L * m0, L * m0).contiguous()
+
+
+def toeplitz_lowest_section():
+    """Lowest 16 eigenpairs of the infinite s-chain's pencil restricted to
+    1920 cells (m0 = 4, N = 7680: the largest order the dense eigensolver
+    takes) by the preconditioned LOBPCG on the embedded products, against
+    the dense generalized eigensolver on the explicit matrices."""
+    import torch
+    from paper_1408_3839_amd import tl, workloads
+    from paper_1408_3839_amd.pipeline import DenseEigh, PeriodicPipeline
+    pp = PeriodicPipeline(workloads.config(1))
+    pp.basis_and_potential()
+    pp.assemble()
+    torch.cuda.synchronize()
+    m0, L, nd, nev, nb, tol = pp.m0, 1920, 4, 16, 21, 1e-9
+    f64 = dict(dtype=torch.float64, device="cuda")
+    Hb = torch.zeros(L, m0, m0, **f64)
+    Sb = torch.zeros(L, m0, m0, **f64)
+    Hb[:nd] = pp.H.reshape(-1, m0, m0)[:nd]
+    Sb[:nd] = pp.S.reshape(-1, m0, m0)[:nd]
+    Hb[0] = 0.5 * (Hb[0] + Hb[0].T)
+    Sb[0] = 0.5 * (Sb[0] + Sb[0].T)
+    del pp
+    N = L * m0
+    ws_bytes = tl.tl_btoepl_lowest_workspace_bytes(L, m0, nb)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    lam = torch.empty(nev, **f64)
+    U = torch.empty(N, nev, **f64)
+    res = torch.empty(nev, **f64)
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    tl.tl_btoepl_lowest(Hb, Sb, L, m0, nev, nb, 400, tol, 0.0, None, lam, U, res, ws, ws_bytes)
+    a, b = ev(), ev()
+    a.record(stream)
+    it, nc = tl.tl_btoepl_lowest(Hb, Sb, L, m0, nev, nb, 400, tol, 0.0, None, lam, U, res, ws,
+                                 ws_bytes)
+    b.record(stream)
+    torch.cuda.synchronize()
+    lob_ms = a.elapsed_time(b)
+    # dense route on the explicit matrices
+    TH, TS = _btoepl_dense(Hb), _btoepl_dense(Sb)
+    eig = DenseEigh(N, nev, with_evecs=False)
+    eig.run(TH, TS)
+    torch.cuda.synchronize()
+    a, b = ev(), ev()
+    a.record(stream)
+    eig.run(TH, TS)
+    b.record(stream)
+    torch.cuda.synchronize()
+    dense_ms = a.elapsed_time(b)
+    w = eig.evals.cpu().numpy()
+    lam_h = lam.cpu().numpy()
+    # residuals with the explicit matrices
+    R = TH @ U - (TS @ U) * lam[None, :]
+    rel = (torch.linalg.norm(R, dim=0)
+           / ((TH.abs().sum(1).max() + lam.abs() * TS.abs().sum(1).max())
+              * torch.linalg.norm(U, dim=0))).max().item()
+    return {
+        "workload": "infinite s-chain pencil (periodic (8,1,1) chain's generating blocks, "
+                    "shifts 0..3) restricted to 1920 cells, m0=4, N=7680; lowest 16",
+        "block": nb, "tol": tol, "iterations": it, "converged": nc,
+        "lobpcg_ms": lob_ms, "ms_per_iteration": lob_ms / max(it, 1),
+        "dense_eigensolver_ms": dense_ms,
+        "max_abs_dlambda_vs_dense_Ha": float(np.abs(lam_h - w).max()),
+        "max_rel_residual_explicit": rel,
+        "lambda_min_Ha": float(lam_h[0]), "lambda_16_Ha": float(lam_h[-1]),
+    }
+
+
 def toeplitz_section(steps: int):
     """Products with the open chain's H made shift-invariant (its central
     block row replicated: a symmetric block-Toeplitz matrix of 256 cells,
     m0 = 8) through the double-size circulant embedding, 64 vectors, against
     the explicit matrix; and the power method for its senior eigenvalue."""
     import torch
-    import oracle
     from paper_1408_3839_amd import tl, workloads
     from paper_1408_3839_amd.pipeline import BoxPipeline
     bp = BoxPipeline(workloads.config(3))
@@ -492,10 +572,10 @@ def toeplitz_section(steps: int):
         torch.cuda.synchronize()
         ts.append(a.elapsed_time(b))
         tm.append(b.elapsed_time(c))
-    T = oracle.btoepl_full(A)
-    Yr = (T @ X.reshape(L * m0, nvec)).reshape(L, m0, nvec)
-    err = float(np.abs(Yd.cpu().numpy() - Yr).max() / (np.abs(T).sum(axis=1).max()
-                                                        * np.abs(X).max()))
+    T = _btoepl_dense(Ad)
+    Yr = T @ Xd.reshape(L * m0, nvec)
+    err = float((Yd.reshape(L * m0, nvec) - Yr).abs().max().item()
+                / (T.abs().sum(1).max().item() * np.abs(X).max()))
     ms = float(np.median(tm))
     # power method, 400 iterations from a constant start
     iters = 400
@@ -510,7 +590,7 @@ def toeplitz_section(steps: int):
     tl.tl_btoepl_power(L, m0, iters, x, y, lam, w1, ws1)
     b.record(stream)
     torch.cuda.synchronize()
-    w = np.linalg.eigvalsh(T)
+    w = torch.linalg.eigvalsh(T).cpu().numpy()
     top = float(w[np.argmax(np.abs(w))])
     return {
         "workload": "open (256,1,1) chain H, central block row replicated: symmetric block "
@@ -859,6 +939,7 @@ def main():
         out["spectra"] = spectra_section()
     if not args.no_toeplitz:
         out["toeplitz"] = toeplitz_section(min(args.steps, 20))
+        out["toeplitz_lowest"] = toeplitz_lowest_section()
     print(json.dumps(out))
 
 

@@ -211,8 +211,9 @@ tl_status matvec(const ToeplitzLayout& t, char* ws, const double* X, double* Y,
 //   * W is made T_S-orthogonal to X before its products are taken; the basis
 //     [X, W, P] is orthonormalised in the T_S metric by SVQB (Stathopoulos
 //     and Wu, SIAM J. Sci. Comput. 23 (2002)): columns scaled to unit norm,
-//     the Gram matrix diagonalised, directions with eigenvalue below 1e-12 of
-//     the largest dropped;
+//     the Gram matrix diagonalised, directions with eigenvalue below 1e-8 of
+//     the largest dropped (T_S-products of nearly dependent directions carry
+//     too few digits for a Rayleigh quotient);
 //   * the small eigenproblems (order <= 3 nb <= 64) are solved by cyclic
 //     Jacobi in one workgroup's LDS;
 //   * T_H X and T_S X are recomputed from X every 10 steps (the recurrences
@@ -223,7 +224,7 @@ tl_status matvec(const ToeplitzLayout& t, char* ws, const double* X, double* Y,
 constexpr int kLobMaxBasis = 64;  // 3 nb, padded
 constexpr int kLobMaxNb = 21;
 constexpr int kLobLd = kLobMaxBasis + 1;
-constexpr double kLobDrop = 1e-12;
+constexpr double kLobDrop = 1e-8;
 constexpr int kLobRefresh = 10;
 
 // Strang circulant blocks of A (first block column), H and S stacked.
@@ -478,19 +479,24 @@ __global__ __launch_bounds__(256) void lob_gram_reduce_kernel(const double* part
 
 // Cyclic Jacobi on the symmetric n x n matrix A (LDS, row stride kLobLd),
 // eigenvectors accumulated into V (columns); parallel round-robin ordering,
-// n / 2 disjoint rotations per step.  On return A's diagonal holds the
-// eigenvalues.
+// n / 2 disjoint rotations per step.  kLobThreads threads: in the update
+// phases thread t applies pair t / 32 to rows (then columns) t % 32 and
+// t % 32 + 32.  On return A's diagonal holds the eigenvalues.
+constexpr int kLobThreads = 1024;
+
 __device__ void jacobi_lds(double (*A)[kLobLd], double (*V)[kLobLd], int n, double* rot,
-                           double* red, int* rotated) {
+                           double* red, int* rotated, int* sweeps) {
   const int tid = threadIdx.x;
   const int ne = n + (n & 1);
   const int npair = ne / 2;
+  const int pi = tid >> 5, k0 = tid & 31;
+  if (tid == 0) *sweeps = 0;
   for (int e = tid; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e - i * n;
     V[i][j] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  for (int sweep = 0; sweep < 30; ++sweep) {
     // off-diagonal and total squared norms
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < n * n; e += blockDim.x) {
@@ -501,20 +507,27 @@ __device__ void jacobi_lds(double (*A)[kLobLd], double (*V)[kLobLd], int n, doub
     }
     off = wave_sum_dpp(off);
     tot = wave_sum_dpp(tot);
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     if (lane == 0) {
       red[wave] = off;
-      red[4 + wave] = tot;
+      red[16 + wave] = tot;
     }
     __syncthreads();
-    const double offs = red[0] + red[1] + red[2] + red[3];
-    const double tots = red[4] + red[5] + red[6] + red[7];
+    double offs = 0.0, tots = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      offs += red[w];
+      tots += red[16 + w];
+    }
     const bool any_rot = sweep == 0 || *rotated != 0;
     __syncthreads();
-    // stop once a sweep rotated nothing (every |a_pq| below 1e-18 of
-    // sqrt|a_pp a_qq|), or the off-diagonal part is below 1e-18 of the norm
+    // stop once a sweep rotated nothing (every |a_pq| at most 1e-16 of
+    // sqrt|a_pp a_qq|: eigenvectors to high relative accuracy), or the
+    // off-diagonal part is below 1e-18 of the Frobenius norm
     if (!any_rot || !(offs > 1e-36 * tots) || ne < 2) break;
-    if (tid == 0) *rotated = 0;
+    if (tid == 0) {
+      *sweeps = sweep + 1;
+      *rotated = 0;
+    }
     __syncthreads();
     for (int step = 0; step < ne - 1; ++step) {
       if (tid < npair) {
@@ -524,7 +537,7 @@ __device__ void jacobi_lds(double (*A)[kLobLd], double (*V)[kLobLd], int n, doub
         double c = 1.0, sn = 0.0;
         if (p < n && q < n) {
           const double apq = A[p][q];
-          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * sqrt(fabs(A[p][p] * A[q][q]))) {
+          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-16 * sqrt(fabs(A[p][p] * A[q][q]))) {
             const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -538,29 +551,42 @@ __device__ void jacobi_lds(double (*A)[kLobLd], double (*V)[kLobLd], int n, doub
         rot[4 * i + 3] = sn;
       }
       __syncthreads();
+      int p = 0, q = 0;
+      double c = 1.0, sn = 0.0;
+      if (pi < npair) {
+        p = (int)rot[4 * pi];
+        q = (int)rot[4 * pi + 1];
+        c = rot[4 * pi + 2];
+        sn = rot[4 * pi + 3];
+      }
+      const bool act = pi < npair && p < n && q < n && sn != 0.0;
       // rows p, q of J^T A
-      for (int e = tid; e < npair * n; e += blockDim.x) {
-        const int i = e / n, k = e - i * n;
-        const int p = (int)rot[4 * i], q = (int)rot[4 * i + 1];
-        const double c = rot[4 * i + 2], sn = rot[4 * i + 3];
-        if (p >= n || q >= n || sn == 0.0) continue;
-        const double ap = A[p][k], aq = A[q][k];
-        A[p][k] = c * ap - sn * aq;
-        A[q][k] = sn * ap + c * aq;
+      if (act) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = k0 + 32 * h;
+          if (k < n) {
+            const double ap = A[p][k], aq = A[q][k];
+            A[p][k] = c * ap - sn * aq;
+            A[q][k] = sn * ap + c * aq;
+          }
+        }
       }
       __syncthreads();
       // columns p, q of (J^T A) J and of V J
-      for (int e = tid; e < npair * n; e += blockDim.x) {
-        const int i = e / n, k = e - i * n;
-        const int p = (int)rot[4 * i], q = (int)rot[4 * i + 1];
-        const double c = rot[4 * i + 2], sn = rot[4 * i + 3];
-        if (p >= n || q >= n || sn == 0.0) continue;
-        const double ap = A[k][p], aq = A[k][q];
-        A[k][p] = c * ap - sn * aq;
-        A[k][q] = sn * ap + c * aq;
-        const double vp = V[k][p], vq = V[k][q];
-        V[k][p] = c * vp - sn * vq;
-        V[k][q] = sn * vp + c * vq;
+      if (act) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = k0 + 32 * h;
+          if (k < n) {
+            const double ap = A[k][p], aq = A[k][q];
+            A[k][p] = c * ap - sn * aq;
+            A[k][q] = sn * ap + c * aq;
+            const double vp = V[k][p], vq = V[k][q];
+            V[k][p] = c * vp - sn * vq;
+            V[k][q] = sn * vp + c * vq;
+          }
+        }
       }
       __syncthreads();
     }
@@ -571,16 +597,16 @@ __device__ void jacobi_lds(double (*A)[kLobLd], double (*V)[kLobLd], int n, doub
 // V^T T_S V.  SVQB of gram[1], then the lowest nb eigenpairs of the projected
 // T_H.  Out: Y (n x nb, row stride nb) with X_new = V Y, lam (nb, ascending),
 // info[0] = kept rank r (r < nb: failure).
-__global__ __launch_bounds__(256) void lob_small_kernel(const double* gram, int n, int nb,
+__global__ __launch_bounds__(kLobThreads) void lob_small_kernel(const double* gram, int n, int nb,
                                                         double* Y, double* lam, int* info) {
   extern __shared__ double lds[];
   double(*GA)[kLobLd] = (double(*)[kLobLd])lds;
   double(*GB)[kLobLd] = GA + kLobMaxBasis;
   double(*Q)[kLobLd] = GB + kLobMaxBasis;
   double(*T)[kLobLd] = Q + kLobMaxBasis;
-  __shared__ double D[kLobMaxBasis], th[kLobMaxBasis], rot[4 * kLobMaxBasis / 2], red[8];
+  __shared__ double D[kLobMaxBasis], th[kLobMaxBasis], rot[4 * kLobMaxBasis / 2], red[32];
   __shared__ int keep_idx[kLobMaxBasis], perm[kLobMaxBasis];
-  __shared__ int r_sh, rotated;
+  __shared__ int r_sh, rotated, sw1, sw2;
   const int tid = threadIdx.x;
   const double* gA = gram;
   const double* gB = gram + kLobMaxBasis * kLobMaxBasis;
@@ -597,7 +623,7 @@ __global__ __launch_bounds__(256) void lob_small_kernel(const double* gram, int 
     T[i][j] = D[i] * GB[i][j] * D[j];
   }
   __syncthreads();
-  jacobi_lds(T, Q, n, rot, red, &rotated);
+  jacobi_lds(T, Q, n, rot, red, &rotated, &sw1);
   if (tid < n) th[tid] = T[tid][tid];
   __syncthreads();
   double tmax = 0.0;
@@ -641,7 +667,7 @@ __global__ __launch_bounds__(256) void lob_small_kernel(const double* gram, int 
     GB[a][b] = 0.5 * (v + w);
   }
   __syncthreads();
-  jacobi_lds(GB, GA, r, rot, red, &rotated);  // eigenvectors into GA
+  jacobi_lds(GB, GA, r, rot, red, &rotated, &sw2);  // eigenvectors into GA
   if (tid < r) {
     const double v = GB[tid][tid];
     int rank = 0;
@@ -663,7 +689,11 @@ __global__ __launch_bounds__(256) void lob_small_kernel(const double* gram, int 
     }
     Y[i * nb + j] = v;
   }
-  if (tid == 0) info[0] = r;
+  if (tid == 0) {
+    info[0] = r;
+    info[1] = sw1;
+    info[2] = sw2;
+  }
 }
 
 // out_f = beta out_f + alpha sum_b in_f[b] Y_b (+ add_f), f = blockIdx.y:
@@ -802,7 +832,7 @@ tl_status lob_layout(int L, int m0, int nb, LobLayout* t, char* ws) {
   t->off_z = take(sizeof(double) * 2 * L * t->Ev);
   t->off_f = take(sizeof(double) * 4 * L * t->Ev);
   for (int v = 0; v < kNVec; ++v) t->off_vec[v] = take(sizeof(double) * t->N * nb);
-  t->chunk_rows = (int)std::max<int64_t>(32, align_up((size_t)ceil_div(t->N, 256), 32));
+  t->chunk_rows = (int)std::max<int64_t>(32, align_up((size_t)ceil_div(t->N, 64), 32));
   t->chunks = (int)ceil_div(t->N, t->chunk_rows);
   t->off_part = take(sizeof(double) * t->chunks * 2 * kLobMaxBasis * kLobMaxBasis);
   t->off_gram = take(sizeof(double) * 2 * kLobMaxBasis * kLobMaxBasis);
@@ -885,7 +915,7 @@ class Lobpcg {
     const int vb[3] = {kX, kW, kP}, ua[3] = {kAX, kAW, kAP}, ub[3] = {kBX, kBW, kBP};
     TL_TRY(gram(vb, ua, ub, nblk));
     const size_t lds = sizeof(double) * 4 * kLobMaxBasis * kLobLd;
-    hipLaunchKernelGGL(lob_small_kernel, dim3(1), dim3(256), lds, st_,
+    hipLaunchKernelGGL(lob_small_kernel, dim3(1), dim3(kLobThreads), lds, st_,
                        (const double*)at(t_.off_gram), nblk * t_.nb, t_.nb, at(t_.off_y),
                        at(t_.off_lam), (int*)(ws_ + t_.off_sinfo));
     TL_CHECK_LAUNCH();
@@ -1070,7 +1100,9 @@ tl_status btoepl_lowest(const double* Hb, const double* Sb, int L, int m0, int n
     return TL_EINVAL;
   }
   const double lmin = sc[0], nA = sc[1], nB = sc[2];
-  const double sigma = lmin - (shift > 0.0 ? shift : 0.02 * std::max(1.0, std::fabs(lmin)));
+  // a shift close below the circulant minimum makes the preconditioner an
+  // approximate shift-and-invert that separates the clustered bottom states
+  const double sigma = lmin - (shift > 0.0 ? shift : 1e-4 * std::max(1.0, std::fabs(lmin)));
   hipLaunchKernelGGL(minv_kernel, dim3((unsigned)ceil_div(L, 64)), dim3(64), 0, st, hat, L, m0,
                      sigma, lob.at(t.off_lf), lob.at(t.off_minv), kinfo);
   TL_CHECK_LAUNCH();
