@@ -815,6 +815,8 @@ def main():
                     help="skip the lattice-sum / FFT HBM section")
     ap.add_argument("--stages-only", action="store_true",
                     help="print only the lattice-sum / FFT HBM section")
+    ap.add_argument("--toeplitz-only", action="store_true",
+                    help="print only the block-Toeplitz product and lowest-eigenpair sections")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -835,6 +837,10 @@ def main():
 
     if args.stages_only:
         print(json.dumps({"stage_rooflines": stage_section()}))
+        return
+    if args.toeplitz_only:
+        print(json.dumps({"toeplitz": toeplitz_section(min(args.steps, 20)),
+                          "toeplitz_lowest": toeplitz_lowest_section()}))
         return
 
     from paper_1408_3839_amd import workloads
