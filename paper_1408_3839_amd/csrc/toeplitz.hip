@@ -208,8 +208,9 @@ tl_status matvec(const ToeplitzLayout& t, char* ws, const double* X, double* Y,
 //     the same blocks, Lemma 2.2), shifted below the circulant pencil's
 //     lowest eigenvalue and inverted through the block DFT over L cells:
 //     W = F^-1 diag_j (Hhat_j - sigma Shat_j)^-1 F R;
-//   * W is made T_S-orthogonal to X before its products are taken; the basis
-//     [X, W, P] is orthonormalised in the T_S metric by SVQB (Stathopoulos
+//   * W is made T_S-orthogonal to X before its products are taken, and P
+//     (with T_H P, T_S P) after; X itself is T_S-orthonormal, so only [W, P]
+//     is orthonormalised in the T_S metric, by SVQB (Stathopoulos
 //     and Wu, SIAM J. Sci. Comput. 23 (2002)): columns scaled to unit norm,
 //     the Gram matrix diagonalised, directions with eigenvalue below 1e-8 of
 //     the largest dropped (T_S-products of nearly dependent directions carry
@@ -594,20 +595,24 @@ __device__ void jacobi_lds(double (*A)[kLobLd], double (*V)[kLobLd], int n, doub
 }
 
 // Rayleigh-Ritz on the basis of n columns: gram[0] = V^T T_H V, gram[1] =
-// V^T T_S V.  SVQB of gram[1], then the lowest nb eigenpairs of the projected
-// T_H.  Out: Y (n x nb, row stride nb) with X_new = V Y, lam (nb, ascending),
-// info[0] = kept rank r (r < nb: failure).
-__global__ __launch_bounds__(kLobThreads) void lob_small_kernel(const double* gram, int n, int nb,
-                                                        double* Y, double* lam, int* info) {
+// V^T T_S V, the first nfix columns already T_S-orthonormal and T_S-orthogonal
+// to the rest.  SVQB of the trailing n - nfix columns, then the lowest nb
+// eigenpairs of the projected T_H.  Out: Y (n x nb, row stride nb) with
+// X_new = V Y, lam (nb, ascending), info = {kept rank r (r < nb: failure),
+// Jacobi sweeps of the two solves}.
+__global__ __launch_bounds__(kLobThreads) void lob_small_kernel(const double* gram, int n,
+                                                                int nfix, int nb, double* Y,
+                                                                double* lam, int* info) {
   extern __shared__ double lds[];
   double(*GA)[kLobLd] = (double(*)[kLobLd])lds;
   double(*GB)[kLobLd] = GA + kLobMaxBasis;
   double(*Q)[kLobLd] = GB + kLobMaxBasis;
   double(*T)[kLobLd] = Q + kLobMaxBasis;
   __shared__ double D[kLobMaxBasis], th[kLobMaxBasis], rot[4 * kLobMaxBasis / 2], red[32];
-  __shared__ int keep_idx[kLobMaxBasis], perm[kLobMaxBasis];
+  __shared__ int inv_idx[kLobMaxBasis], perm[kLobMaxBasis];
   __shared__ int r_sh, rotated, sw1, sw2;
   const int tid = threadIdx.x;
+  const int m = n - nfix;  // columns orthonormalised here
   const double* gA = gram;
   const double* gB = gram + kLobMaxBasis * kLobMaxBasis;
   for (int e = tid; e < n * n; e += blockDim.x) {
@@ -616,36 +621,42 @@ __global__ __launch_bounds__(kLobThreads) void lob_small_kernel(const double* gr
     GB[i][j] = 0.5 * (gB[i * kLobMaxBasis + j] + gB[j * kLobMaxBasis + i]);
   }
   __syncthreads();
-  if (tid < n) D[tid] = GB[tid][tid] > 0.0 ? 1.0 / sqrt(GB[tid][tid]) : 0.0;
-  __syncthreads();
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e - i * n;
-    T[i][j] = D[i] * GB[i][j] * D[j];
+  if (tid < m) {
+    const double g = GB[nfix + tid][nfix + tid];
+    D[tid] = g > 0.0 ? 1.0 / sqrt(g) : 0.0;
   }
   __syncthreads();
-  jacobi_lds(T, Q, n, rot, red, &rotated, &sw1);
-  if (tid < n) th[tid] = T[tid][tid];
+  for (int e = tid; e < m * m; e += blockDim.x) {
+    const int i = e / m, j = e - i * m;
+    T[i][j] = D[i] * GB[nfix + i][nfix + j] * D[j];
+  }
+  __syncthreads();
+  jacobi_lds(T, Q, m, rot, red, &rotated, &sw1);
+  if (tid < m) th[tid] = T[tid][tid];
   __syncthreads();
   double tmax = 0.0;
-  for (int i = 0; i < n; ++i) tmax = fmax(tmax, th[i]);
-  if (tid < n) {
-    int pos = 0;
-    const bool kp = th[tid] > kLobDrop * tmax;
-    for (int i = 0; i < tid; ++i) pos += th[i] > kLobDrop * tmax;
-    keep_idx[tid] = kp ? pos : -1;
-  }
+  for (int i = 0; i < m; ++i) tmax = fmax(tmax, th[i]);
   if (tid == 0) {
-    int r = 0;
-    for (int i = 0; i < n; ++i) r += th[i] > kLobDrop * tmax;
-    r_sh = r;
+    int c = 0;
+    for (int k = 0; k < m; ++k)
+      if (th[k] > kLobDrop * tmax) inv_idx[c++] = k;  // kept column c <- eigenvector k
+    r_sh = nfix + c;
   }
   __syncthreads();
   const int r = r_sh;
-  // M = D Q_keep theta^-1/2 (n x r) into T
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    const int i = e / n, k = e - i * n;
-    const int c = keep_idx[k];
-    if (c >= 0) T[i][c] = D[i] * Q[i][k] / sqrt(th[k]);
+  // M (n x r) into T: identity on the first nfix columns, D Q_keep theta^-1/2 below
+  for (int e = tid; e < n * r; e += blockDim.x) {
+    const int i = e / r, c = e - i * r;
+    double v;
+    if (i < nfix)
+      v = c == i ? 1.0 : 0.0;
+    else if (c < nfix)
+      v = 0.0;
+    else {
+      const int k = inv_idx[c - nfix];
+      v = D[i - nfix] * Q[i - nfix][k] / sqrt(th[k]);
+    }
+    T[i][c] = v;
   }
   __syncthreads();
   // Q = GA M (n x r)
@@ -915,8 +926,10 @@ class Lobpcg {
     const int vb[3] = {kX, kW, kP}, ua[3] = {kAX, kAW, kAP}, ub[3] = {kBX, kBW, kBP};
     TL_TRY(gram(vb, ua, ub, nblk));
     const size_t lds = sizeof(double) * 4 * kLobMaxBasis * kLobLd;
+    // X is T_S-orthonormal after the first step, and W and P are projected off it
+    const int nfix = nblk > 1 ? t_.nb : 0;
     hipLaunchKernelGGL(lob_small_kernel, dim3(1), dim3(kLobThreads), lds, st_,
-                       (const double*)at(t_.off_gram), nblk * t_.nb, t_.nb, at(t_.off_y),
+                       (const double*)at(t_.off_gram), nblk * t_.nb, nfix, t_.nb, at(t_.off_y),
                        at(t_.off_lam), (int*)(ws_ + t_.off_sinfo));
     TL_CHECK_LAUNCH();
     int si[4];
@@ -959,6 +972,23 @@ class Lobpcg {
       if (nblk > 1) std::swap(cur_[ps[f]], cur_[p2[f]]);
     }
     return TL_OK;
+  }
+  // P <- P - X (BX^T P), with T_H P and T_S P alike
+  tl_status project_p() {
+    const int vb[1] = {kBX}, ub[1] = {kP};
+    TL_TRY(gram(vb, ub, nullptr, 1));
+    TsArgs a = base();
+    const int xs[3] = {kX, kAX, kBX}, ps[3] = {kP, kAP, kBP};
+    for (int f = 0; f < 3; ++f) {
+      a.in[f][0] = v(xs[f]);
+      a.out[f] = v(ps[f]);
+    }
+    a.Y[0] = at(t_.off_gram);
+    a.ldy = kLobMaxBasis;
+    a.nin = 1;
+    a.alpha = -1.0;
+    a.beta = 1.0;
+    return launch_ts(a);
   }
   // W <- W - X (BX^T W)
   tl_status project_w() {
@@ -1162,6 +1192,7 @@ tl_status btoepl_lowest(const double* Hb, const double* Sb, int L, int m0, int n
     TL_TRY(lob.precondition());
     TL_TRY(lob.project_w());
     TL_TRY(lob.products(kW, kAW, kBW));
+    if (nblk == 3) TL_TRY(lob.project_p());
     TL_TRY(lob.rayleigh_ritz(nblk));
     TL_TRY(lob.update(nblk));
     nblk = 3;
