@@ -375,9 +375,10 @@ tl_status tl_btoepl_power(int L, int m0, int iters, double* x_dev, double* y_dev
  *   max_iter: iteration limit; tol: relative residual target
  *     |T_H x - lambda T_S x| / ((|T_H| + |lambda| |T_S|) |x|), the norms
  *     bounded by the sums over k of the largest row and column sums of |A_k|.
- *   shift: sigma below the circulant minimum (<= 0: 1e-4 max(1, |lambda_min|),
- *     suited to long chains whose circulant is close to the pencil; a short
- *     or strongly non-periodic pencil may need a larger shift).
+ *   shift: sigma below the circulant minimum; <= 0 takes the larger of
+ *     1e-4 max(1, |lambda_min|) and 10 times the estimated finite-size offset
+ *     of the pencil's lowest eigenvalue (a quarter of the gap between the two
+ *     smallest k-block minima).
  *   x0_dev (nullable): start block [L m0][nb]; NULL draws it from a fixed seed.
  *   evals_dev: nev doubles, ascending; evecs_dev (nullable): [L][m0][nev],
  *     T_S-normalised; resid_dev (nullable): the nev relative residuals,

@@ -254,33 +254,50 @@ __global__ __launch_bounds__(256) void strang_kernel(StrangArgs a) {
   a.out[idx] = v;
 }
 
-// scal[0] = lowest eigenvalue over the k-blocks, scal[3] = 1 if a block
-// failed (not definite or not converged).
+// scal[0] = lowest eigenvalue over the k-blocks, scal[4] = the second
+// smallest of the blocks' lowest eigenvalues, scal[3] = 1 if a block failed
+// (not definite or not converged).
 __global__ __launch_bounds__(256) void lmin_kernel(const double* evals, const int* info, int L,
                                                    int m0, double* scal) {
-  __shared__ double red[4];
-  __shared__ int bad[4];
-  double v = INFINITY;
+  __shared__ double lo1[256], lo2[256];
+  __shared__ int bad[256];
+  double a1 = INFINITY, a2 = INFINITY;  // smallest and second smallest block minimum
   int b = 0;
   for (int j = threadIdx.x; j < L; j += blockDim.x) {
     if (info[j] != 0) b = 1;
+    double v = INFINITY;
     for (int i = 0; i < m0; ++i) {
       const double e = evals[(int64_t)j * m0 + i];
       if (e != e) b = 1;
       else v = fmin(v, e);
     }
+    if (v < a1) {
+      a2 = a1;
+      a1 = v;
+    } else {
+      a2 = fmin(a2, v);
+    }
   }
-  v = wave_min_dpp(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int any = __any(b) ? 1 : 0;
-  if (lane == 0) {
-    red[wave] = v;
-    bad[wave] = any;
-  }
+  lo1[threadIdx.x] = a1;
+  lo2[threadIdx.x] = a2;
+  bad[threadIdx.x] = b;
   __syncthreads();
   if (threadIdx.x == 0) {
-    scal[0] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
-    scal[3] = (bad[0] | bad[1] | bad[2] | bad[3]) ? 1.0 : 0.0;
+    double m1 = INFINITY, m2 = INFINITY;
+    int any = 0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+      any |= bad[t];
+      const double c1 = lo1[t], c2 = lo2[t];
+      if (c1 < m1) {
+        m2 = fmin(m1, c2);
+        m1 = c1;
+      } else {
+        m2 = fmin(m2, c1);
+      }
+    }
+    scal[0] = m1;
+    scal[4] = m2;
+    scal[3] = any ? 1.0 : 0.0;
   }
 }
 
@@ -851,7 +868,7 @@ tl_status lob_layout(int L, int m0, int nb, LobLayout* t, char* ws) {
   t->off_lam = take(sizeof(double) * kLobMaxNb);
   t->off_sinfo = take(sizeof(int) * 4);
   t->off_norms = take(sizeof(double) * 2 * kLobMaxNb);
-  t->off_scal = take(sizeof(double) * 4);
+  t->off_scal = take(sizeof(double) * 8);
   t->off_mask = take(sizeof(double) * kLobMaxNb);
   t->off_lambest = take(sizeof(double) * kLobMaxNb);
   const int Ls[3] = {L, 1, 1};
@@ -1123,7 +1140,7 @@ tl_status btoepl_lowest(const double* Hb, const double* Sb, int L, int m0, int n
   TL_CHECK_LAUNCH();
   hipLaunchKernelGGL(tnorm_kernel, dim3(1), dim3(256), 0, st, Hb, Sb, L, m0, scal);
   TL_CHECK_LAUNCH();
-  double sc[4];
+  double sc[8];
   TL_TRY(lob_read(scal, sc, sizeof(sc), st));
   if (sc[3] != 0.0) {
     set_error("a k-block of the circulant preconditioner is not definite");
@@ -1131,8 +1148,14 @@ tl_status btoepl_lowest(const double* Hb, const double* Sb, int L, int m0, int n
   }
   const double lmin = sc[0], nA = sc[1], nB = sc[2];
   // a shift close below the circulant minimum makes the preconditioner an
-  // approximate shift-and-invert that separates the clustered bottom states
-  const double sigma = lmin - (shift > 0.0 ? shift : 1e-4 * std::max(1.0, std::fabs(lmin)));
+  // approximate shift-and-invert that separates the clustered bottom states;
+  // it stays 10 times above the finite-size offset of the pencil's lowest
+  // eigenvalue from the circulant minimum, estimated as a quarter of the gap
+  // to the next k-block minimum (a band minimum is quadratic in k)
+  const double fin = std::isfinite(sc[4]) ? 0.25 * (sc[4] - lmin) : 0.0;
+  const double delta = shift > 0.0 ? shift
+                                   : std::max(1e-4 * std::max(1.0, std::fabs(lmin)), 10.0 * fin);
+  const double sigma = lmin - delta;
   hipLaunchKernelGGL(minv_kernel, dim3((unsigned)ceil_div(L, 64)), dim3(64), 0, st, hat, L, m0,
                      sigma, lob.at(t.off_lf), lob.at(t.off_minv), kinfo);
   TL_CHECK_LAUNCH();

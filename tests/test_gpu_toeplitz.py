@@ -202,10 +202,12 @@ def test_btoepl_lowest_chain(L):
     _check_pairs(Hb, Sb, lam, U, 1e-9, f"chain L={L}")
 
 
-def test_btoepl_lowest_random_pencil():
+@pytest.mark.parametrize("shift", [0.0, 0.03], ids=["default_shift", "shift0.03"])
+def test_btoepl_lowest_random_pencil(shift):
     """Random banded pencil, L = 61 (prime: Bluestein transforms of lengths
-    L and 2L), m0 = 3, T_S diagonally dominant.  A short pencil far from its
-    circulant: the shift is given (0.03 below the circulant minimum)."""
+    L and 2L), m0 = 3, T_S diagonally dominant: a short pencil far from its
+    circulant, with the default shift (set from the finite-size offset) and
+    a given one."""
     rng = np.random.default_rng(61)
     L, m0 = 61, 3
     Hb = np.zeros((L, m0, m0))
@@ -217,7 +219,7 @@ def test_btoepl_lowest_random_pencil():
     for k, (hs, ss) in enumerate([(0.5, 0.05), (0.2, 0.01)], start=1):
         Hb[k] = hs * rng.standard_normal((m0, m0))
         Sb[k] = ss * rng.standard_normal((m0, m0))
-    it, nc, lam, U, res = _lowest(Hb, Sb, 4, 6, tol=1e-11, shift=0.03)
+    it, nc, lam, U, res = _lowest(Hb, Sb, 4, 6, tol=1e-11, shift=shift)
     print(f"\nrandom pencil: {it} iterations, {nc} converged")
     assert nc == 4
     _check_pairs(Hb, Sb, lam, U, 1e-11, "random L=61")
