@@ -280,3 +280,20 @@ def test_btoepl_matvec_graph_replay():
         assert np.array_equal(got, Yd.cpu().numpy()), rep
         Yr = (T @ X.reshape(L * m0, nvec)).reshape(L, m0, nvec)
         assert np.abs(got - Yr).max() <= 1e-13 * np.abs(T).sum(axis=1).max() * np.abs(X).max()
+
+
+@pytest.mark.parametrize("case", [(40, 2, 1, 1), (64, 4, 4, 4), (5, 3, 2, 4), (33, 4, 3, 7)],
+                         ids=["nb1", "no_guard", "tiny_L5", "odd_L33"])
+def test_btoepl_lowest_edge_sizes(case):
+    """Block of one vector, no guard vectors, a 5-cell pencil whose basis of
+    3 nb columns nearly fills the space, and an odd chain length (Bluestein
+    transforms): lowest pairs of the s-chain pencil (m0 = 4 or its leading
+    2 x 2 / 3 x 3 sub-blocks) against the oracle."""
+    L, m0, nev, nb = case
+    Hb, Sb = _chain_pencil(L)
+    Hb = np.ascontiguousarray(Hb[:, :m0, :m0])
+    Sb = np.ascontiguousarray(Sb[:, :m0, :m0])
+    it, nc, lam, U, res = _lowest(Hb, Sb, nev, nb, max_iter=400, tol=1e-9)
+    print(f"\n{case}: {it} iterations, {nc} converged, residuals {res.max():.2e}")
+    assert nc == nev
+    _check_pairs(Hb, Sb, lam, U, 1e-9, f"edge {case}")
