@@ -426,6 +426,33 @@ def bloch_vectors(u: np.ndarray, L: Sequence[int], states: Sequence[int]) -> np.
     return out
 
 
+def bloch_orbital(sys, U: np.ndarray, nodes: Sequence[Sequence[int]]) -> np.ndarray:
+    """Values of the orbital with full-lattice coefficients U ([L1 L2 L3 m0],
+    e.g. a row of bloch_vectors) at grid nodes (i0, i1, i2):
+      psi(x_i) = sum_c sum_mu U[c][mu] prod_d g_mu^d(x_(i_d) - c_d a_d),
+    the Galerkin expansion over the replicated basis (eq. (eigvecA) for the
+    coefficients, Sec. 3.4 for the nodal samples); on a torus the shifted
+    periodised sample of cell 0 is read c_d * cell_nodes_d nodes back."""
+    L = [int(v) for v in sys.L]
+    m0 = sys.m0
+    G = [cell0_basis(sys, d) for d in range(3)]
+    cn = [int(sys.n[d]) // L[d] for d in range(3)]
+    out = np.zeros(len(nodes), dtype=np.complex128)
+    for r, node in enumerate(nodes):
+        v = 0.0 + 0.0j
+        for c1 in range(L[0]):
+            for c2 in range(L[1]):
+                for c3 in range(L[2]):
+                    c = (c1 * L[1] + c2) * L[2] + c3
+                    for mu in range(m0):
+                        g = 1.0
+                        for d, cd in enumerate((c1, c2, c3)):
+                            g *= G[d][mu][(int(node[d]) - cd * cn[d]) % int(sys.n[d])]
+                        v += U[c * m0 + mu] * g
+        out[r] = v
+    return out
+
+
 def lowest_generalized_eigs(H: np.ndarray, S: np.ndarray, k: int):
     """Lowest k eigenpairs of the symmetric-definite pencil (H, S)."""
     w, v = sla.eigh(H, S, subset_by_index=[0, k - 1])

@@ -359,6 +359,38 @@ def test_bloch_vectors_are_eigenvectors_of_the_full_pencil(L):
     np.testing.assert_allclose(U[cf * m0:(cf + 1) * m0, jf * m0], ph * u[jf][:, 0], atol=1e-14)
 
 
+@pytest.mark.parametrize("L", [(4, 1, 1), (3, 2, 2)])
+def test_bloch_orbital_values(L):
+    """The orbital of a Bloch state on the grid: equal to the expansion over
+    every cell's explicitly sampled functions (functions sampled at shifted
+    centres, not by rolling cell 0's samples), and of unit FEM norm,
+    psi^H (S_1 x S_2 x S_3) psi = U^H S U = 1, for S-normalised k-block
+    eigenvectors (Sec. 3.4: S is the FEM mass of the sampled functions)."""
+    s = wl.tiny_periodic(L=L, m0=3 if np.prod(L) < 10 else 2, c=6, h=0.3, R=8,
+                         alpha_range=(0.25, 2.0))
+    H, S, _ = oracle.core_hamiltonian_blocks(s)
+    Hb, Sb = oracle.block_dft(H), oracle.block_dft(S)
+    m0, nc = s.m0, int(np.prod(L))
+    u = np.zeros((nc, m0, m0), complex)
+    for j in range(nc):
+        _, u[j] = sla.eigh(Hb.reshape(nc, m0, m0)[j], Sb.reshape(nc, m0, m0)[j])
+    states = [0, m0 + 1, nc * m0 - 1]
+    U = oracle.bloch_vectors(u, L, states)
+    n = [int(v) for v in s.n]
+    nodes = list(np.ndindex(*n))
+    from oracle import core as oc
+    X = [oc._all_function_samples(s, d, oc.cell_origins(s)) for d in range(3)]
+    for r in range(len(states)):
+        psi = oracle.bloch_orbital(s, U[r], nodes).reshape(n)
+        ref = np.einsum("f,fa,fb,fc->abc", U[r], X[0], X[1], X[2])
+        assert np.abs(psi - ref).max() <= 1e-12 * np.abs(ref).max()
+        Spsi = psi
+        for d in range(3):
+            Spsi = np.moveaxis(oracle.fem_mass(np.moveaxis(Spsi, d, -1), bool(s.periodic[d]),
+                                               s.h), -1, d)
+        assert abs(np.vdot(psi, Spsi) - 1.0) < 1e-9
+
+
 def test_full_matrix_scales():
     """The entry scales of the explicit full matrices: on a torus they equal
     the block-circulant matrix of the shift-structured scales (two separate
