@@ -448,7 +448,69 @@ def spectra_section():
             "energy_per_cell_box_Ha": energy_per_cell(ev_b, L),
         }
         del pl, bp
+    out["orbitals"] = orbital_section()
     return out
+
+
+def orbital_section():
+    """Orbitals 4 and 8 (ascending energy over all k-points) of the periodic
+    (128,1,1) chain as rank-m0 canonical tensors on the 2048 x 128 x 128 grid:
+    factor time, FEM norm from the factors, sign changes of Re psi along the
+    chain axis through the transverse centre, and the storage against the
+    full grid."""
+    import torch
+    from paper_1408_3839_amd import workloads
+    from paper_1408_3839_amd.pipeline import PeriodicPipeline
+    L = 128
+    per = workloads.periodic_system(f"chain{L}", [L, 1, 1], [2.0, 0, 0], 0.125,
+                                    [0, 16.0, 16.0], [[0, 0, 0]], [1.0], 4, (0.1, 20.0), 20,
+                                    seed=1)
+    pl = PeriodicPipeline(per, with_evecs=True)
+    pl.run()
+    torch.cuda.synchronize()
+    ev = pl.evals.cpu().numpy().ravel()
+    order = np.argsort(ev, kind="stable")
+    states = [int(order[3]), int(order[7])]
+    pl.orbital_factors(states)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    coef, fac = pl.orbital_factors(states)
+    b.record(stream)
+    torch.cuda.synchronize()
+    m0 = per.m0
+    n = [int(v) for v in per.n]
+    w = coef.cpu().numpy()
+    w = w[..., 0] + 1j * w[..., 1]
+    F = fac.cpu().numpy()
+    F = F[..., 0] + 1j * F[..., 1]
+    offs = np.cumsum([0] + [m0 * n[d] for d in range(3)])
+
+    def fem_mass(f, periodic):  # (h/6) tridiag(1, 4, 1), circulant on a torus
+        lft, rgt = np.roll(f, 1, axis=-1), np.roll(f, -1, axis=-1)
+        if not periodic:
+            lft[..., 0] = 0.0
+            rgt[..., -1] = 0.0
+        return (4.0 * f + lft + rgt) * (per.h / 6.0)
+    res = {"workload": "periodic (128,1,1) chain, a=2.0 bohr, Z=1, m0=4 s; grid 2048x128x128",
+           "factor_kernel_ms": a.elapsed_time(b)}
+    for r, label in enumerate(("orbital_4", "orbital_8")):
+        phi = [F[r, offs[d]:offs[d + 1]].reshape(m0, n[d]) for d in range(3)]
+        gram = np.ones((m0, m0), complex)
+        for d in range(3):
+            gram *= phi[d].conj() @ fem_mass(phi[d], bool(per.periodic[d])).T
+        line = (w[r][:, None] * phi[0] * phi[1][:, n[1] // 2][:, None]
+                * phi[2][:, n[2] // 2][:, None]).sum(axis=0)
+        re = line.real if np.abs(line.real).max() >= np.abs(line.imag).max() else line.imag
+        big = re[np.abs(re) > 1e-6 * np.abs(re).max()]
+        res[label] = {"state": states[r], "energy_Ha": float(ev[states[r]]),
+                      "fem_norm_minus_1": float(abs(np.vdot(w[r], gram @ w[r]) - 1.0)),
+                      "x_line_sign_changes": int(np.sum(np.sign(big[1:]) != np.sign(big[:-1])))}
+    res["canonical_storage_complex"] = int(m0 * (1 + sum(n)))
+    res["full_grid_complex"] = int(np.prod(n))
+    del pl
+    return res
 
 
 def _btoepl_dense(A):

@@ -327,6 +327,25 @@ tl_status tl_bloch_vectors(const double* evecs_dev, int L1, int L2, int L3, int 
                            const int* states_dev, int n_states, double* out_dev, void* stream);
 
 /*
+ * tl_bloch_orbital_factors - the orbital of a Bloch state on the grid as a
+ * canonical tensor of rank m0 (eq. (eigvecA) with the separable basis of
+ * Sec. 3.4): psi(x) = sum_mu w_mu prod_d phi^d_mu(x_d), with
+ *   w_mu = L^(-1/2) u_(j,m)[mu],
+ *   phi^d_mu(x_i) = sum_(c=0)^(L_d-1) exp(2 pi i j_d c / L_d) g^d_mu(x_i - c a_d)
+ * (the periodised samples of tl_build_basis read c * cell_nodes_d nodes back
+ * on the torus; an open dim has phi = g).  Periodic systems only.
+ *   G_dev: the basis samples of tl_build_basis (basis_elems doubles).
+ *   evecs_dev, states_dev: as for tl_bloch_vectors.
+ *   coef_dev: [n_states][m0] complex; factors_dev: [n_states][basis_elems]
+ *   complex, dim d at offset basis_off(d) = sum_(e<d) m0 n_e, row mu of n_d.
+ *   An index outside [0, L m0) yields NaN.
+ * Errors: TL_EINVAL (system, null array), TL_EUNSUPPORTED (box mode).
+ */
+tl_status tl_bloch_orbital_factors(const tl_system* sys, const double* G_dev,
+                                   const double* evecs_dev, const int* states_dev, int n_states,
+                                   double* coef_dev, double* factors_dev, void* stream);
+
+/*
  * Symmetric block-Toeplitz matrices (Sec. 2, Definition of the block
  * Toeplitz class; Appendix eq. (block_SToepl)), as the open chain's matrices
  * are up to a boundary defect (Sec. 3.3): A = BToepl_s{A_0..A_{L-1}}, block

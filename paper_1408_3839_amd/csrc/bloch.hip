@@ -52,8 +52,111 @@ __global__ __launch_bounds__(256) void bloch_kernel(BlochArgs a) {
   o[1] = rs * (cs * u[1] + sn * u[0]);
 }
 
+// The orbital of state (j, m) on the grid is a canonical tensor of rank m0
+// (the basis is separable and the Bloch phase factorises over the dims):
+//   psi(x) = sum_mu w_mu prod_d phi^d_mu(x_d),  w_mu = L^(-1/2) u_(j,m)[mu],
+//   phi^d_mu(x_i) = sum_(c=0)^(L_d - 1) exp(2 pi i j_d c / L_d) g^d_mu(x_i - c a_d),
+// the shifted periodised sample read c * cell_nodes_d nodes back on the torus
+// (an open dim has L_d = 1: phi = g).
+struct OrbArgs {
+  const double* G;      // basis samples, dim d at off[d]: [m0][n_d]
+  const double* evecs;  // [nc][m0][m0] complex, column m = eigenvector m
+  const int* states;    // [n] flat state indices j m0 + m
+  double* coef;         // [n][m0] complex
+  double* fac;          // [n][elems] complex, dims as in G
+  int L[3], cn[3], n[3], m0, ns;
+  int64_t off[3], elems;
+};
+
+__global__ __launch_bounds__(256) void orbital_factors_kernel(OrbArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)a.ns * a.elems) return;
+  const int s = (int)(e / a.elems);
+  const int64_t r = e - (int64_t)s * a.elems;
+  const int d = r >= a.off[2] ? 2 : (r >= a.off[1] ? 1 : 0);
+  const int64_t rr = r - a.off[d];
+  const int mu = (int)(rr / a.n[d]);
+  const int i = (int)(rr - (int64_t)mu * a.n[d]);
+  const int nc = a.L[0] * a.L[1] * a.L[2];
+  const int st = a.states[s];
+  double* o = a.fac + 2 * e;
+  const bool ok = st >= 0 && st < nc * a.m0;
+  if (!ok) {
+    o[0] = NAN;
+    o[1] = NAN;
+    if (d == 0 && i == 0) {
+      a.coef[2 * ((int64_t)s * a.m0 + mu)] = NAN;
+      a.coef[2 * ((int64_t)s * a.m0 + mu) + 1] = NAN;
+    }
+    return;
+  }
+  const int j = st / a.m0, m = st - j * a.m0;
+  const int j12 = j / a.L[2], j3 = j - j12 * a.L[2];
+  const int j1 = j12 / a.L[1], j2 = j12 - j1 * a.L[1];
+  const int jd = d == 0 ? j1 : (d == 1 ? j2 : j3);
+  const int Ld = a.L[d], nd = a.n[d];
+  const double* g = a.G + a.off[d] + (int64_t)mu * nd;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < Ld; ++c) {
+    int src = i - (int)(((int64_t)c * a.cn[d]) % nd);
+    if (src < 0) src += nd;
+    const double v = g[src];
+    if (v == 0.0) continue;
+    double sn, cs;
+    sincospi(2.0 * (double)((int64_t)jd * c % Ld) / Ld, &sn, &cs);
+    re = fma(cs, v, re);
+    im = fma(sn, v, im);
+  }
+  o[0] = re;
+  o[1] = im;
+  if (d == 0 && i == 0) {
+    const double rs = 1.0 / sqrt((double)nc);
+    const double* u = a.evecs + 2 * (((int64_t)j * a.m0 + mu) * a.m0 + m);
+    a.coef[2 * ((int64_t)s * a.m0 + mu)] = rs * u[0];
+    a.coef[2 * ((int64_t)s * a.m0 + mu) + 1] = rs * u[1];
+  }
+}
+
 }  // namespace
 }  // namespace tl
+
+extern "C" tl_status tl_bloch_orbital_factors(const tl_system* sys, const double* G_dev,
+                                              const double* evecs_dev, const int* states_dev,
+                                              int n_states, double* coef_dev,
+                                              double* factors_dev, void* stream) {
+  tl::clear_error();
+  tl::Geometry g;
+  TL_TRY(tl::digest(sys, &g));
+  if (g.mode != TL_MODE_PERIODIC) {
+    tl::set_error("orbital factors of Bloch states need a periodic system");
+    return TL_EUNSUPPORTED;
+  }
+  TL_REQUIRE(n_states >= 0, "n_states = %d < 0", n_states);
+  if (n_states == 0) return TL_OK;
+  TL_REQUIRE(G_dev && evecs_dev && states_dev && coef_dev && factors_dev, "null array argument");
+  tl::OrbArgs a;
+  a.G = G_dev;
+  a.evecs = evecs_dev;
+  a.states = states_dev;
+  a.coef = coef_dev;
+  a.fac = factors_dev;
+  for (int d = 0; d < 3; ++d) {
+    a.L[d] = g.L[d];
+    a.n[d] = g.n[d];
+    a.cn[d] = g.L[d] > 1 ? g.cell_nodes[d] : 0;
+    a.off[d] = g.basis_off[d];
+  }
+  a.m0 = g.m0;
+  a.ns = n_states;
+  a.elems = g.basis_elems;
+  const int64_t total = (int64_t)n_states * a.elems;
+  TL_REQUIRE(tl::ceil_div(total, 256) <= INT32_MAX, "output of %lld values too large",
+             (long long)total);
+  hipLaunchKernelGGL(tl::orbital_factors_kernel, dim3((unsigned)tl::ceil_div(total, 256)),
+                     dim3(256), 0, (hipStream_t)stream, a);
+  TL_CHECK_LAUNCH();
+  return TL_OK;
+}
 
 extern "C" tl_status tl_bloch_vectors(const double* evecs_dev, int L1, int L2, int L3, int m0,
                                       const int* states_dev, int n_states, double* out_dev,

@@ -102,6 +102,20 @@ class PeriodicPipeline:
         tl.tl_bloch_vectors(self.evecs, L[0], L[1], L[2], self.m0, st, st.numel(), out, stream)
         return out
 
+    def orbital_factors(self, states, stream=None):
+        """Rank-m0 canonical form of the orbitals of the given flat states on
+        the grid (needs with_evecs and the basis samples):
+        (coef [n][m0][2], factors [n][basis_elems][2]), dim d of the factors
+        at offset sum_(e<d) m0 n_e."""
+        if self.evecs is None:
+            raise ValueError("orbital_factors needs a pipeline built with with_evecs=True")
+        st = torch.as_tensor(states, dtype=torch.int32).to(self.device)
+        coef = torch.empty(st.numel(), self.m0, 2, dtype=torch.float64, device=self.device)
+        fac = torch.empty(st.numel(), self.G.numel(), 2, dtype=torch.float64, device=self.device)
+        tl.tl_bloch_orbital_factors(self.handle, self.G, self.evecs, st, st.numel(), coef, fac,
+                                    stream)
+        return coef, fac
+
     def basis_and_potential(self, stream=None):
         tl.tl_build_basis_and_potential(self.handle, self.G, self.AG, self.SG, self.P,
                                         self.pot_ws, self.pot_ws_bytes, stream)

@@ -127,6 +127,8 @@ SIGNATURES = {
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "tl_bloch_vectors": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 4
                          + [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "tl_bloch_orbital_factors": (ctypes.c_int, [ctypes.POINTER(TlSystem)] + [ctypes.c_void_p] * 3
+                                 + [ctypes.c_int] + [ctypes.c_void_p] * 3),
     "tl_btoepl_workspace_bytes": (ctypes.c_int, [ctypes.c_int] * 3
                                   + [ctypes.POINTER(ctypes.c_size_t)]),
     "tl_btoepl_setup": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 3
@@ -374,6 +376,13 @@ def tl_batched_heigh(H, S, count, m0, evals, evecs, info, stream=None):
 def tl_bloch_vectors(evecs, L1, L2, L3, m0, states, n_states, out, stream=None):
     _check(load().tl_bloch_vectors(_ptr(evecs), int(L1), int(L2), int(L3), int(m0), _ptr(states),
                                    int(n_states), _ptr(out), _stream(stream)), "tl_bloch_vectors")
+
+
+def tl_bloch_orbital_factors(sys, G, evecs, states, n_states, coef, factors, stream=None):
+    h = _handle(sys)
+    _check(load().tl_bloch_orbital_factors(h.ref, _ptr(G), _ptr(evecs), _ptr(states),
+                                           int(n_states), _ptr(coef), _ptr(factors),
+                                           _stream(stream)), "tl_bloch_orbital_factors")
 
 
 def tl_btoepl_workspace_bytes(L, m0, nvec) -> int:

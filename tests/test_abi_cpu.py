@@ -219,6 +219,15 @@ def test_btoepl_sizes_and_validation():
     _expect(tl.tl_btoepl_power, tl.TL_EINVAL, 16, 4, 0, 8, 8, 8, 8, 1 << 30, 0)
 
 
+def test_bloch_orbital_factors_validation():
+    box = wl.config(3)
+    _expect(lambda: tl.tl_bloch_orbital_factors(box, 8, 8, 8, 1, 8, 8, 0), tl.TL_EUNSUPPORTED)
+    per = wl.config(1)
+    _expect(lambda: tl.tl_bloch_orbital_factors(per, None, 8, 8, 1, 8, 8, 0), tl.TL_EINVAL)
+    _expect(lambda: tl.tl_bloch_orbital_factors(per, 8, 8, 8, -1, 8, 8, 0), tl.TL_EINVAL)
+    tl.tl_bloch_orbital_factors(per, None, None, None, 0, None, None, 0)  # nothing to do
+
+
 def test_btoepl_lowest_sizes_and_validation():
     b = tl.tl_btoepl_lowest_workspace_bytes(256, 4, 12)
     # two embedded operators, 15 blocks of N nb vectors, the preconditioner's k-blocks

@@ -136,3 +136,43 @@ def test_kblock_eigenvectors_c2_vs_oracle():
     print("  worst (j, m, lambda, gap, cond, lambda_min(S), angle, bound, |r|, |H|):", info)
     assert worst_res <= 1e-10
     assert n_cmp >= 400 and worst_ratio <= 2.0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_bloch_orbital_factors(name):
+    """The orbital of a Bloch state on the grid as a rank-m0 canonical tensor
+    (tl_bloch_orbital_factors): its values at sampled grid nodes against the
+    oracle's expansion over all cells of the oracle's Bloch vector of the same
+    k-block eigenvector, and its FEM norm psi^H (S_1 x S_2 x S_3) psi = 1;
+    out-of-range states give NaN."""
+    s = CASES[name]()
+    pl = _run(s)
+    L = [int(v) for v in s.L]
+    m0, nc = s.m0, int(np.prod(L))
+    states = [0, m0 + 1, nc * m0 - 1, -1, nc * m0]
+    coef, fac = pl.orbital_factors(states)
+    torch.cuda.synchronize()
+    w, F = _cx(coef), _cx(fac)
+    assert np.all(np.isnan(w[3:])) and np.all(np.isnan(F[3:]))
+    u = _cx(pl.evecs)
+    U = oracle.bloch_vectors(u, L, states[:3])
+    n = [int(v) for v in s.n]
+    offs = np.cumsum([0] + [m0 * n[d] for d in range(3)])
+    rng = np.random.default_rng(5)
+    nodes = [tuple(int(rng.integers(0, n[d])) for d in range(3)) for _ in range(150)]
+    for r in range(3):
+        phi = [F[r, offs[d]:offs[d + 1]].reshape(m0, n[d]) for d in range(3)]
+        got = np.array([np.sum(w[r] * phi[0][:, a] * phi[1][:, b] * phi[2][:, c])
+                        for a, b, c in nodes])
+        ref = oracle.bloch_orbital(s, U[r], nodes)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        # FEM norm from the factors: sum_(mu,nu) conj(w_mu) w_nu prod_d phi_mu^H S_d phi_nu
+        gram = np.ones((m0, m0), complex)
+        for d in range(3):
+            Sphi = oracle.fem_mass(phi[d], bool(s.periodic[d]), s.h)
+            gram *= phi[d].conj() @ Sphi.T
+        norm = np.vdot(w[r], gram @ w[r])
+        print(f"\n{name} state {states[r]}: max |dpsi| / max|psi| = {err:.2e}, "
+              f"FEM norm - 1 = {abs(norm - 1):.2e}")
+        assert err <= 1e-12
+        assert abs(norm - 1.0) <= 1e-9
