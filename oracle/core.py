@@ -453,6 +453,15 @@ def bloch_orbital(sys, U: np.ndarray, nodes: Sequence[Sequence[int]]) -> np.ndar
     return out
 
 
+def chain_orbital(sys, U: np.ndarray, nodes: Sequence[Sequence[int]]) -> np.ndarray:
+    """Values of the orbital with coefficients U over all N_b functions of an
+    open chain (cell-major, function-minor) at grid nodes (i0, i1, i2):
+    psi(x_i) = sum_f U[f] prod_d g_f^d(x_(i_d)), every function sampled at its
+    own centre (Sec. 3.4; the coefficients of the full eigensolver)."""
+    X = [_all_function_samples(sys, d, cell_origins(sys)) for d in range(3)]
+    return np.array([np.sum(U * X[0][:, a] * X[1][:, b] * X[2][:, c]) for a, b, c in nodes])
+
+
 def lowest_generalized_eigs(H: np.ndarray, S: np.ndarray, k: int):
     """Lowest k eigenpairs of the symmetric-definite pencil (H, S)."""
     w, v = sla.eigh(H, S, subset_by_index=[0, k - 1])

@@ -391,6 +391,39 @@ def test_bloch_orbital_values(L):
         assert abs(np.vdot(psi, Spsi) - 1.0) < 1e-9
 
 
+def test_chain_orbital_values():
+    """The open chain's orbital: at single nodes equal to the Gaussian factors
+    written out (coef (x - A)^l exp(-alpha (x - A)^2) per dim, centres at the
+    cell origins), and of unit FEM norm on the whole grid for an
+    S-normalised eigenvector of the full pencil."""
+    b = wl.box_chain_system("b3", 3, 1.5, [1.0, 2.0], 0.2, [40, 24, 24], 2, (0.4, 2.0), 10,
+                            seed=9)
+    H, S = oracle.full_matrices(b)
+    _, V = sla.eigh(H, S)
+    n = [int(v) for v in b.n]
+    origins = np.asarray(b.cell_origin)
+    nodes = list(np.ndindex(*n))
+    for col in (0, 3):
+        U = V[:, col]
+        psi = oracle.chain_orbital(b, U, nodes).reshape(n)
+        for node in [(3, 5, 7), (20, 12, 12), (39, 0, 23)]:
+            v = 0.0
+            for c in range(3):
+                for mu in range(b.m0):
+                    g = 1.0
+                    for d in range(3):
+                        x = b.x0[d] + b.h * node[d]
+                        A = origins[c][d] + b.fn_center[mu][d]
+                        g *= (b.fn_coef[mu][d] * (x - A) ** int(b.fn_l[mu][d])
+                              * np.exp(-b.fn_alpha[mu] * (x - A) ** 2))
+                    v += U[c * b.m0 + mu] * g
+            assert abs(psi[node] - v) <= 1e-13 * np.abs(psi).max()
+        Spsi = psi
+        for d in range(3):
+            Spsi = np.moveaxis(oracle.fem_mass(np.moveaxis(Spsi, d, -1), False, b.h), -1, d)
+        assert abs(np.vdot(psi, Spsi) - 1.0) < 1e-9
+
+
 def test_full_matrix_scales():
     """The entry scales of the explicit full matrices: on a torus they equal
     the block-circulant matrix of the shift-structured scales (two separate
