@@ -346,6 +346,22 @@ tl_status tl_bloch_orbital_factors(const tl_system* sys, const double* G_dev,
                                    double* coef_dev, double* factors_dev, void* stream);
 
 /*
+ * tl_chain_orbital_factors - the open chain's orbitals on the grid as
+ * canonical tensors of rank m0 (Sec. 3.4's separable basis; the transverse
+ * factors are the same for every cell): psi = sum_mu phi^x_mu x g^y_mu x g^z_mu,
+ * phi^x_mu(x_i) = sum_c U[c m0 + mu] g^x_(c,mu)(x_i).  Box systems only.
+ *   G_dev: the box-mode basis samples of tl_build_basis.
+ *   evecs_dev: n_states rows of L m0 doubles (the layout tl_dense_gen_eigh_lowest
+ *   writes, cell-major, function-minor).
+ *   factors_dev: [n_states][m0 (n0 + n1 + n2)] doubles, dim d at offset
+ *   m0 sum_(e<d) n_e, row mu of n_d.
+ * Errors: TL_EINVAL (system, null array), TL_EUNSUPPORTED (periodic mode).
+ */
+tl_status tl_chain_orbital_factors(const tl_system* sys, const double* G_dev,
+                                   const double* evecs_dev, int n_states, double* factors_dev,
+                                   void* stream);
+
+/*
  * Symmetric block-Toeplitz matrices (Sec. 2, Definition of the block
  * Toeplitz class; Appendix eq. (block_SToepl)), as the open chain's matrices
  * are up to a boundary defect (Sec. 3.3): A = BToepl_s{A_0..A_{L-1}}, block

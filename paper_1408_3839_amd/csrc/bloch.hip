@@ -117,8 +117,80 @@ __global__ __launch_bounds__(256) void orbital_factors_kernel(OrbArgs a) {
   }
 }
 
+// The open chain's orbital with coefficients U over the L m0 functions is a
+// canonical tensor of rank m0 as well (the transverse factors do not depend
+// on the cell): psi = sum_mu phi^x_mu x g^y_mu x g^z_mu with
+// phi^x_mu(x_i) = sum_c U[c m0 + mu] g^x_(c,mu)(x_i).
+struct ChainOrbArgs {
+  const double* G;      // box-mode samples: dim 0 [L m0][n0], dims 1, 2 [m0][n_d]
+  const double* U;      // [ns][L m0]
+  double* fac;          // [ns][m0 (n0 + n1 + n2)]
+  int L, m0, ns, n[3];
+  int64_t goff[3], foff[3], elems;
+};
+
+__global__ __launch_bounds__(256) void chain_orbital_kernel(ChainOrbArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)a.ns * a.elems) return;
+  const int s = (int)(e / a.elems);
+  const int64_t r = e - (int64_t)s * a.elems;
+  const int d = r >= a.foff[2] ? 2 : (r >= a.foff[1] ? 1 : 0);
+  const int64_t rr = r - a.foff[d];
+  const int mu = (int)(rr / a.n[d]);
+  const int i = (int)(rr - (int64_t)mu * a.n[d]);
+  double v;
+  if (d == 0) {
+    const double* u = a.U + (int64_t)s * a.L * a.m0;
+    v = 0.0;
+    for (int c = 0; c < a.L; ++c) {
+      const int f = c * a.m0 + mu;
+      v = fma(u[f], a.G[a.goff[0] + (int64_t)f * a.n[0] + i], v);
+    }
+  } else {
+    v = a.G[a.goff[d] + (int64_t)mu * a.n[d] + i];
+  }
+  a.fac[e] = v;
+}
+
 }  // namespace
 }  // namespace tl
+
+extern "C" tl_status tl_chain_orbital_factors(const tl_system* sys, const double* G_dev,
+                                              const double* evecs_dev, int n_states,
+                                              double* factors_dev, void* stream) {
+  tl::clear_error();
+  tl::Geometry g;
+  TL_TRY(tl::digest(sys, &g));
+  if (g.mode != TL_MODE_BOX) {
+    tl::set_error("orbital factors of an open chain need a box-mode system");
+    return TL_EUNSUPPORTED;
+  }
+  TL_REQUIRE(n_states >= 0, "n_states = %d < 0", n_states);
+  if (n_states == 0) return TL_OK;
+  TL_REQUIRE(G_dev && evecs_dev && factors_dev, "null array argument");
+  tl::ChainOrbArgs a;
+  a.G = G_dev;
+  a.U = evecs_dev;
+  a.fac = factors_dev;
+  a.L = g.L[0];
+  a.m0 = g.m0;
+  a.ns = n_states;
+  int64_t fo = 0;
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = g.n[d];
+    a.goff[d] = g.basis_off[d];
+    a.foff[d] = fo;
+    fo += (int64_t)g.m0 * g.n[d];
+  }
+  a.elems = fo;
+  const int64_t total = (int64_t)n_states * a.elems;
+  TL_REQUIRE(tl::ceil_div(total, 256) <= INT32_MAX, "output of %lld values too large",
+             (long long)total);
+  hipLaunchKernelGGL(tl::chain_orbital_kernel, dim3((unsigned)tl::ceil_div(total, 256)),
+                     dim3(256), 0, (hipStream_t)stream, a);
+  TL_CHECK_LAUNCH();
+  return TL_OK;
+}
 
 extern "C" tl_status tl_bloch_orbital_factors(const tl_system* sys, const double* G_dev,
                                               const double* evecs_dev, const int* states_dev,

@@ -276,6 +276,18 @@ class BoxPipeline:
         if self.eig is not None:
             self.eig.run(self.H, self.S, stream)
 
+    def orbital_factors(self, stream=None):
+        """Rank-m0 canonical factors of the k computed orbitals on the grid
+        (needs the eigenvectors): [k][m0 (n0 + n1 + n2)], dim d at offset
+        m0 sum_(e<d) n_e."""
+        if self.eig is None or self.eig.evecs is None:
+            raise ValueError("orbital_factors needs the eigenvectors (k > 0, with_evecs)")
+        n = [int(v) for v in self.sys.n]
+        fac = torch.empty(self.eig.k, self.sys.m0 * sum(n), dtype=torch.float64,
+                          device=self.device)
+        tl.tl_chain_orbital_factors(self.handle, self.G, self.eig.evecs, self.eig.k, fac, stream)
+        return fac
+
     def capture(self):
         """Capture one whole run() (assembly and eigensolve) into a HIP graph."""
         side = torch.cuda.Stream(device=self.device)

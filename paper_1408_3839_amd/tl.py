@@ -129,6 +129,8 @@ SIGNATURES = {
                          + [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "tl_bloch_orbital_factors": (ctypes.c_int, [ctypes.POINTER(TlSystem)] + [ctypes.c_void_p] * 3
                                  + [ctypes.c_int] + [ctypes.c_void_p] * 3),
+    "tl_chain_orbital_factors": (ctypes.c_int, [ctypes.POINTER(TlSystem)] + [ctypes.c_void_p] * 2
+                                 + [ctypes.c_int] + [ctypes.c_void_p] * 2),
     "tl_btoepl_workspace_bytes": (ctypes.c_int, [ctypes.c_int] * 3
                                   + [ctypes.POINTER(ctypes.c_size_t)]),
     "tl_btoepl_setup": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_int] * 3
@@ -383,6 +385,13 @@ def tl_bloch_orbital_factors(sys, G, evecs, states, n_states, coef, factors, str
     _check(load().tl_bloch_orbital_factors(h.ref, _ptr(G), _ptr(evecs), _ptr(states),
                                            int(n_states), _ptr(coef), _ptr(factors),
                                            _stream(stream)), "tl_bloch_orbital_factors")
+
+
+def tl_chain_orbital_factors(sys, G, evecs, n_states, factors, stream=None):
+    h = _handle(sys)
+    _check(load().tl_chain_orbital_factors(h.ref, _ptr(G), _ptr(evecs), int(n_states),
+                                           _ptr(factors), _stream(stream)),
+           "tl_chain_orbital_factors")
 
 
 def tl_btoepl_workspace_bytes(L, m0, nvec) -> int:

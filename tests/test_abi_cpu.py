@@ -226,6 +226,9 @@ def test_bloch_orbital_factors_validation():
     _expect(lambda: tl.tl_bloch_orbital_factors(per, None, 8, 8, 1, 8, 8, 0), tl.TL_EINVAL)
     _expect(lambda: tl.tl_bloch_orbital_factors(per, 8, 8, 8, -1, 8, 8, 0), tl.TL_EINVAL)
     tl.tl_bloch_orbital_factors(per, None, None, None, 0, None, None, 0)  # nothing to do
+    _expect(lambda: tl.tl_chain_orbital_factors(per, 8, 8, 1, 8, 0), tl.TL_EUNSUPPORTED)
+    _expect(lambda: tl.tl_chain_orbital_factors(box, None, 8, 1, 8, 0), tl.TL_EINVAL)
+    tl.tl_chain_orbital_factors(box, None, None, 0, None, 0)
 
 
 def test_btoepl_lowest_sizes_and_validation():

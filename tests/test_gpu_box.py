@@ -167,3 +167,38 @@ def test_box_chain_256_split_entries(mode):
           f"sampled vs oracle {eh:.3e} / {es:.3e}")
     assert dh <= 1e-12 and ds <= 1e-12
     assert eh <= 1e-12 and es <= 1e-12
+
+
+def test_chain_orbital_factors():
+    """The open chain's orbitals as rank-m0 canonical tensors
+    (tl_chain_orbital_factors): the lowest 4 orbitals of a 12-cell chain at
+    sampled grid nodes against the oracle's expansion over every function of
+    the same GPU eigenvector, and their FEM norm from the factors equal to 1
+    (the eigenvectors are S-normalised)."""
+    from paper_1408_3839_amd.pipeline import BoxPipeline
+    s = wl.box_chain_system("c12", 12, 1.8, [1.0, 3.0], 0.0625, [600, 96, 96], 8, (0.1, 30.0),
+                            16, seed=3)
+    bp = BoxPipeline(s, k=4)
+    bp.run()
+    fac = bp.orbital_factors()
+    torch.cuda.synchronize()
+    F = fac.cpu().numpy()
+    U = bp.eig.evecs.cpu().numpy()
+    m0 = s.m0
+    n = [int(v) for v in s.n]
+    offs = np.cumsum([0] + [m0 * n[d] for d in range(3)])
+    rng = np.random.default_rng(3)
+    nodes = [(int(rng.integers(200, 400)), int(rng.integers(30, 66)), int(rng.integers(30, 66)))
+             for _ in range(60)]
+    for r in range(4):
+        phi = [F[r, offs[d]:offs[d + 1]].reshape(m0, n[d]) for d in range(3)]
+        got = np.array([np.sum(phi[0][:, a] * phi[1][:, b] * phi[2][:, c]) for a, b, c in nodes])
+        ref = oracle.chain_orbital(s, U[r], nodes)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        gram = np.ones((m0, m0))
+        for d in range(3):
+            gram *= phi[d] @ oracle.fem_mass(phi[d], False, s.h).T
+        norm = gram.sum()
+        print(f"\norbital {r}: max |dpsi| / max|psi| = {err:.2e}, FEM norm - 1 = {abs(norm - 1):.2e}")
+        assert err <= 1e-12
+        assert abs(norm - 1.0) <= 1e-8
