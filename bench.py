@@ -545,6 +545,38 @@ def _supercell_blocks(a, s, Lsc):
     return A
 
 
+def _toeplitz_host_lapack(a_h, a_s, m0, nd):
+    """The same chain on 600 cells (N = 2400): LOBPCG on the GPU beside
+    LAPACK's generalized eigensolver on the host cores (scipy, explicit
+    matrices), lowest 8."""
+    import scipy.linalg as sla
+    import torch
+    from paper_1408_3839_amd import tl
+    L, nev, nb = 600, 8, 12
+    f64 = dict(dtype=torch.float64, device="cuda")
+    Hb = torch.zeros(L, m0, m0, **f64)
+    Sb = torch.zeros(L, m0, m0, **f64)
+    Hb[:nd], Sb[:nd] = a_h, a_s
+    ws_bytes = tl.tl_btoepl_lowest_workspace_bytes(L, m0, nb)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    lam = torch.empty(nev, **f64)
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    it, nc = tl.tl_btoepl_lowest(Hb, Sb, L, m0, nev, nb, 400, 1e-9, 0.0, None, lam, None, None,
+                                 ws, ws_bytes)
+    b.record(stream)
+    torch.cuda.synchronize()
+    TH = _btoepl_dense(Hb).cpu().numpy()
+    TS = _btoepl_dense(Sb).cpu().numpy()
+    t0 = time.perf_counter()
+    w = sla.eigh(TH, TS, eigvals_only=True, subset_by_index=[0, nev - 1])
+    host_s = time.perf_counter() - t0
+    return {"N": L * m0, "lobpcg_ms": a.elapsed_time(b), "iterations": it, "converged": nc,
+            "host_lapack_s": host_s, "host_cpus": os.cpu_count(),
+            "max_abs_dlambda_Ha": float(np.abs(lam.cpu().numpy() - w).max())}
+
+
 def _toeplitz_beyond_dense(a_h, a_s, m0, nd):
     """The same s-chain on 8192 cells, as 2048 supercells of 4 cells (m0 = 16,
     N = 32768: four times the dense eigensolver's largest order); residuals
@@ -631,10 +663,12 @@ def toeplitz_lowest_section():
               * torch.linalg.norm(U, dim=0))).max().item()
     del TH, TS, R, eig
     beyond = _toeplitz_beyond_dense(Hb[:nd].clone(), Sb[:nd].clone(), m0, nd)
+    host = _toeplitz_host_lapack(Hb[:nd].clone(), Sb[:nd].clone(), m0, nd)
     return {
         "workload": "infinite s-chain pencil (periodic (8,1,1) chain's generating blocks, "
                     "shifts 0..3) restricted to 1920 cells, m0=4, N=7680; lowest 16",
         "beyond_dense": beyond,
+        "host_lapack_600_cells": host,
         "block": nb, "tol": tol, "iterations": it, "converged": nc,
         "lobpcg_ms": lob_ms, "ms_per_iteration": lob_ms / max(it, 1),
         "dense_eigensolver_ms": dense_ms,
