@@ -349,6 +349,22 @@ def btoepl_full(blocks: np.ndarray) -> np.ndarray:
     return A
 
 
+def btoepl_multilevel_full(B: np.ndarray, L: Sequence[int]) -> np.ndarray:
+    """The multilevel block Toeplitz matrix over L1 x L2 x L3 cells (the
+    recursive Definition of the d-level class, without its symmetry
+    constraint): block (r, c) = B[r - c + L - 1] for cells r, c flattened as
+    [r1][r2][r3].  B: [2L1-1][2L2-1][2L3-1][m0][m0]."""
+    L1, L2, L3 = (int(v) for v in L)
+    m0 = B.shape[-1]
+    cells = [(a, b, c) for a in range(L1) for b in range(L2) for c in range(L3)]
+    A = np.zeros((len(cells) * m0, len(cells) * m0), dtype=B.dtype)
+    for i, r in enumerate(cells):
+        for j, c in enumerate(cells):
+            A[i * m0:(i + 1) * m0, j * m0:(j + 1) * m0] = \
+                B[r[0] - c[0] + L1 - 1, r[1] - c[1] + L2 - 1, r[2] - c[2] + L3 - 1]
+    return A
+
+
 def block_dft(blocks: np.ndarray) -> np.ndarray:
     """Abar_j = sum_k omega_1^(j1 k1) omega_2^(j2 k2) omega_3^(j3 k3) A_k with
     omega_l = exp(-2 pi i / L_l), by explicit O(|L|^2) sums (Proposition on

@@ -424,6 +424,28 @@ def test_chain_orbital_values():
         assert abs(np.vdot(psi, Spsi) - 1.0) < 1e-9
 
 
+def test_btoepl_multilevel_full():
+    """The multilevel block Toeplitz matrix: on one level it is the symmetric
+    one-level matrix of eq. (block_SToepl) when B(-d) = A_d^T; with separable
+    blocks B(d) = t1[d1] t2[d2] t3[d3] M it is kron(T1, T2, T3, M) for the
+    scalar Toeplitz matrices T_l (scipy.linalg.toeplitz)."""
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((5, 2, 2))
+    A[0] = A[0] + A[0].T
+    B = np.zeros((9, 1, 1, 2, 2))
+    for d in range(-4, 5):
+        B[d + 4, 0, 0] = A[d] if d >= 0 else A[-d].T
+    np.testing.assert_array_equal(oracle.btoepl_multilevel_full(B, (5, 1, 1)),
+                                  oracle.btoepl_full(A))
+    L = (3, 4, 2)
+    t = [rng.standard_normal(2 * n - 1) for n in L]
+    M = rng.standard_normal((2, 2))
+    B = np.einsum("a,b,c,ij->abcij", t[0], t[1], t[2], M)
+    T = [sla.toeplitz(t[d][L[d] - 1:], t[d][L[d] - 1::-1]) for d in range(3)]
+    np.testing.assert_allclose(oracle.btoepl_multilevel_full(B, L),
+                               np.kron(np.kron(np.kron(T[0], T[1]), T[2]), M), atol=1e-14)
+
+
 def test_full_matrix_scales():
     """The entry scales of the explicit full matrices: on a torus they equal
     the block-circulant matrix of the shift-structured scales (two separate
