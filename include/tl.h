@@ -395,6 +395,28 @@ tl_status tl_btoepl_power(int L, int m0, int iters, double* x_dev, double* y_dev
                           double* lambda_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
 /*
+ * Multilevel block-Toeplitz products (the recursive Definition of the d-level
+ * class; the Remark's double-size embedding at each level): A over
+ * L1 x L2 x L3 cells, block (r, c) = B(r - c) for cells r, c flattened as
+ * [r1][r2][r3], through the block circulant C over 2L1 x 2L2 x 2L3 cells
+ * (a level with L_l = 1 stays 1) and a 3D block DFT.
+ *   tl_btoepl3_workspace_bytes  workspace for (L, m0, nvec).
+ *   tl_btoepl3_setup  B_dev: [2L1-1][2L2-1][2L3-1][m0][m0], shift d at index
+ *       d + L - 1 per level (any blocks: the symmetric class of the paper has
+ *       B(-d) = B(d)^T); forms C's k-blocks in the workspace.
+ *   tl_btoepl3_matvec  Y = A X, X_dev and Y_dev [L1][L2][L3][m0][nvec] FP64.
+ * Limits: at most 4096 embedded cells; with two or more levels each doubled
+ * length must be 7-smooth (one level may use Bluestein as in the one-level
+ * product); 1 <= m0 <= TL_MAX_M0, 1 <= nvec <= 1024.
+ * Errors: TL_EINVAL, TL_EWORKSPACE, TL_EUNSUPPORTED (no transform plan).
+ */
+tl_status tl_btoepl3_workspace_bytes(int L1, int L2, int L3, int m0, int nvec, size_t* bytes);
+tl_status tl_btoepl3_setup(const double* B_dev, int L1, int L2, int L3, int m0, int nvec,
+                           void* ws_dev, size_t ws_bytes, void* stream);
+tl_status tl_btoepl3_matvec(const double* X_dev, double* Y_dev, int L1, int L2, int L3, int m0,
+                            int nvec, void* ws_dev, size_t ws_bytes, void* stream);
+
+/*
  * tl_btoepl_lowest - the nev lowest eigenpairs of the symmetric-definite
  * pencil T_H u = lambda T_S u of two symmetric block-Toeplitz matrices given
  * by their first block columns (the iterative route for boxes too large for

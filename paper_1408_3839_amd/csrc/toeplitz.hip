@@ -196,6 +196,159 @@ tl_status matvec(const ToeplitzLayout& t, char* ws, const double* X, double* Y,
 }
 
 // ===========================================================================
+// Multilevel block-Toeplitz products (the Definition of the d-level class and
+// the Remark's embedding at each level): A over L1 x L2 x L3 cells with block
+// (r, c) = B(r - c), B given for every shift d in (-L, L)^3.  C over
+// 2L1 x 2L2 x 2L3 cells, C_k = B(k') with k'_l = k_l (k_l < L_l), none
+// (k_l = L_l), k_l - 2 L_l (k_l > L_l), is block circulant on that lattice and
+// A X is its product with X padded by zeros, read on the first L cells (a
+// level with L_l = 1 is not doubled); the transforms are 3D (each doubled
+// length 7-smooth, at most 4096 embedded cells).
+
+struct Toeplitz3Layout {
+  int L[3], L2[3], m0, nvec, P;  // P = 8 L1 L2 L3 embedded cells
+  int64_t Eb, Ev;
+  size_t off_chat, off_xt, off_xhat, off_r, off_f, off_tab[3], bytes;
+  FftArgs fb, fx, fr;
+};
+
+tl_status layout3(const int L[3], int m0, int nvec, Toeplitz3Layout* t, char* ws) {
+  int P = 1;
+  for (int d = 0; d < 3; ++d) {
+    TL_REQUIRE(L[d] >= 1, "L[%d] = %d < 1", d, L[d]);
+    t->L[d] = L[d];
+    t->L2[d] = L[d] > 1 ? 2 * L[d] : 1;
+    P *= t->L2[d];
+    TL_REQUIRE(P <= kFftPoints, "embedded lattice of more than %d cells", kFftPoints);
+  }
+  TL_REQUIRE(m0 >= 1 && m0 <= TL_MAX_M0, "m0 = %d outside [1, %d]", m0, TL_MAX_M0);
+  TL_REQUIRE(nvec >= 1 && nvec <= 1024, "nvec = %d outside [1, 1024]", nvec);
+  t->P = P;
+  t->m0 = m0;
+  t->nvec = nvec;
+  t->Eb = (int64_t)m0 * m0;
+  t->Ev = (int64_t)m0 * nvec;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t r = o;
+    o += align_up(b, 256);
+    return r;
+  };
+  t->off_chat = take(sizeof(double) * 2 * P * t->Eb);
+  t->off_xt = take(sizeof(double) * P * std::max(t->Ev, t->Eb));
+  t->off_xhat = take(sizeof(double) * 2 * P * t->Ev);
+  t->off_r = take(sizeof(double) * 2 * P * t->Ev);
+  t->off_f = take(sizeof(double) * 4 * P * t->Ev);
+  auto ptr = [&](size_t off) { return (double*)(ws ? ws + off : nullptr); };
+  if (!plan_fft_cols(ptr(t->off_xt), ptr(t->off_chat), t->L2, t->Eb, 1, &t->fb, 64) ||
+      !plan_fft_cols(ptr(t->off_xt), ptr(t->off_xhat), t->L2, t->Ev, 1, &t->fx, 64) ||
+      !plan_fft_cols(ptr(t->off_r), ptr(t->off_f), t->L2, t->Ev, 2, &t->fr, 64)) {
+    set_error("no FFT plan for the embedded lattice %d x %d x %d", t->L2[0], t->L2[1], t->L2[2]);
+    return TL_EUNSUPPORTED;
+  }
+  FftArgs* plans[3] = {&t->fb, &t->fx, &t->fr};
+  for (int q = 0; q < 3; ++q) {
+    t->off_tab[q] = take(fft_blue_table_bytes(*plans[q]));
+    if (ws) set_fft_blue_tables(plans[q], ws + t->off_tab[q]);
+  }
+  t->bytes = o;
+  return TL_OK;
+}
+
+struct Embed3Args {
+  const double* B;  // [2L1-1][2L2-1][2L3-1][m0][m0], shift d at d + L - 1
+  double* Cb;       // [n1][n2][n3][m0][m0], n_l the embedded extents
+  int L[3], n[3], m0;
+  int64_t total;
+};
+
+__global__ __launch_bounds__(256) void embed3_kernel(Embed3Args a) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.total) return;
+  const int64_t m2 = (int64_t)a.m0 * a.m0;
+  const int64_t cell = idx / m2;
+  const int e = (int)(idx - cell * m2);
+  const int n3 = a.n[2], n2 = a.n[1];
+  const int k3 = (int)(cell % n3), k2 = (int)((cell / n3) % n2), k1 = (int)(cell / (n3 * n2));
+  const int k[3] = {k1, k2, k3};
+  int src[3];
+  bool zero = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int s = k[d] < a.L[d] ? k[d] : k[d] - 2 * a.L[d];  // the shift this cell carries
+    zero |= k[d] == a.L[d];
+    src[d] = s + a.L[d] - 1;
+  }
+  double v = 0.0;
+  if (!zero) {
+    const int64_t b = ((int64_t)src[0] * (2 * a.L[1] - 1) + src[1]) * (2 * a.L[2] - 1) + src[2];
+    v = a.B[b * m2 + e];
+  }
+  a.Cb[idx] = v;
+}
+
+struct Pad3Args {
+  const double* X;  // [L1][L2][L3][E]
+  double* Xt;       // [n1][n2][n3][E]
+  int L[3], n[3];
+  int64_t E, total;
+};
+
+__global__ __launch_bounds__(256) void pad3_kernel(Pad3Args a) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.total) return;
+  const int64_t cell = idx / a.E;
+  const int64_t e = idx - cell * a.E;
+  const int n3 = a.n[2], n2 = a.n[1];
+  const int k3 = (int)(cell % n3), k2 = (int)((cell / n3) % n2), k1 = (int)(cell / (n3 * n2));
+  double v = 0.0;
+  if (k1 < a.L[0] && k2 < a.L[1] && k3 < a.L[2])
+    v = a.X[(((int64_t)k1 * a.L[1] + k2) * a.L[2] + k3) * a.E + e];
+  a.Xt[idx] = v;
+}
+
+struct Comb3Args {
+  const double* F;  // [2][P][E] complex: DFT(R), DFT(I) over the embedded lattice
+  double* Y;        // [L1][L2][L3][E]
+  int L[3], n[3], P;
+  int64_t E, total;
+};
+
+__global__ __launch_bounds__(256) void comb3_kernel(Comb3Args a) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.total) return;
+  const int64_t cell = idx / a.E;
+  const int64_t e = idx - cell * a.E;
+  const int r3 = (int)(cell % a.L[2]), r2 = (int)((cell / a.L[2]) % a.L[1]);
+  const int r1 = (int)(cell / ((int64_t)a.L[2] * a.L[1]));
+  const int64_t src = (((int64_t)r1 * a.n[1] + r2) * a.n[2] + r3) * a.E + e;
+  const double fr = a.F[2 * src];
+  const double fi = a.F[2 * ((int64_t)a.P * a.E + src) + 1];
+  a.Y[idx] = (fr + fi) / (double)a.P;
+}
+
+tl_status matvec3(const Toeplitz3Layout& t, char* ws, const double* X, double* Y,
+                  hipStream_t stream) {
+  const int64_t nx = (int64_t)t.P * t.Ev;
+  hipLaunchKernelGGL(pad3_kernel, dim3((unsigned)ceil_div(nx, 256)), dim3(256), 0, stream,
+                     Pad3Args{X, (double*)(ws + t.off_xt), {t.L[0], t.L[1], t.L[2]},
+                              {t.L2[0], t.L2[1], t.L2[2]}, t.Ev, nx});
+  TL_CHECK_LAUNCH();
+  TL_TRY(launch_fft(t.fx, stream));
+  hipLaunchKernelGGL(mul_kernel, dim3((unsigned)ceil_div(nx, 256)), dim3(256), 0, stream,
+                     MulArgs{(const double*)(ws + t.off_chat), (const double*)(ws + t.off_xhat),
+                             (double*)(ws + t.off_r), t.P, t.m0, t.nvec});
+  TL_CHECK_LAUNCH();
+  TL_TRY(launch_fft(t.fr, stream));
+  const int64_t ny = (int64_t)t.L[0] * t.L[1] * t.L[2] * t.Ev;
+  hipLaunchKernelGGL(comb3_kernel, dim3((unsigned)ceil_div(ny, 256)), dim3(256), 0, stream,
+                     Comb3Args{(const double*)(ws + t.off_f), Y, {t.L[0], t.L[1], t.L[2]},
+                               {t.L2[0], t.L2[1], t.L2[2]}, t.P, t.Ev, ny});
+  TL_CHECK_LAUNCH();
+  return TL_OK;
+}
+
+// ===========================================================================
 // Lowest eigenpairs of the symmetric-definite block-Toeplitz pencil
 // (T_H, T_S): the iterative route the paper points to for open boxes whose
 // full matrices are too large to diagonalise (Sec. 3.3, closing remark), on
@@ -1328,4 +1481,50 @@ extern "C" tl_status tl_btoepl_lowest(const double* H_dev, const double* S_dev, 
   return btoepl_lowest(H_dev, S_dev, L, m0, nev, nb, max_iter, tol, shift, x0_dev, evals_dev,
                        evecs_dev, resid_dev, iters, nconv, (char*)ws_dev, ws_bytes,
                        (hipStream_t)stream);
+}
+
+extern "C" tl_status tl_btoepl3_workspace_bytes(int L1, int L2, int L3, int m0, int nvec,
+                                                size_t* bytes) {
+  clear_error();
+  TL_REQUIRE(bytes != nullptr, "null output");
+  const int L[3] = {L1, L2, L3};
+  Toeplitz3Layout t;
+  TL_TRY(layout3(L, m0, nvec, &t, nullptr));
+  *bytes = t.bytes;
+  return TL_OK;
+}
+
+extern "C" tl_status tl_btoepl3_setup(const double* B_dev, int L1, int L2, int L3, int m0,
+                                      int nvec, void* ws_dev, size_t ws_bytes, void* stream) {
+  clear_error();
+  const int L[3] = {L1, L2, L3};
+  Toeplitz3Layout t;
+  TL_TRY(layout3(L, m0, nvec, &t, (char*)ws_dev));
+  TL_REQUIRE(B_dev && ws_dev, "null array argument");
+  if (ws_bytes < t.bytes) {
+    set_error("workspace: need %zu bytes, got %zu", t.bytes, ws_bytes);
+    return TL_EWORKSPACE;
+  }
+  char* ws = (char*)ws_dev;
+  Embed3Args a{B_dev, (double*)(ws + t.off_xt), {L1, L2, L3}, {t.L2[0], t.L2[1], t.L2[2]}, m0,
+               (int64_t)t.P * t.Eb};
+  hipLaunchKernelGGL(embed3_kernel, dim3((unsigned)ceil_div(a.total, 256)), dim3(256), 0,
+                     (hipStream_t)stream, a);
+  TL_CHECK_LAUNCH();
+  return launch_fft(t.fb, (hipStream_t)stream);
+}
+
+extern "C" tl_status tl_btoepl3_matvec(const double* X_dev, double* Y_dev, int L1, int L2, int L3,
+                                       int m0, int nvec, void* ws_dev, size_t ws_bytes,
+                                       void* stream) {
+  clear_error();
+  const int L[3] = {L1, L2, L3};
+  Toeplitz3Layout t;
+  TL_TRY(layout3(L, m0, nvec, &t, (char*)ws_dev));
+  TL_REQUIRE(X_dev && Y_dev && ws_dev, "null array argument");
+  if (ws_bytes < t.bytes) {
+    set_error("workspace: need %zu bytes, got %zu", t.bytes, ws_bytes);
+    return TL_EWORKSPACE;
+  }
+  return matvec3(t, (char*)ws_dev, X_dev, Y_dev, (hipStream_t)stream);
 }

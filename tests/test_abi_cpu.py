@@ -231,6 +231,20 @@ def test_bloch_orbital_factors_validation():
     tl.tl_chain_orbital_factors(box, None, None, 0, None, 0)
 
 
+def test_btoepl3_sizes_and_validation():
+    b = tl.tl_btoepl3_workspace_bytes(4, 3, 2, 2, 3)
+    # embedded k-blocks, padded X, its transform, [R; I] and their transforms
+    P, Ev = 8 * 4 * 3 * 2, 2 * 3
+    assert b >= 8 * (2 * P * 4 + P * Ev + 2 * P * Ev + 2 * P * Ev + 4 * P * Ev)
+    assert tl.tl_btoepl3_workspace_bytes(37, 1, 1, 2, 1) > 0  # Bluestein on one level
+    with pytest.raises(tl.TlError):
+        tl.tl_btoepl3_workspace_bytes(9, 8, 8, 1, 1)  # 4608 embedded cells
+    with pytest.raises(tl.TlError):
+        tl.tl_btoepl3_workspace_bytes(0, 1, 1, 1, 1)
+    _expect(lambda: tl.tl_btoepl3_workspace_bytes(11, 2, 1, 1, 1), tl.TL_EUNSUPPORTED)
+    _expect(lambda: tl.tl_btoepl3_matvec(8, 8, 4, 3, 2, 2, 3, 8, 8, 0), tl.TL_EWORKSPACE)
+
+
 def test_btoepl_lowest_sizes_and_validation():
     b = tl.tl_btoepl_lowest_workspace_bytes(256, 4, 12)
     # two embedded operators, 15 blocks of N nb vectors, the preconditioner's k-blocks

@@ -297,3 +297,50 @@ def test_btoepl_lowest_edge_sizes(case):
     print(f"\n{case}: {it} iterations, {nc} converged, residuals {res.max():.2e}")
     assert nc == nev
     _check_pairs(Hb, Sb, lam, U, 1e-9, f"edge {case}")
+
+
+@pytest.mark.parametrize("shape", [(4, 3, 2, 2, 3), (3, 1, 5, 3, 2), (8, 8, 8, 1, 2),
+                                   (37, 1, 1, 2, 4), (1, 1, 1, 3, 2)], ids=str)
+def test_btoepl3_matvec(shape):
+    """Multilevel products against the oracle's explicit multilevel matrix:
+    three levels, odd extents, the 8 x 8 x 8 lattice (4096 embedded cells),
+    one level of prime length (Bluestein) and a single cell."""
+    L1, L2, L3, m0, nvec = shape
+    rng = np.random.default_rng(L1 * 100 + L2 * 10 + L3)
+    B = rng.standard_normal((2 * L1 - 1, 2 * L2 - 1, 2 * L3 - 1, m0, m0))
+    X = rng.standard_normal((L1, L2, L3, m0, nvec))
+    ws_bytes = tl.tl_btoepl3_workspace_bytes(L1, L2, L3, m0, nvec)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    Bd = torch.from_numpy(B).cuda()
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.full_like(Xd, float("nan"))
+    tl.tl_btoepl3_setup(Bd, L1, L2, L3, m0, nvec, ws, ws_bytes)
+    tl.tl_btoepl3_matvec(Xd, Yd, L1, L2, L3, m0, nvec, ws, ws_bytes)
+    torch.cuda.synchronize()
+    T = oracle.btoepl_multilevel_full(B, (L1, L2, L3))
+    N = L1 * L2 * L3 * m0
+    Yr = (T @ X.reshape(N, nvec)).reshape(X.shape)
+    err = np.abs(Yd.cpu().numpy() - Yr).max() / (np.abs(T).sum(axis=1).max() * np.abs(X).max())
+    print(f"\n{shape}: max |dY| / (|T|_inf max|X|) = {err:.2e}")
+    assert err <= 1e-13
+
+
+def test_btoepl3_matches_one_level():
+    """On one level with B(-d) = A_d^T the multilevel product is the one-level
+    symmetric product."""
+    rng = np.random.default_rng(12)
+    L, m0, nvec = 50, 3, 4
+    A = _blocks(rng, L, m0)
+    B = np.zeros((2 * L - 1, 1, 1, m0, m0))
+    for d in range(-(L - 1), L):
+        B[d + L - 1, 0, 0] = A[d] if d >= 0 else A[-d].T
+    X = rng.standard_normal((L, m0, nvec))
+    ws_bytes = tl.tl_btoepl3_workspace_bytes(L, 1, 1, m0, nvec)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    tl.tl_btoepl3_setup(torch.from_numpy(B).cuda(), L, 1, 1, m0, nvec, ws, ws_bytes)
+    tl.tl_btoepl3_matvec(Xd, Yd, L, 1, 1, m0, nvec, ws, ws_bytes)
+    torch.cuda.synchronize()
+    Y1 = _matvec(A, X)
+    assert np.abs(Yd.cpu().numpy() - Y1).max() <= 1e-13 * np.abs(Y1).max()
