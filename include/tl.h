@@ -415,6 +415,12 @@ tl_status tl_btoepl3_setup(const double* B_dev, int L1, int L2, int L3, int m0, 
                            void* ws_dev, size_t ws_bytes, void* stream);
 tl_status tl_btoepl3_matvec(const double* X_dev, double* Y_dev, int L1, int L2, int L3, int m0,
                             int nvec, void* ws_dev, size_t ws_bytes, void* stream);
+/* tl_btoepl3_power: the power method of the Remark on the multilevel
+ * product, as tl_btoepl_power (x_dev, y_dev: L1 L2 L3 m0 doubles; workspace
+ * and set-up for nvec = 1). */
+tl_status tl_btoepl3_power(int L1, int L2, int L3, int m0, int iters, double* x_dev,
+                           double* y_dev, double* lambda_dev, void* ws_dev, size_t ws_bytes,
+                           void* stream);
 
 /*
  * tl_btoepl_lowest - the nev lowest eigenpairs of the symmetric-definite

@@ -1528,3 +1528,26 @@ extern "C" tl_status tl_btoepl3_matvec(const double* X_dev, double* Y_dev, int L
   }
   return matvec3(t, (char*)ws_dev, X_dev, Y_dev, (hipStream_t)stream);
 }
+
+extern "C" tl_status tl_btoepl3_power(int L1, int L2, int L3, int m0, int iters, double* x_dev,
+                                      double* y_dev, double* lambda_dev, void* ws_dev,
+                                      size_t ws_bytes, void* stream) {
+  clear_error();
+  const int L[3] = {L1, L2, L3};
+  Toeplitz3Layout t;
+  TL_TRY(layout3(L, m0, 1, &t, (char*)ws_dev));
+  TL_REQUIRE(x_dev && y_dev && lambda_dev && ws_dev, "null array argument");
+  TL_REQUIRE(iters >= 1, "iters = %d < 1", iters);
+  if (ws_bytes < t.bytes) {
+    set_error("workspace: need %zu bytes, got %zu", t.bytes, ws_bytes);
+    return TL_EWORKSPACE;
+  }
+  const int n = L1 * L2 * L3 * m0;
+  for (int it = 0; it < iters; ++it) {
+    TL_TRY(matvec3(t, (char*)ws_dev, x_dev, y_dev, (hipStream_t)stream));
+    hipLaunchKernelGGL(power_update_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, x_dev,
+                       (const double*)y_dev, n, lambda_dev + it);
+    TL_CHECK_LAUNCH();
+  }
+  return TL_OK;
+}

@@ -145,6 +145,8 @@ SIGNATURES = {
                          + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "tl_btoepl3_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5
                           + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "tl_btoepl3_power": (ctypes.c_int, [ctypes.c_int] * 5 + [ctypes.c_void_p] * 4
+                         + [ctypes.c_size_t, ctypes.c_void_p]),
     "tl_btoepl_lowest_workspace_bytes": (ctypes.c_int, [ctypes.c_int] * 3
                                          + [ctypes.POINTER(ctypes.c_size_t)]),
     "tl_btoepl_lowest": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5
@@ -438,6 +440,12 @@ def tl_btoepl3_matvec(X, Y, L1, L2, L3, m0, nvec, ws, ws_bytes, stream=None):
     _check(load().tl_btoepl3_matvec(_ptr(X), _ptr(Y), int(L1), int(L2), int(L3), int(m0),
                                     int(nvec), _ptr(ws), int(ws_bytes), _stream(stream)),
            "tl_btoepl3_matvec")
+
+
+def tl_btoepl3_power(L1, L2, L3, m0, iters, x, y, lam, ws, ws_bytes, stream=None):
+    _check(load().tl_btoepl3_power(int(L1), int(L2), int(L3), int(m0), int(iters), _ptr(x),
+                                   _ptr(y), _ptr(lam), _ptr(ws), int(ws_bytes), _stream(stream)),
+           "tl_btoepl3_power")
 
 
 def tl_btoepl_lowest_workspace_bytes(L, m0, nb) -> int:

@@ -344,3 +344,47 @@ def test_btoepl3_matches_one_level():
     torch.cuda.synchronize()
     Y1 = _matvec(A, X)
     assert np.abs(Yd.cpu().numpy() - Y1).max() <= 1e-13 * np.abs(Y1).max()
+
+
+def test_btoepl3_power():
+    """The power method on a symmetric three-level block-Toeplitz matrix
+    (B(-d) = B(d)^T): every Rayleigh quotient and the last iterate equal the
+    same iteration with the oracle's explicit matrix, and the quotients stay
+    below the senior eigenvalue in magnitude."""
+    rng = np.random.default_rng(21)
+    L, m0, iters = (3, 4, 2), 2, 150
+    shp = tuple(2 * n - 1 for n in L)
+    B = np.zeros(shp + (m0, m0))
+    for d in np.ndindex(*shp):
+        dd = tuple(d[i] - (L[i] - 1) for i in range(3))
+        md = tuple(-dd[i] + (L[i] - 1) for i in range(3))
+        if dd == (0, 0, 0):
+            b = rng.standard_normal((m0, m0))
+            B[d] = b + b.T + np.diag([12.0, 0.0])
+        elif d < md:  # one of each pair of opposite shifts
+            B[d] = 0.3 * rng.standard_normal((m0, m0)) / (1.0 + sum(abs(v) for v in dd))
+            B[md] = B[d].T
+    T = oracle.btoepl_multilevel_full(B, L)
+    assert np.abs(T - T.T).max() == 0.0
+    n = T.shape[0]
+    x0 = rng.standard_normal(n)
+    ws_bytes = tl.tl_btoepl3_workspace_bytes(*L, m0, 1)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    tl.tl_btoepl3_setup(torch.from_numpy(B).cuda(), *L, m0, 1, ws, ws_bytes)
+    x = torch.from_numpy(x0.copy()).cuda()
+    y = torch.empty_like(x)
+    lam = torch.empty(iters, dtype=torch.float64, device="cuda")
+    tl.tl_btoepl3_power(*L, m0, iters, x, y, lam, ws, ws_bytes)
+    torch.cuda.synchronize()
+    lam, x = lam.cpu().numpy(), x.cpu().numpy()
+    xr, lr = x0.copy(), []
+    for _ in range(iters):
+        yr = T @ xr
+        lr.append(xr @ yr / (xr @ xr))
+        xr = yr / np.linalg.norm(yr)
+    assert np.abs(lam - np.array(lr)).max() <= 1e-12 * np.abs(lr).max()
+    assert np.abs(x - xr).max() <= 1e-10
+    w = np.linalg.eigvalsh(T)
+    top = w[np.argmax(np.abs(w))]
+    print(f"\nsenior eigenvalue {top:.6f}, power after {iters} steps {lam[-1]:.6f}")
+    assert np.all(np.abs(lam) <= abs(top) * (1 + 1e-12))
