@@ -456,6 +456,20 @@ tl_status tl_btoepl3_power(int L1, int L2, int L3, int m0, int iters, double* x_
  * TL_EUNSUPPORTED (no transform plan for L).
  */
 tl_status tl_btoepl_lowest_workspace_bytes(int L, int m0, int nb, size_t* bytes);
+/* tl_btoepl3_lowest: the same solver for a pencil of symmetric multilevel
+ * block-Toeplitz matrices over L1 x L2 x L3 cells (blocks for every shift as
+ * for tl_btoepl3_setup, with B(-d) = B(d)^T), on the multilevel product; the
+ * preconditioner is the shifted Strang circulant over the L1 x L2 x L3
+ * lattice (at a half-period shift the mean of both blocks).  Vectors
+ * [L1][L2][L3][m0][nev]; limits of the multilevel product (at most 4096
+ * embedded cells). */
+tl_status tl_btoepl3_lowest_workspace_bytes(int L1, int L2, int L3, int m0, int nb,
+                                            size_t* bytes);
+tl_status tl_btoepl3_lowest(const double* H_dev, const double* S_dev, int L1, int L2, int L3,
+                            int m0, int nev, int nb, int max_iter, double tol, double shift,
+                            const double* x0_dev, double* evals_dev, double* evecs_dev,
+                            double* resid_dev, int* iters, int* nconv, void* ws_dev,
+                            size_t ws_bytes, void* stream);
 tl_status tl_btoepl_lowest(const double* H_dev, const double* S_dev, int L, int m0, int nev,
                            int nb, int max_iter, double tol, double shift, const double* x0_dev,
                            double* evals_dev, double* evecs_dev, double* resid_dev, int* iters,

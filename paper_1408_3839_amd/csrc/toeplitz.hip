@@ -489,6 +489,81 @@ __global__ __launch_bounds__(256) void tnorm_kernel(const double* H, const doubl
   }
 }
 
+// Strang block circulant of a multilevel Toeplitz matrix over L1 x L2 x L3
+// cells: c_k = B(k') with k'_l = k_l (2 k_l < L_l), k_l - L_l (2 k_l > L_l)
+// and the mean of both at 2 k_l = L_l, for H and S.
+struct Strang3Args {
+  const double* B[2];  // [2L1-1][2L2-1][2L3-1][m0][m0]
+  double* out;         // [2][L1 L2 L3][m0][m0]
+  int L[3], m0;
+  int64_t total;
+};
+
+__global__ __launch_bounds__(256) void strang3_kernel(Strang3Args a) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.total) return;
+  const int64_t m2 = (int64_t)a.m0 * a.m0;
+  const int64_t cells = (int64_t)a.L[0] * a.L[1] * a.L[2];
+  const int w = (int)(idx / (cells * m2));
+  const int64_t rest = idx - w * cells * m2;
+  const int64_t cell = rest / m2;
+  const int e = (int)(rest - cell * m2);
+  const int k3 = (int)(cell % a.L[2]), k2 = (int)((cell / a.L[2]) % a.L[1]);
+  const int k1 = (int)(cell / ((int64_t)a.L[2] * a.L[1]));
+  const int k[3] = {k1, k2, k3};
+  int c0[3], c1[3], nc[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int twice = 2 * k[d];
+    c0[d] = twice < a.L[d] ? k[d] : k[d] - a.L[d];
+    c1[d] = k[d];
+    nc[d] = twice == a.L[d] ? 2 : 1;
+  }
+  const double* B = a.B[w];
+  double v = 0.0;
+  for (int i1 = 0; i1 < nc[0]; ++i1)
+    for (int i2 = 0; i2 < nc[1]; ++i2)
+      for (int i3 = 0; i3 < nc[2]; ++i3) {
+        const int s1 = (i1 ? c1[0] : c0[0]) + a.L[0] - 1;
+        const int s2 = (i2 ? c1[1] : c0[1]) + a.L[1] - 1;
+        const int s3 = (i3 ? c1[2] : c0[2]) + a.L[2] - 1;
+        const int64_t b = ((int64_t)s1 * (2 * a.L[1] - 1) + s2) * (2 * a.L[2] - 1) + s3;
+        v += B[b * m2 + e];
+      }
+  a.out[idx] = v / (double)(nc[0] * nc[1] * nc[2]);
+}
+
+// scal[1], scal[2]: sum over all shifts of the largest row sum of |B(d)|,
+// the infinity norm bound of the multilevel matrices H and S.
+__global__ __launch_bounds__(256) void tnorm3_kernel(const double* H, const double* S, int nblk,
+                                                     int m0, double* scal) {
+  __shared__ double red[2][4];
+  double acc[2] = {0.0, 0.0};
+  const int64_t m2 = (int64_t)m0 * m0;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+    for (int w = 0; w < 2; ++w) {
+      const double* A = (w ? S : H) + k * m2;
+      double rmax = 0.0;
+      for (int i = 0; i < m0; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < m0; ++j) r += fabs(A[i * m0 + j]);
+        rmax = fmax(rmax, r);
+      }
+      acc[w] += rmax;
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int w = 0; w < 2; ++w) {
+    const double t = wave_sum_dpp(acc[w]);
+    if (lane == 0) red[w][wave] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int w = threadIdx.x;
+    scal[1 + w] = red[w][0] + red[w][1] + red[w][2] + red[w][3];
+  }
+}
+
 // Minv_j = (Hhat_j - sigma Shat_j)^-1 by complex Cholesky, one thread per j
 // (Lf: the factor, workspace).  info[j] = 1 + the failing pivot, else 0.
 __global__ __launch_bounds__(64) void minv_kernel(const double* hat, int L, int m0, double sigma,
@@ -964,9 +1039,11 @@ enum LobVec {
 };
 
 struct LobLayout {
-  int L, m0, nb;
+  int Lv[3], cells, m0, nb;
+  bool three;  // operators are multilevel products (blocks for every shift)
   int64_t N, Ev;
   ToeplitzLayout tH, tS;
+  Toeplitz3Layout tH3, tS3;
   size_t off_tH, off_tS;
   FftArgs fblk, fr, fz;
   size_t off_strang, off_hat, off_evals, off_info, off_lf, off_minv, off_rhat, off_z, off_f;
@@ -978,14 +1055,21 @@ struct LobLayout {
   size_t bytes;
 };
 
-tl_status lob_layout(int L, int m0, int nb, LobLayout* t, char* ws) {
+tl_status lob_layout(const int Lv[3], bool three, int m0, int nb, LobLayout* t, char* ws) {
   TL_REQUIRE(nb >= 1 && nb <= kLobMaxNb, "nb = %d outside [1, %d]", nb, kLobMaxNb);
-  TL_REQUIRE(L >= 1 && L <= kFftPoints / 2, "L = %d outside [1, %d]", L, kFftPoints / 2);
   TL_REQUIRE(m0 >= 1 && m0 <= TL_MAX_M0, "m0 = %d outside [1, %d]", m0, TL_MAX_M0);
-  t->L = L;
+  if (!three) TL_REQUIRE(Lv[0] >= 1 && Lv[0] <= kFftPoints / 2, "L = %d outside [1, %d]", Lv[0],
+                         kFftPoints / 2);
+  t->three = three;
+  t->cells = 1;
+  for (int d = 0; d < 3; ++d) {
+    t->Lv[d] = Lv[d];
+    t->cells *= Lv[d];
+  }
+  const int cells = t->cells;
   t->m0 = m0;
   t->nb = nb;
-  t->N = (int64_t)L * m0;
+  t->N = (int64_t)cells * m0;
   t->Ev = (int64_t)m0 * nb;
   size_t o = 0;
   auto take = [&](size_t b) {
@@ -993,25 +1077,37 @@ tl_status lob_layout(int L, int m0, int nb, LobLayout* t, char* ws) {
     o += align_up(b, 256);
     return r;
   };
-  TL_TRY(layout(L, m0, nb, &t->tH, nullptr));
-  t->off_tH = take(t->tH.bytes);
-  t->off_tS = take(t->tH.bytes);
-  if (ws) {
-    TL_TRY(layout(L, m0, nb, &t->tH, ws + t->off_tH));
-    TL_TRY(layout(L, m0, nb, &t->tS, ws + t->off_tS));
+  if (three) {
+    TL_TRY(layout3(Lv, m0, nb, &t->tH3, nullptr));
+    t->off_tH = take(t->tH3.bytes);
+    t->off_tS = take(t->tH3.bytes);
+    if (ws) {
+      TL_TRY(layout3(Lv, m0, nb, &t->tH3, ws + t->off_tH));
+      TL_TRY(layout3(Lv, m0, nb, &t->tS3, ws + t->off_tS));
+    } else {
+      t->tS3 = t->tH3;
+    }
   } else {
-    t->tS = t->tH;
+    TL_TRY(layout(Lv[0], m0, nb, &t->tH, nullptr));
+    t->off_tH = take(t->tH.bytes);
+    t->off_tS = take(t->tH.bytes);
+    if (ws) {
+      TL_TRY(layout(Lv[0], m0, nb, &t->tH, ws + t->off_tH));
+      TL_TRY(layout(Lv[0], m0, nb, &t->tS, ws + t->off_tS));
+    } else {
+      t->tS = t->tH;
+    }
   }
   const int64_t m2 = (int64_t)m0 * m0;
-  t->off_strang = take(sizeof(double) * 2 * L * m2);
-  t->off_hat = take(sizeof(double) * 4 * L * m2);
-  t->off_evals = take(sizeof(double) * L * m0);
-  t->off_info = take(sizeof(int) * L);
-  t->off_lf = take(sizeof(double) * 2 * L * m2);
-  t->off_minv = take(sizeof(double) * 2 * L * m2);
-  t->off_rhat = take(sizeof(double) * 2 * L * t->Ev);
-  t->off_z = take(sizeof(double) * 2 * L * t->Ev);
-  t->off_f = take(sizeof(double) * 4 * L * t->Ev);
+  t->off_strang = take(sizeof(double) * 2 * cells * m2);
+  t->off_hat = take(sizeof(double) * 4 * cells * m2);
+  t->off_evals = take(sizeof(double) * cells * m0);
+  t->off_info = take(sizeof(int) * cells);
+  t->off_lf = take(sizeof(double) * 2 * cells * m2);
+  t->off_minv = take(sizeof(double) * 2 * cells * m2);
+  t->off_rhat = take(sizeof(double) * 2 * cells * t->Ev);
+  t->off_z = take(sizeof(double) * 2 * cells * t->Ev);
+  t->off_f = take(sizeof(double) * 4 * cells * t->Ev);
   for (int v = 0; v < kNVec; ++v) t->off_vec[v] = take(sizeof(double) * t->N * nb);
   t->chunk_rows = (int)std::max<int64_t>(32, align_up((size_t)ceil_div(t->N, 64), 32));
   t->chunks = (int)ceil_div(t->N, t->chunk_rows);
@@ -1024,12 +1120,11 @@ tl_status lob_layout(int L, int m0, int nb, LobLayout* t, char* ws) {
   t->off_scal = take(sizeof(double) * 8);
   t->off_mask = take(sizeof(double) * kLobMaxNb);
   t->off_lambest = take(sizeof(double) * kLobMaxNb);
-  const int Ls[3] = {L, 1, 1};
   auto ptr = [&](size_t off) { return (double*)(ws ? ws + off : nullptr); };
-  if (!plan_fft_cols(ptr(t->off_strang), ptr(t->off_hat), Ls, m2, 2, &t->fblk, 64) ||
-      !plan_fft_cols(ptr(t->off_vec[kW]), ptr(t->off_rhat), Ls, t->Ev, 1, &t->fr, 64) ||
-      !plan_fft_cols(ptr(t->off_z), ptr(t->off_f), Ls, t->Ev, 2, &t->fz, 64)) {
-    set_error("no FFT plan for L = %d", L);
+  if (!plan_fft_cols(ptr(t->off_strang), ptr(t->off_hat), t->Lv, m2, 2, &t->fblk, 64) ||
+      !plan_fft_cols(ptr(t->off_vec[kW]), ptr(t->off_rhat), t->Lv, t->Ev, 1, &t->fr, 64) ||
+      !plan_fft_cols(ptr(t->off_z), ptr(t->off_f), t->Lv, t->Ev, 2, &t->fz, 64)) {
+    set_error("no FFT plan for the lattice %d x %d x %d", Lv[0], Lv[1], Lv[2]);
     return TL_EUNSUPPORTED;
   }
   FftArgs* plans[3] = {&t->fblk, &t->fr, &t->fz};
@@ -1065,6 +1160,10 @@ class Lobpcg {
   double* at(size_t off) const { return (double*)(ws_ + off); }
 
   tl_status products(int src, int dA, int dB) {
+    if (t_.three) {
+      TL_TRY(matvec3(t_.tH3, ws_ + t_.off_tH, v(src), v(dA), st_));
+      return matvec3(t_.tS3, ws_ + t_.off_tS, v(src), v(dB), st_);
+    }
     TL_TRY(matvec(t_.tH, ws_ + t_.off_tH, v(src), v(dA), st_));
     return matvec(t_.tS, ws_ + t_.off_tS, v(src), v(dB), st_);
   }
@@ -1202,14 +1301,14 @@ class Lobpcg {
   // W <- Strang shift-inverse of W (through the block DFT over L cells)
   tl_status precondition() {
     TL_TRY(launch_fft(t_.fr, st_));
-    const int64_t nx = (int64_t)t_.L * t_.Ev;
+    const int64_t nx = (int64_t)t_.cells * t_.Ev;
     hipLaunchKernelGGL(mul_kernel, dim3((unsigned)ceil_div(nx, 256)), dim3(256), 0, st_,
                        MulArgs{(const double*)at(t_.off_minv), (const double*)at(t_.off_rhat),
-                               at(t_.off_z), t_.L, t_.m0, t_.nb});
+                               at(t_.off_z), t_.cells, t_.m0, t_.nb});
     TL_CHECK_LAUNCH();
     TL_TRY(launch_fft(t_.fz, st_));
     hipLaunchKernelGGL(comb_kernel, dim3((unsigned)ceil_div(nx, 256)), dim3(256), 0, st_,
-                       CombArgs{(const double*)at(t_.off_f), v(kW), t_.L, t_.L, t_.Ev});
+                       CombArgs{(const double*)at(t_.off_f), v(kW), t_.cells, t_.cells, t_.Ev});
     TL_CHECK_LAUNCH();
     return TL_OK;
   }
@@ -1252,12 +1351,12 @@ class Lobpcg {
   int cur_[kNVec];
 };
 
-tl_status btoepl_lowest(const double* Hb, const double* Sb, int L, int m0, int nev, int nb,
-                        int max_iter, double tol, double shift, const double* x0, double* evals,
-                        double* evecs, double* resid, int* iters, int* nconv, char* ws,
-                        size_t ws_bytes, hipStream_t st) {
+tl_status btoepl_lowest(const double* Hb, const double* Sb, const int Lv[3], bool three, int m0,
+                        int nev, int nb, int max_iter, double tol, double shift, const double* x0,
+                        double* evals, double* evecs, double* resid, int* iters, int* nconv,
+                        char* ws, size_t ws_bytes, hipStream_t st) {
   LobLayout t;
-  TL_TRY(lob_layout(L, m0, nb, &t, ws));
+  TL_TRY(lob_layout(Lv, three, m0, nb, &t, ws));
   if (ws_bytes < t.bytes) {
     set_error("workspace: need %zu bytes, got %zu", t.bytes, ws_bytes);
     return TL_EWORKSPACE;
@@ -1267,31 +1366,54 @@ tl_status btoepl_lowest(const double* Hb, const double* Sb, int L, int m0, int n
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   Lobpcg lob(t, ws, st);
   const int64_t m2 = (int64_t)m0 * m0;
+  const int cells = t.cells;
   // the two Toeplitz operators
   for (int w = 0; w < 2; ++w) {
-    const ToeplitzLayout& tw = w ? t.tS : t.tH;
     char* base = ws + (w ? t.off_tS : t.off_tH);
-    const int64_t nbk = 2 * (int64_t)L * m2;
-    hipLaunchKernelGGL(embed_kernel, dim3((unsigned)ceil_div(nbk, 256)), dim3(256), 0, st,
-                       EmbedArgs{w ? Sb : Hb, (double*)(base + tw.off_xt), L, m0});
-    TL_CHECK_LAUNCH();
-    TL_TRY(launch_fft(tw.fb, st));
+    if (three) {
+      const Toeplitz3Layout& tw = w ? t.tS3 : t.tH3;
+      Embed3Args a{w ? Sb : Hb, (double*)(base + tw.off_xt), {Lv[0], Lv[1], Lv[2]},
+                   {tw.L2[0], tw.L2[1], tw.L2[2]}, m0, (int64_t)tw.P * tw.Eb};
+      hipLaunchKernelGGL(embed3_kernel, dim3((unsigned)ceil_div(a.total, 256)), dim3(256), 0, st,
+                         a);
+      TL_CHECK_LAUNCH();
+      TL_TRY(launch_fft(tw.fb, st));
+    } else {
+      const ToeplitzLayout& tw = w ? t.tS : t.tH;
+      const int64_t nbk = 2 * (int64_t)Lv[0] * m2;
+      hipLaunchKernelGGL(embed_kernel, dim3((unsigned)ceil_div(nbk, 256)), dim3(256), 0, st,
+                         EmbedArgs{w ? Sb : Hb, (double*)(base + tw.off_xt), Lv[0], m0});
+      TL_CHECK_LAUNCH();
+      TL_TRY(launch_fft(tw.fb, st));
+    }
   }
   // preconditioner: Strang k-blocks, their lowest eigenvalue, the shifted inverses
-  StrangArgs sa{{Hb, Sb}, lob.at(t.off_strang), L, m0};
-  hipLaunchKernelGGL(strang_kernel, dim3((unsigned)ceil_div(2 * L * m2, 256)), dim3(256), 0, st,
-                     sa);
+  if (three) {
+    Strang3Args sa{{Hb, Sb}, lob.at(t.off_strang), {Lv[0], Lv[1], Lv[2]}, m0,
+                   2 * (int64_t)cells * m2};
+    hipLaunchKernelGGL(strang3_kernel, dim3((unsigned)ceil_div(sa.total, 256)), dim3(256), 0, st,
+                       sa);
+  } else {
+    StrangArgs sa{{Hb, Sb}, lob.at(t.off_strang), Lv[0], m0};
+    hipLaunchKernelGGL(strang_kernel, dim3((unsigned)ceil_div(2 * cells * m2, 256)), dim3(256),
+                       0, st, sa);
+  }
   TL_CHECK_LAUNCH();
   TL_TRY(launch_fft(t.fblk, st));
   const double* hat = lob.at(t.off_hat);
   int* kinfo = (int*)(ws + t.off_info);
-  TL_TRY(batched_heigh(hat, hat + 2 * (int64_t)L * m2, L, m0, lob.at(t.off_evals), nullptr,
-                       kinfo, st));
+  TL_TRY(batched_heigh(hat, hat + 2 * (int64_t)cells * m2, cells, m0, lob.at(t.off_evals),
+                       nullptr, kinfo, st));
   double* scal = lob.at(t.off_scal);
   hipLaunchKernelGGL(lmin_kernel, dim3(1), dim3(256), 0, st, (const double*)lob.at(t.off_evals),
-                     (const int*)kinfo, L, m0, scal);
+                     (const int*)kinfo, cells, m0, scal);
   TL_CHECK_LAUNCH();
-  hipLaunchKernelGGL(tnorm_kernel, dim3(1), dim3(256), 0, st, Hb, Sb, L, m0, scal);
+  if (three) {
+    const int nblk = (2 * Lv[0] - 1) * (2 * Lv[1] - 1) * (2 * Lv[2] - 1);
+    hipLaunchKernelGGL(tnorm3_kernel, dim3(1), dim3(256), 0, st, Hb, Sb, nblk, m0, scal);
+  } else {
+    hipLaunchKernelGGL(tnorm_kernel, dim3(1), dim3(256), 0, st, Hb, Sb, Lv[0], m0, scal);
+  }
   TL_CHECK_LAUNCH();
   double sc[8];
   TL_TRY(lob_read(scal, sc, sizeof(sc), st));
@@ -1309,11 +1431,11 @@ tl_status btoepl_lowest(const double* Hb, const double* Sb, int L, int m0, int n
   const double delta = shift > 0.0 ? shift
                                    : std::max(1e-4 * std::max(1.0, std::fabs(lmin)), 10.0 * fin);
   const double sigma = lmin - delta;
-  hipLaunchKernelGGL(minv_kernel, dim3((unsigned)ceil_div(L, 64)), dim3(64), 0, st, hat, L, m0,
-                     sigma, lob.at(t.off_lf), lob.at(t.off_minv), kinfo);
+  hipLaunchKernelGGL(minv_kernel, dim3((unsigned)ceil_div(cells, 64)), dim3(64), 0, st, hat,
+                     cells, m0, sigma, lob.at(t.off_lf), lob.at(t.off_minv), kinfo);
   TL_CHECK_LAUNCH();
   hipLaunchKernelGGL(lmin_kernel, dim3(1), dim3(256), 0, st, (const double*)lob.at(t.off_evals),
-                     (const int*)kinfo, L, m0, scal);
+                     (const int*)kinfo, cells, m0, scal);
   TL_CHECK_LAUNCH();
   TL_TRY(lob_read(scal, sc, sizeof(sc), st));
   if (sc[3] != 0.0) {
@@ -1460,7 +1582,8 @@ extern "C" tl_status tl_btoepl_lowest_workspace_bytes(int L, int m0, int nb, siz
   clear_error();
   TL_REQUIRE(bytes != nullptr, "null output");
   LobLayout t;
-  TL_TRY(lob_layout(L, m0, nb, &t, nullptr));
+  const int Lv[3] = {L, 1, 1};
+  TL_TRY(lob_layout(Lv, false, m0, nb, &t, nullptr));
   *bytes = t.bytes;
   return TL_OK;
 }
@@ -1478,8 +1601,9 @@ extern "C" tl_status tl_btoepl_lowest(const double* H_dev, const double* S_dev, 
              (long long)L * m0, 3 * nb);
   TL_REQUIRE(max_iter >= 1, "max_iter = %d < 1", max_iter);
   TL_REQUIRE(tol > 0.0, "tol must be positive");
-  return btoepl_lowest(H_dev, S_dev, L, m0, nev, nb, max_iter, tol, shift, x0_dev, evals_dev,
-                       evecs_dev, resid_dev, iters, nconv, (char*)ws_dev, ws_bytes,
+  const int Lv[3] = {L, 1, 1};
+  return btoepl_lowest(H_dev, S_dev, Lv, false, m0, nev, nb, max_iter, tol, shift, x0_dev,
+                       evals_dev, evecs_dev, resid_dev, iters, nconv, (char*)ws_dev, ws_bytes,
                        (hipStream_t)stream);
 }
 
@@ -1550,4 +1674,35 @@ extern "C" tl_status tl_btoepl3_power(int L1, int L2, int L3, int m0, int iters,
     TL_CHECK_LAUNCH();
   }
   return TL_OK;
+}
+
+extern "C" tl_status tl_btoepl3_lowest_workspace_bytes(int L1, int L2, int L3, int m0, int nb,
+                                                       size_t* bytes) {
+  clear_error();
+  TL_REQUIRE(bytes != nullptr, "null output");
+  const int Lv[3] = {L1, L2, L3};
+  LobLayout t;
+  TL_TRY(lob_layout(Lv, true, m0, nb, &t, nullptr));
+  *bytes = t.bytes;
+  return TL_OK;
+}
+
+extern "C" tl_status tl_btoepl3_lowest(const double* H_dev, const double* S_dev, int L1, int L2,
+                                       int L3, int m0, int nev, int nb, int max_iter, double tol,
+                                       double shift, const double* x0_dev, double* evals_dev,
+                                       double* evecs_dev, double* resid_dev, int* iters,
+                                       int* nconv, void* ws_dev, size_t ws_bytes, void* stream) {
+  clear_error();
+  TL_REQUIRE(H_dev && S_dev && evals_dev && iters && nconv && ws_dev, "null argument");
+  TL_REQUIRE(L1 >= 1 && L2 >= 1 && L3 >= 1, "lattice extents must be >= 1");
+  TL_REQUIRE(nb >= 1 && nb <= kLobMaxNb, "nb = %d outside [1, %d]", nb, kLobMaxNb);
+  TL_REQUIRE(nev >= 1 && nev <= nb, "nev = %d outside [1, nb = %d]", nev, nb);
+  TL_REQUIRE((int64_t)L1 * L2 * L3 * m0 >= 3 * (int64_t)nb, "L1 L2 L3 m0 below 3 nb = %d",
+             3 * nb);
+  TL_REQUIRE(max_iter >= 1, "max_iter = %d < 1", max_iter);
+  TL_REQUIRE(tol > 0.0, "tol must be positive");
+  const int Lv[3] = {L1, L2, L3};
+  return btoepl_lowest(H_dev, S_dev, Lv, true, m0, nev, nb, max_iter, tol, shift, x0_dev,
+                       evals_dev, evecs_dev, resid_dev, iters, nconv, (char*)ws_dev, ws_bytes,
+                       (hipStream_t)stream);
 }

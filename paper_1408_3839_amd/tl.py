@@ -153,6 +153,12 @@ SIGNATURES = {
                          + [ctypes.c_double, ctypes.c_double] + [ctypes.c_void_p] * 4
                          + [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "tl_btoepl3_lowest_workspace_bytes": (ctypes.c_int, [ctypes.c_int] * 5
+                                          + [ctypes.POINTER(ctypes.c_size_t)]),
+    "tl_btoepl3_lowest": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 7
+                          + [ctypes.c_double, ctypes.c_double] + [ctypes.c_void_p] * 4
+                          + [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "tl_dense_gen_eigh_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int,
                                                          ctypes.POINTER(ctypes.c_size_t)]),
     "tl_set_dense_eigh_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -463,6 +469,26 @@ def tl_btoepl_lowest(H, S, L, m0, nev, nb, max_iter, tol, shift, x0, evals, evec
                                    int(max_iter), float(tol), float(shift), _ptr(x0), _ptr(evals),
                                    _ptr(evecs), _ptr(resid), ctypes.byref(it), ctypes.byref(nc),
                                    _ptr(ws), int(ws_bytes), _stream(stream)), "tl_btoepl_lowest")
+    return it.value, nc.value
+
+
+def tl_btoepl3_lowest_workspace_bytes(L1, L2, L3, m0, nb) -> int:
+    v = ctypes.c_size_t()
+    _check(load().tl_btoepl3_lowest_workspace_bytes(int(L1), int(L2), int(L3), int(m0), int(nb),
+                                                    ctypes.byref(v)),
+           "tl_btoepl3_lowest_workspace_bytes")
+    return v.value
+
+
+def tl_btoepl3_lowest(H, S, L1, L2, L3, m0, nev, nb, max_iter, tol, shift, x0, evals, evecs,
+                      resid, ws, ws_bytes, stream=None):
+    """Returns (iterations, converged count)."""
+    it, nc = ctypes.c_int(), ctypes.c_int()
+    _check(load().tl_btoepl3_lowest(_ptr(H), _ptr(S), int(L1), int(L2), int(L3), int(m0),
+                                    int(nev), int(nb), int(max_iter), float(tol), float(shift),
+                                    _ptr(x0), _ptr(evals), _ptr(evecs), _ptr(resid),
+                                    ctypes.byref(it), ctypes.byref(nc), _ptr(ws), int(ws_bytes),
+                                    _stream(stream)), "tl_btoepl3_lowest")
     return it.value, nc.value
 
 

@@ -245,6 +245,20 @@ def test_btoepl3_sizes_and_validation():
     _expect(lambda: tl.tl_btoepl3_matvec(8, 8, 4, 3, 2, 2, 3, 8, 8, 0), tl.TL_EWORKSPACE)
 
 
+def test_btoepl3_lowest_sizes_and_validation():
+    assert tl.tl_btoepl3_lowest_workspace_bytes(4, 4, 3, 2, 6) > 0
+    with pytest.raises(tl.TlError):
+        tl.tl_btoepl3_lowest_workspace_bytes(9, 8, 8, 1, 4)  # 4608 embedded cells
+    with pytest.raises(tl.TlError):
+        tl.tl_btoepl3_lowest_workspace_bytes(4, 4, 3, 2, 22)
+    for bad in [dict(nev=7), dict(nb=22), dict(L1=1, L2=1, L3=1), dict(tol=0.0), dict(L2=0)]:
+        a = dict(L1=4, L2=4, L3=3, nev=4, nb=6, tol=1e-9)
+        a.update(bad)
+        _expect(lambda: tl.tl_btoepl3_lowest(8, 8, a["L1"], a["L2"], a["L3"], 2, a["nev"], a["nb"],
+                                             10, a["tol"], 0.0, None, 8, None, None, 8, 8, 0),
+                tl.TL_EINVAL)
+
+
 def test_btoepl_lowest_sizes_and_validation():
     b = tl.tl_btoepl_lowest_workspace_bytes(256, 4, 12)
     # two embedded operators, 15 blocks of N nb vectors, the preconditioner's k-blocks
