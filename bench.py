@@ -970,7 +970,7 @@ def stage_section(replicas=(1, 8), reps: int = 5):
         alg, wr = lattice_sum_bytes(systems)
         out[f"x{rep}"] = {
             "instances": len(systems),
-            "fft": {"bound": "hbm", "kernel": "batch_fft_kernel", "avg_kernel_ms": times["fft"],
+            "fft": {"bound": "hbm", "kernel": "batch_fft_kernel + batch_fft_blue_kernel (7-smooth and Bluestein lengths, two launches)", "avg_kernel_ms": times["fft"],
                     "algorithmic_bytes": fb,
                     "achieved": fb / (times["fft"] * 1e-3) / 1e9, "peak": 8000.0,
                     "unit": "GB/s", "frac": fb / (times["fft"] * 1e-3) / 8e12},

@@ -24,7 +24,8 @@ enum Stage {
   kReduce,
   kCombine,
   kFftTables,
-  kDft,
+  kDft,      // block FFT of the instances with 7-smooth chain lengths
+  kDftBlue,  // block FFT of the others (Bluestein)
   kHeigh,
   kStages
 };
@@ -135,14 +136,21 @@ __global__ __launch_bounds__(dev::kFftThreads) void batch_fft_tables_kernel(
   dev::fft_blue_tables_body(J.fft, smem);
 }
 
+// The Stockham and the Bluestein transforms run as two launches: one kernel
+// holding both bodies takes the union of their registers (over 200 VGPRs,
+// one 512-thread workgroup per CU), each alone about 115 (two per CU).
 __global__ __launch_bounds__(dev::kFftThreads) void batch_fft_kernel(
     const BatchDesc* __restrict__ d) {
   extern __shared__ __align__(16) double smem[];
   TL_BATCH_LOCATE(kDft)
-  if (J.fft.blue)  // uniform per workgroup
-    dev::fft_block_body<true>(J.fft, lb, smem);
-  else
-    dev::fft_block_body<false>(J.fft, lb, smem);
+  dev::fft_block_body<false>(J.fft, lb, smem);
+}
+
+__global__ __launch_bounds__(dev::kFftThreads) void batch_fft_blue_kernel(
+    const BatchDesc* __restrict__ d) {
+  extern __shared__ __align__(16) double smem[];
+  TL_BATCH_LOCATE(kDftBlue)
+  dev::fft_block_body<true>(J.fft, lb, smem);
 }
 
 template <int MAXM>
@@ -323,7 +331,8 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
                              : ceil_div(J.asmb.combine_total, 4);
     }
     blocks[kFftTables] = J.fft.blue ? 1 : 0;
-    blocks[kDft] = ceil_div(J.fft.cols, J.fft.W);
+    blocks[kDft] = J.fft.blue ? 0 : ceil_div(J.fft.cols, J.fft.W);
+    blocks[kDftBlue] = J.fft.blue ? ceil_div(J.fft.cols, J.fft.W) : 0;
     blocks[kHeigh] = g.L[0];
     for (int st = 0; st < kStages; ++st) d->prefix[st][i + 1] = d->prefix[st][i] + blocks[st];
     ob += g.basis_elems;
@@ -441,21 +450,36 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
   TL_CHECK_LAUNCH();
   hipLaunchKernelGGL(batch_combine_kernel, dim3(blocks(kCombine)), dim3(256), 0, stream, d);
   TL_CHECK_LAUNCH();
-  size_t fft_lds = 0, tab_lds = 0;
+  size_t fft_lds = 0, blue_lds = 0, tab_lds = 0;
   for (int i = 0; i < hd->count; ++i) {
-    fft_lds = std::max(fft_lds, dev::fft_lds_bytes(hd->job[i].fft));
-    if (hd->job[i].fft.blue) tab_lds = std::max(tab_lds, dev::fft_tables_lds_bytes(hd->job[i].fft));
+    const dev::FftArgs& fa = hd->job[i].fft;
+    if (fa.blue) {
+      blue_lds = std::max(blue_lds, dev::fft_lds_bytes(fa));
+      tab_lds = std::max(tab_lds, dev::fft_tables_lds_bytes(fa));
+    } else {
+      fft_lds = std::max(fft_lds, dev::fft_lds_bytes(fa));
+    }
   }
   if (blocks(kFftTables)) {
     hipLaunchKernelGGL(batch_fft_tables_kernel, dim3(blocks(kFftTables)), dim3(dev::kFftThreads),
                        tab_lds, stream, d);
     TL_CHECK_LAUNCH();
   }
+  // the stage's start event goes with the first of the two transform
+  // launches, its stop event with the last
   hipEvent_t f0, f1;
   stage_events(TL_STAGE_FFT, &f0, &f1);
-  launch_with_events(batch_fft_kernel, dim3(blocks(kDft)), dim3(dev::kFftThreads), fft_lds,
-                     stream, f0, f1, d);
-  TL_CHECK_LAUNCH();
+  const unsigned nstd = blocks(kDft), nblue = blocks(kDftBlue);
+  if (nstd) {
+    launch_with_events(batch_fft_kernel, dim3(nstd), dim3(dev::kFftThreads), fft_lds, stream, f0,
+                       nblue ? nullptr : f1, d);
+    TL_CHECK_LAUNCH();
+  }
+  if (nblue) {
+    launch_with_events(batch_fft_blue_kernel, dim3(nblue), dim3(dev::kFftThreads), blue_lds,
+                       stream, nstd ? nullptr : f0, f1, d);
+    TL_CHECK_LAUNCH();
+  }
   if (plan->max_m0 <= 8)
     hipLaunchKernelGGL(batch_heigh_kernel<8>, dim3(blocks(kHeigh)), dim3(64), 0, stream, d);
   else if (plan->max_m0 <= 16)
