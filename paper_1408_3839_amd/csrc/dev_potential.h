@@ -42,6 +42,48 @@ __device__ __forceinline__ double cell_int(double t, double x, double h, double 
   return d * (0.886226925452758014 / t);  // sqrt(pi)/2 / t
 }
 
+// Sum of the Gauss-Legendre cell integrals (the t h < 1/2 rule of cell_int)
+// over a run of images whose cells sit at x0 - i D (i = 1 .. n_up) and
+// x0 + i D (i = 1 .. n_dn) besides x0 itself, where x0 is the cell of the run
+// nearest the Gaussian's centre.  At each rule node y the values
+// f_i = exp(-t^2 (y -+ i D)^2) obey f_{i+1} = f_i r_i with
+// r_{i+1} = r_i exp(-2 t^2 D^2) (q below): three exponentials per node
+// instead of one per image.  Outward from x0 every ratio after the first is
+// below one, and the first stays below exp(t^2 h D), so nothing overflows.
+__device__ __forceinline__ double gl_run(double t2, double h, double D, double q, double x0,
+                                         int n_up, int n_dn) {
+  double acc = 0.0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const double o = 0.5 * h * kGLx[g];
+    double sum = 0.0;
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg) {
+      const double y0 = sg ? x0 - o : x0 + o;
+      const double f0 = exp(-t2 * y0 * y0);
+      sum += f0;
+      if (n_up > 0) {  // y -> y - D
+        double f = f0, r = exp(-t2 * D * (D - 2.0 * y0));
+        for (int i = 0; i < n_up; ++i) {
+          f *= r;
+          r *= q;
+          sum += f;
+        }
+      }
+      if (n_dn > 0) {  // y -> y + D
+        double f = f0, r = exp(-t2 * D * (D + 2.0 * y0));
+        for (int i = 0; i < n_dn; ++i) {
+          f *= r;
+          r *= q;
+          sum += f;
+        }
+      }
+    }
+    acc += kGLw[g] * sum;
+  }
+  return 0.5 * h * acc;
+}
+
 struct QuadArgs {  // the exponential-sum table, passed by value
   double t[TL_MAX_R];
   double w[TL_MAX_R];
@@ -114,15 +156,49 @@ __device__ inline void fold_body(const FoldArgs& p, const QuadArgs& quad, double
   const int q = t - g * p.R;
   const double tq = quad.t[q], h = p.h;
   const int rr = r - c / 2;  // offset of the node from the cell centre
+  // A cell whose nearest point lies at t |y| > sqrt(750) from the Gaussian's
+  // centre has an integral below 1e-326, zero in FP64: such images are
+  // skipped, and a round of 64 images that holds only such cells costs the
+  // wave no arithmetic (narrow Gaussians reach a few images only).
+  const double tq2 = tq * tq;
   double acc = 0.0;
+  const int m = (2 * K + 64) / 64;  // images per lane when each lane takes a run
+  const double D = (double)c * h;
+  // uniform per wave: Gaussians wide enough to reach every image of a window
+  // of at least 193 images take lane runs of m consecutive images summed by
+  // the recurrence of gl_run; narrower ones reach a few rounds of images,
+  // which the per-image test below keeps cheaper
+  if (tq * h < 0.5 && m >= 4 && tq2 * ((K + 1) * D) * ((K + 1) * D) <= 750.0) {
+    const double qd = exp(-2.0 * tq2 * D * D);
+    const int k_lo = -K + lane * m, k_hi = min(K, k_lo + m - 1);
+    if (k_lo <= K) {
+      for (int s = 0; s < (dim == 0 ? p.n_sites : 1); ++s) {
+        if (dim == 0 && p.site_group[s] != g) continue;
+        const int base = rr - (dim == 0 ? p.site_off[0][s] : p.group_off[dim][g]);
+        // image nearest the centre within the run: x_k = (base - k c) h
+        const int ks = min(k_hi, max(k_lo, (int)rint((double)base / (double)c)));
+        const double x0 = (double)(base - ks * c) * h;
+        const double e = fmax(fabs(x0) - 0.5 * h, 0.0);
+        if (tq2 * e * e > 750.0) continue;  // the whole run is zero
+        const double v = gl_run(tq2, h, D, qd, x0, k_hi - ks, ks - k_lo);
+        acc += dim == 0 ? p.site_Z[s] * v : v;
+      }
+    }
+  } else {
   for (int k = -K + lane; k <= K; k += 64) {
     if (dim == 0) {
       for (int s = 0; s < p.n_sites; ++s)
-        if (p.site_group[s] == g)
-          acc += p.site_Z[s] * cell_int(tq, (double)(rr - p.site_off[0][s] - k * c) * h, h, 0.0);
+        if (p.site_group[s] == g) {
+          const double x = (double)(rr - p.site_off[0][s] - k * c) * h;
+          const double e = fmax(fabs(x) - 0.5 * h, 0.0);
+          if (tq2 * e * e <= 750.0) acc += p.site_Z[s] * cell_int(tq, x, h, 0.0);
+        }
     } else {
-      acc += cell_int(tq, (double)(rr - p.group_off[dim][g] - k * c) * h, h, 0.0);
+      const double x = (double)(rr - p.group_off[dim][g] - k * c) * h;
+      const double e = fmax(fabs(x) - 0.5 * h, 0.0);
+      if (tq2 * e * e <= 750.0) acc += cell_int(tq, x, h, 0.0);
     }
+  }
   }
   const double v = wave_sum_dpp(acc) * (dim == 0 ? quad.w[q] : 1.0);
   // node r of the window lands on every i = rr (mod c) of the torus

@@ -101,6 +101,35 @@ def test_potential_parity(name):
         assert np.all(err <= 1e-13 * scale), (name, d, float((err / scale).max()))
 
 
+LONG_WINDOWS = {
+    # windows of 201 and 601 images: the wide Gaussians (t (K+1) c h <= sqrt(750))
+    # take the lane-run recurrence, the narrower ones the per-image path
+    "L200_c4": lambda: wl.tiny_periodic(L=(200, 1, 1), m0=2, c=4, h=0.5, R=12),
+    "L600_c3_2site": lambda: wl.tiny_periodic(L=(600, 1, 1), m0=2, c=3, h=0.5, R=12,
+                                              sites=((0, 0, 0), (0.5, 0, 0)), Z=(1.0, 2.0)),
+}
+
+
+@pytest.mark.parametrize("name", list(LONG_WINDOWS))
+def test_potential_parity_long_window(name):
+    """Lattice sums over long image windows (the image-run recurrence for
+    Gaussians that reach every image) against the oracle's direct sums."""
+    sys = LONG_WINDOWS[name]()
+    K, D = int(sys.K[0]), int(sys.cell_nodes[0]) * sys.h
+    assert (2 * K + 64) // 64 >= 4
+    assert any(t * sys.h < 0.5 and (t * (K + 1) * D) ** 2 <= 750.0 for t in sys.t_q)
+    pl = _pipeline(sys)
+    pl.lattice_sum_potential()
+    torch.cuda.synchronize()
+    T = pl.sizes["pot_terms"]
+    P = _split_dims(pl.P.cpu().numpy(), [T, T, T], sys.n)
+    ref = oracle.potential_vectors(sys)
+    for d in range(3):
+        scale = np.abs(ref[d]).max(axis=1, keepdims=True)
+        err = np.abs(P[d] - ref[d])
+        assert np.all(err <= 1e-13 * scale), (name, d, float((err / scale).max()))
+
+
 @pytest.mark.parametrize("name", NAMES + ["box12"])
 def test_basis_and_potential_one_call(name):
     """The combined call (one launch for periodic m0 <= 8, two otherwise)
