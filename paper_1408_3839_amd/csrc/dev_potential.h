@@ -245,9 +245,14 @@ __device__ inline void box_potential_body(const BoxArgs& p, const QuadArgs& quad
   int q = t - g * p.R;
   double x = p.x0 + p.h * (double)idx;
   double tt = quad.t[q];
+  const double tt2 = tt * tt;
   double acc = 0.0;
   for (int s = 0; s < p.count; ++s) {
     if (p.group[s] != g) continue;
+    // nuclei whose cell integral lies below FP64's underflow (as in
+    // fold_body) are skipped; neighbouring nodes skip the same nuclei
+    const double e = fmax(fabs(x - p.pos[s]) - 0.5 * p.h, 0.0);
+    if (tt2 * e * e > 750.0) continue;
     acc += p.Z[s] * cell_int(tt, x, p.h, p.pos[s]);
   }
   acc *= quad.w[q];
