@@ -48,6 +48,46 @@ def test_batch_equals_single(precision, slices):
         assert torch.equal(v["info"], sp.info), s.name
 
 
+@pytest.mark.parametrize("lengths", [(11, 13), (8, 9)], ids=["bluestein_only", "smooth_only"])
+def test_batch_single_kind_fft(lengths):
+    """Batches whose chain lengths all take one of the two transform kernels
+    (Bluestein, or Stockham for 7-smooth lengths): the other launch is
+    skipped and the stage events go with the one that runs."""
+    from paper_1408_3839_amd import tl
+    from paper_1408_3839_amd.pipeline import BatchPipeline, PeriodicPipeline
+    systems = [wl.tiny_periodic(L=(L, 1, 1), m0=m0, c=6, h=0.25, R=8, seed=70 + i,
+                                alpha_range=(0.3, 5.0))
+               for i, (L, m0) in enumerate(zip(lengths, (3, 5)))]
+    bp = BatchPipeline(systems)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    e1.record(stream)
+    tl.tl_set_stage_events(tl.TL_STAGE_FFT, e0.cuda_event, e1.cuda_event)
+    try:
+        bp.run()
+    finally:
+        tl.tl_set_stage_events(tl.TL_STAGE_FFT, None, None)
+    torch.cuda.synchronize()
+    assert e0.elapsed_time(e1) > 0.0
+    for s, v in zip(systems, bp.views):
+        sp = PeriodicPipeline(s)
+        sp.run()
+        torch.cuda.synchronize()
+        assert torch.equal(v["H"], sp.H), s.name
+        assert _same_evals(v["evals"], sp.evals), s.name
+        Hr, Sr, _ = oracle.core_hamiltonian_blocks(s)
+        Hb = oracle.block_dft(Hr).reshape(-1, s.m0, s.m0)
+        Sb = oracle.block_dft(Sr).reshape(-1, s.m0, s.m0)
+        ev = v["evals"].cpu().numpy()
+        for j in range(Hb.shape[0]):
+            lam, U = sla.eigh(Hb[j], Sb[j])
+            un = np.sum(np.abs(U) ** 2, axis=0)
+            tol = 1e-10 * np.maximum(1, np.abs(lam)) + 256 * 2.0 ** -52 * (
+                np.linalg.norm(Hb[j], 2) + np.abs(lam) * np.linalg.norm(Sb[j], 2)) * un
+            assert np.all(np.abs(ev[j] - lam) <= tol), (s.name, j)
+
+
 def test_batch_parity_with_oracle():
     from paper_1408_3839_amd.pipeline import BatchPipeline
     systems = _ragged()
