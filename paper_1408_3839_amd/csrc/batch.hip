@@ -26,7 +26,8 @@ enum Stage {
   kFftTables,
   kDft,      // block FFT of the instances with 7-smooth chain lengths
   kDftBlue,  // block FFT of the others (Bluestein)
-  kHeigh,
+  kHeigh,   // k-block eigenvalues of the instances with m0 > 8
+  kHeigh8,  // those of the instances with m0 <= 8, one wave per k-block
   kStages
 };
 
@@ -160,17 +161,21 @@ __global__ __launch_bounds__(MAXM * MAXM < 64 ? 64 : MAXM * MAXM) void batch_hei
   dev::heigh_body<MAXM>(J.Hb, J.Sb, J.m0, J.evals, nullptr, J.info, lb);
 }
 
-// Eigenvalues of batches with 8 < max m0 <= 16: blocks with m0 <= 8 take the
-// one-wave route (the first wave), larger ones the 256-thread tridiagonal
-// route, as in the single-system launches.
+// Eigenvalues of the instances with m0 <= 8: one one-wave workgroup per
+// k-block that reduces it once and bisects all its eigenvalues (for a batch
+// this beats the single-system launch's wave per eigenvalue, which repeats
+// the reduction m0 times), without the idle waves of a wider workgroup.
+__global__ __launch_bounds__(64) void batch_heigh8_kernel(const BatchDesc* __restrict__ d) {
+  TL_BATCH_LOCATE(kHeigh8)
+  dev::heigh_wave8_body(J.Hb, J.Sb, J.m0, J.evals, nullptr, J.info, lb);
+}
+
+// Eigenvalues of the instances with 8 < m0 <= 16: the 256-thread
+// tridiagonal route of the single-system launches.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 batch_heigh16_kernel(const BatchDesc* __restrict__ d) {
   TL_BATCH_LOCATE(kHeigh)
-  if (J.m0 <= 8) {  // uniform per workgroup
-    if (threadIdx.x < 64) dev::heigh_wave8_body(J.Hb, J.Sb, J.m0, J.evals, nullptr, J.info, lb);
-  } else {
-    dev::heigh_evals16_body(J.Hb, J.Sb, J.m0, J.evals, J.info, lb);
-  }
+  dev::heigh_evals16_body(J.Hb, J.Sb, J.m0, J.evals, J.info, lb);
 }
 
 struct InstanceSizes {
@@ -333,7 +338,8 @@ extern "C" tl_status tl_batch_write_descriptor(const tl_system* systems, int cou
     blocks[kFftTables] = J.fft.blue ? 1 : 0;
     blocks[kDft] = J.fft.blue ? 0 : ceil_div(J.fft.cols, J.fft.W);
     blocks[kDftBlue] = J.fft.blue ? ceil_div(J.fft.cols, J.fft.W) : 0;
-    blocks[kHeigh] = g.L[0];
+    blocks[kHeigh] = g.m0 <= 8 ? 0 : g.L[0];
+    blocks[kHeigh8] = g.m0 <= 8 ? g.L[0] : 0;
     for (int st = 0; st < kStages; ++st) d->prefix[st][i + 1] = d->prefix[st][i] + blocks[st];
     ob += g.basis_elems;
     op += g.pot_elems;
@@ -480,12 +486,16 @@ extern "C" tl_status tl_batch_run(const tl_batch_plan* plan, const void* host_de
                        stream, nstd ? nullptr : f0, f1, d);
     TL_CHECK_LAUNCH();
   }
-  if (plan->max_m0 <= 8)
-    hipLaunchKernelGGL(batch_heigh_kernel<8>, dim3(blocks(kHeigh)), dim3(64), 0, stream, d);
-  else if (plan->max_m0 <= 16)
-    hipLaunchKernelGGL(batch_heigh16_kernel, dim3(blocks(kHeigh)), dim3(256), 0, stream, d);
-  else
-    hipLaunchKernelGGL(batch_heigh_kernel<32>, dim3(blocks(kHeigh)), dim3(1024), 0, stream, d);
-  TL_CHECK_LAUNCH();
+  if (blocks(kHeigh8)) {
+    hipLaunchKernelGGL(batch_heigh8_kernel, dim3(blocks(kHeigh8)), dim3(64), 0, stream, d);
+    TL_CHECK_LAUNCH();
+  }
+  if (blocks(kHeigh)) {  // instances with m0 > 8
+    if (plan->max_m0 <= 16)
+      hipLaunchKernelGGL(batch_heigh16_kernel, dim3(blocks(kHeigh)), dim3(256), 0, stream, d);
+    else
+      hipLaunchKernelGGL(batch_heigh_kernel<32>, dim3(blocks(kHeigh)), dim3(1024), 0, stream, d);
+    TL_CHECK_LAUNCH();
+  }
   return TL_OK;
 }
